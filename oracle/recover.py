@@ -27,7 +27,7 @@ def mean_intensity(disc, u):
 def l2_norm_sq(disc, h, v):
     """sum_e (h_e/2)^2 sum_nd W_nd v[e, nd]^2 for v [E, nn]."""
     h = np.broadcast_to(np.asarray(h, dtype=np.float64), (v.shape[0],))
-    return float(np.sum((0.5 * h) ** 2 * (v * v) @ disc.W))
+    return float(np.sum((0.5 * h) ** 2 * ((v * v) @ disc.W)))
 
 
 def rel_l2(disc, h, v, ref):

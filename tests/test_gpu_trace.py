@@ -1,0 +1,167 @@
+"""GPU parity of the skeleton pieces and the whole plain path against the oracle.
+
+* element DOF maps and the boundary right-hand side: bit-exact (integers /
+  copies of the boundary data);
+* (I - P) x with FP64 operators: <= 1e-13 relative; with bfloat16 operators
+  against the oracle product with the same bfloat16-rounded operator: <= 1e-13;
+* trace solution (GMRES at 1e-12 vs the oracle's sparse direct solve) and the
+  recovered intensity / mean intensity: <= 1e-10 relative;
+* at 32 x 32 (p = 6, N_a = 16) where the oracle cannot run whole: sampled
+  element operators against the oracle one by one, GMRES residual, and the
+  global energy balance (incoming = outgoing + absorbed), a property that
+  holds at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.local import LocalDisc, local_solve_batch
+from oracle.mesh import Mesh
+from oracle import trace as otrace, recover as orecover
+from paper_2308_02467_amd import inputs
+
+from _util import mesh_problem, oracle_pipeline, per_element_rel, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def T(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2308_02467_amd import el
+    c = el.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("p,n_a,nx,ny", [(3, 8, 4, 4), (6, 16, 5, 3), (2, 4, 1, 1)])
+def test_element_dofs_bit_exact(ctx, p, n_a, nx, ny):
+    from paper_2308_02467_amd import el
+    d, ms = el.disc(p, n_a), el.mesh(nx, ny, 1.0 / max(nx, ny))
+    _, _, m = el.disc_sizes(d)
+    ind = torch.empty((nx * ny, m), dtype=torch.int32, device=DEV)
+    outd = torch.empty_like(ind)
+    print(f"[el_element_dofs] p={p} n_a={n_a} {nx}x{ny}", flush=True)
+    ctx.el_element_dofs(d, ms, ind, outd)
+    oi, oo = Mesh(nx, ny, 1.0 / max(nx, ny)).element_dofs(LocalDisc(p, n_a))
+    assert np.array_equal(ind.cpu().numpy(), oi)
+    assert np.array_equal(outd.cpu().numpy(), oo)
+
+
+def test_trace_rhs_bit_exact(ctx):
+    from paper_2308_02467_amd import el
+    p, n_a, nx, ny = 4, 8, 3, 5
+    d, ms = el.disc(p, n_a), el.mesh(nx, ny, 0.2)
+    g = np.random.default_rng(0).uniform(0, 2, (4, n_a))
+    b = torch.full((el.trace_size(d, ms),), float("nan"), dtype=torch.float64, device=DEV)
+    print("[el_trace_rhs]", flush=True)
+    ctx.el_trace_rhs(d, ms, g, b)
+    ref = Mesh(nx, ny, 0.2).boundary_vector_sides(LocalDisc(p, n_a), g)
+    assert np.array_equal(b.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("p,n_a,nx,ny", [(3, 8, 4, 4), (6, 16, 3, 2)])
+def test_matvec_f64_and_bf16(ctx, p, n_a, nx, ny):
+    from paper_2308_02467_amd import el
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, ny)
+    i2o, _, _ = local_solve_batch(od, hh, kap, sig)
+    ind, outd = oms.element_dofs(od)
+    d, ms = el.disc(p, n_a), el.mesh(nx, ny, oms.h)
+    nt = el.trace_size(d, ms)
+    x = np.random.default_rng(1).standard_normal(nt)
+    y = torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV)
+    print(f"[el_trace_matvec] p={p} n_a={n_a} {nx}x{ny} f64", flush=True)
+    ctx.el_trace_matvec(d, ms, T(i2o), T(x), y)
+    ref = otrace.matvec(i2o, ind, outd, x)
+    assert rel_err(y.cpu().numpy(), ref) <= 1e-13
+    # bfloat16 operator (round to nearest even), FP64 accumulation
+    op16 = T(i2o).to(torch.bfloat16)
+    print(f"[el_trace_matvec] p={p} n_a={n_a} {nx}x{ny} bf16", flush=True)
+    ctx.el_trace_matvec(d, ms, op16, T(x), y)
+    ref16 = otrace.matvec(op16.to(torch.float64).cpu().numpy(), ind, outd, x)
+    assert rel_err(y.cpu().numpy(), ref16) <= 1e-13
+
+
+def _gpu_pipeline(ctx, p, n_a, g, nx, ny, hh, kap, sig, g_side, tol=1e-12, outputs=True):
+    from paper_2308_02467_amd import el
+    d, ms = el.disc(p, n_a, g), el.mesh(nx, ny, 1.0 / max(nx, ny))
+    nn, n, m = el.disc_sizes(d)
+    E = nx * ny
+    i2o = torch.empty((E, m, m), dtype=torch.float64, device=DEV)
+    i2s = torch.empty((E, n, m), dtype=torch.float64, device=DEV)
+    i2m = torch.empty((E, nn, m), dtype=torch.float64, device=DEV)
+    print(f"[pipeline] p={p} n_a={n_a} {nx}x{ny} local", flush=True)
+    ctx.el_local_solve(d, T(hh), T(kap), T(sig), in2out=i2o, in2sol=i2s, in2mean=i2m)
+    nt = el.trace_size(d, ms)
+    b = torch.empty(nt, dtype=torch.float64, device=DEV)
+    ctx.el_trace_rhs(d, ms, g_side, b)
+    t = torch.empty(nt, dtype=torch.float64, device=DEV)
+    print(f"[pipeline] p={p} n_a={n_a} {nx}x{ny} gmres", flush=True)
+    st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=tol, restart=50, max_iter=3000)
+    u = torch.empty((E, n), dtype=torch.float64, device=DEV)
+    mean = torch.empty((E, nn), dtype=torch.float64, device=DEV)
+    print(f"[pipeline] p={p} n_a={n_a} {nx}x{ny} recover", flush=True)
+    ctx.el_recover(d, ms, i2s, t, u, mean)
+    mean2 = torch.empty_like(mean)
+    ctx.el_recover_mean(d, ms, i2m, t, mean2)
+    torch.cuda.synchronize()
+    res = dict(in2out=i2o, in2sol=i2s, in2mean=i2m, b=b, t=t, u=u, mean=mean, mean2=mean2)
+    return {k: v.cpu().numpy() for k, v in res.items()}, rep[0], st
+
+
+@pytest.mark.parametrize("p,n_a,nx,field", [(3, 8, 4, "const"), (6, 16, 6, "gauss"), (4, 8, 5, "sharp")])
+def test_plain_pipeline_parity(ctx, p, n_a, nx, field):
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, field=field)
+    gs = inputs.left_inflow(n_a)
+    ref = oracle_pipeline(od, oms, hh, kap, sig, gs)
+    gpu, rep, st = _gpu_pipeline(ctx, p, n_a, 0.0, nx, nx, hh, kap, sig, gs)
+    assert rep["converged"] and rep["relres"] <= 1e-12, rep
+    for k in ("in2out", "in2sol", "in2mean"):
+        assert per_element_rel(gpu[k], ref[k]) <= 1e-10, k
+    assert np.array_equal(gpu["b"], ref["b"])
+    for k in ("t", "u", "mean"):
+        assert rel_err(gpu[k], ref[k]) <= 1e-10, (k, rel_err(gpu[k], ref[k]))
+    assert rel_err(gpu["mean2"], ref["mean"]) <= 1e-10
+    from paper_2308_02467_amd import el
+    a = gpu["mean"] + 1e-3
+    d2, r2 = ctx.el_mean_l2(el.disc(p, n_a), T(hh), T(a), T(ref["mean"]))
+    exp_d2 = orecover.l2_norm_sq(od, hh, a - ref["mean"])
+    assert abs(d2 - exp_d2) <= 1e-12 * exp_d2 + 1e-300
+    assert abs(r2 - orecover.l2_norm_sq(od, hh, ref["mean"])) <= 1e-12 * r2
+
+
+def test_hg_pipeline_parity(ctx):
+    p, n_a, g, nx = 3, 12, 0.85, 4
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, g=g)
+    gs = inputs.left_inflow(n_a)
+    gs[3, :] = 0.3
+    ref = oracle_pipeline(od, oms, hh, kap, sig, gs)
+    gpu, rep, st = _gpu_pipeline(ctx, p, n_a, g, nx, nx, hh, kap, sig, gs)
+    for k in ("t", "u", "mean"):
+        assert rel_err(gpu[k], ref[k]) <= 1e-10, k
+
+
+def test_full_size_32x32_sampled_and_energy(ctx):
+    """The 32x32, p=6, N_a=16 Gaussian-cloud workload: sampled element
+    operators vs the oracle, GMRES residual, global energy balance."""
+    p, n_a, nx = 6, 16, 32
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, nx)
+    gs = inputs.left_inflow(n_a)
+    gpu, rep, st = _gpu_pipeline(ctx, p, n_a, 0.0, nx, nx, hh, kap, sig, gs)
+    assert rep["converged"] and rep["relres"] <= 1e-12, rep
+    sel = np.array([0, 17, 31, 32, 500, 527, 777, 1023])
+    i2o, i2s, i2m = local_solve_batch(od, hh[sel], kap[sel], sig[sel])
+    assert per_element_rel(gpu["in2out"][sel], i2o) <= 1e-10
+    assert per_element_rel(gpu["in2sol"][sel], i2s) <= 1e-10
+    assert per_element_rel(gpu["in2mean"][sel], i2m) <= 1e-10
+    inc, outg = orecover.boundary_fluxes(od, oms, gpu["t"], oms.inflow_mask(od))
+    ab = orecover.absorption(od, hh, kap, gpu["u"])
+    assert abs(inc - outg - ab) <= 1e-10 * inc, (inc, outg, ab)
+    # the recovered outflow equals the trace on every outflow DOF (R^o u = t)
+    ind, outd = oms.element_dofs(od)
+    u = gpu["u"]
+    assert rel_err(u[:, od.out_rows].reshape(-1), gpu["t"][outd].reshape(-1)) <= 1e-10

@@ -350,3 +350,19 @@ def test_p_convergence_manufactured():
     errs = [_manufactured(p) for p in (2, 4, 6, 8)]
     assert all(errs[i + 1] < 0.05 * errs[i] for i in range(3)), errs
     assert errs[-1] < 1e-8, errs
+
+
+# ---- element L2 norm of the mean intensity (relative L2 error of Sec. 3.2.1) ----
+@pytest.mark.parametrize("p,nx,ny", [(3, 4, 4), (6, 6, 3), (2, 5, 7)])
+def test_l2_norm_closed_forms(p, nx, ny):
+    """||1||^2 = area, ||x||^2 = int x^2 (exact with LGL for p >= 2), on
+    meshes with E != nn so that a mis-broadcast of h fails."""
+    d = LocalDisc(p, 4)
+    h = 1.0 / max(nx, ny)
+    X, Y = inputs.element_node_coords(nx, ny, h, d.xi)
+    hh = np.full(nx * ny, h)
+    area = nx * ny * h * h
+    assert abs(recover.l2_norm_sq(d, hh, np.ones_like(X)) - area) < 1e-13
+    Lx, Ly = nx * h, ny * h
+    assert abs(recover.l2_norm_sq(d, hh, X) - Lx ** 3 / 3 * Ly) < 1e-13
+    assert abs(recover.rel_l2(d, hh, 2 * X, X) - 1.0) < 1e-13
