@@ -1,0 +1,167 @@
+"""Benchmark of the element-learning hot path on one MI355X.
+
+Workload (named in the output's config): 128 x 128 square elements on the
+unit square, Q6 LGL (p = 6) x 16 discrete ordinates (n = 784 volume and
+m = 224 inflow DOFs per element), isotropic scattering, the smooth Gaussian
+cloud kappa = 0.01 + 0.5 G, sigma = 0.1 + 30 G (G a Gaussian bump of width
+0.2 at the centre), radiance 1 entering through the left side.
+
+One step = the whole plain FP64 path: element local solves (assembly + LU +
+solves, writing in2out, in2sol and in2mean), the skeleton right-hand side,
+GMRES on the skeleton system, and recovery of u and the mean intensity.
+Inputs are resident in HBM before the timed region.  value = elements per
+second of the whole step.
+
+Also reported: the local-solve kernel time (roofline of the dominant kernel,
+FP64 matrix cores) and the CPU oracle timed on a bounded sample of the same
+workload (cpu_baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128, help="elements per side")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="elements in the oracle sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2308_02467_amd import el, inputs
+
+    dev = torch.device("cuda:0")
+    p, n_a, nx = 6, 16, args.n
+    h = 1.0 / nx
+    d = el.disc(p, n_a)
+    ms = el.mesh(nx, nx, h)
+    nn, n, m = el.disc_sizes(d)
+    E = nx * nx
+    xi, _ = el.lgl(p)
+    X, Y = inputs.element_node_coords(nx, nx, h, xi)
+    kap_np, sig_np = inputs.gaussian_cloud(X, Y)
+    g_side = inputs.left_inflow(n_a)
+
+    ctx = el.Context(0)
+    stream = torch.cuda.current_stream()
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    hh, kap, sig = T(np.full(E, h)), T(kap_np), T(sig_np)
+    i2o = torch.empty((E, m, m), dtype=torch.float64, device=dev)
+    i2s = torch.empty((E, n, m), dtype=torch.float64, device=dev)
+    i2m = torch.empty((E, nn, m), dtype=torch.float64, device=dev)
+    nt = el.trace_size(d, ms)
+    b = torch.empty(nt, dtype=torch.float64, device=dev)
+    t = torch.empty(nt, dtype=torch.float64, device=dev)
+    u = torch.empty((E, n), dtype=torch.float64, device=dev)
+    mean = torch.empty((E, nn), dtype=torch.float64, device=dev)
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    reports = []
+
+    def step(record):
+        e0, e1, e2, e3, e4 = ev(), ev(), ev(), ev(), ev()
+        e0.record(stream)
+        ctx.el_local_solve(d, hh, kap, sig, in2out=i2o, in2sol=i2s, in2mean=i2m)
+        e1.record(stream)
+        ctx.el_trace_rhs(d, ms, g_side, b)
+        e2.record(stream)
+        st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=args.tol, restart=50, max_iter=5000)
+        e3.record(stream)
+        ctx.el_recover(d, ms, i2s, t, u, mean)
+        e4.record(stream)
+        if record:
+            reports.append((e0, e1, e2, e3, e4, rep[0]))
+
+    print(f"[bench] warmup {args.warmup} step(s), E={E}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[2]), r[2].elapsed_time(r[3]),
+                        r[3].elapsed_time(r[4])] for r in reports])           # ms
+    ms_step = wall * 1e3 / args.steps
+    local_ms = float(np.median(phases[:, 0]))
+    gm = reports[-1][5]
+
+    # roofline of the dominant kernel: FP64 LU + solves on the matrix cores
+    flop_el = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * m
+    achieved = flop_el * E / (local_ms * 1e-3) / 1e12
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu oracle sample of {args.cpu_sample} elements", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p, n_a, h, kap_np, sig_np, args.cpu_sample)
+
+    out = {
+        "metric": "element solves/s + full solve time at 1e-3 rel L2, learned vs plain (p=6)",
+        "value": E / (ms_step * 1e-3),
+        "unit": "element solves/s (whole plain step)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"plain FP64 HDG, {nx}x{nx} elements, p=6, N_a=16, Gaussian cloud, left inflow",
+                   "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol, "gmres_restart": 50},
+        "phases_ms": {"local_solve": local_ms, "trace_rhs": float(np.median(phases[:, 1])),
+                      "gmres": float(np.median(phases[:, 2])), "recover": float(np.median(phases[:, 3]))},
+        "local_solve_el_per_s": E / (local_ms * 1e-3),
+        "gmres": gm,
+        "roofline": {"bound": "mfma", "kernel": "k_local_lu<double>", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def cpu_baseline(p, n_a, h, kap, sig, count):
+    """The CPU oracle (NumPy / LAPACK, FP64) on a bounded sample of the same
+    workload: local solves of `count` elements spread over the mesh."""
+    from oracle.local import LocalDisc
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    d = LocalDisc(p, n_a)
+    E = kap.shape[0]
+    sel = np.linspace(0, E - 1, count).astype(np.int64)
+    t0 = time.perf_counter()
+    for e in sel:
+        d.local_solve(h, kap[e], sig[e])
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "element local solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 local solves (assembly + LAPACK LU solve for all 224 inflow columns) of {count} "
+                      f"of the {E} elements; {dt:.1f} s; the oracle's skeleton solve is not in the sample"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * el.h -- C ABI of the element-learning hot path for the 2D steady radiative
+ * transfer equation on one MI355X (gfx950).
+ *
+ * Method: upwind HDG with Q_p tensor LGL collocation in space and N_a discrete
+ * ordinates in angle (paper: "Element learning ...", arXiv 2308.02467,
+ * Sec. 2.2).  Per element the local problem (eq. hdg_local_mat) gives
+ *     in2sol  = A_i2u = -(B - C + M - S)^{-1} B_hat      (eq. hdg_local_i2u)
+ *     in2out  = A_i2o = R^o A_i2u                        (eq. hdg_local_i2o)
+ *     in2mean = A_i2m = R_u2m A_i2u                      (Sec. 2.4, eq. ang_ave)
+ * and the skeleton system (eq. hdg_global_mat) couples elements through in2out.
+ * Algorithm 1 (HDG implementation): local solve -> assemble -> global solve
+ * -> recover.  The learned form (Sec. 2.4, eq. param2sol) replaces the local
+ * solve by a fully connected network.
+ *
+ * Conventions (all arrays row-major, all sizes in elements):
+ *   q = p+1, nn = q*q, n = nn*N_a (volume DOFs), m = 2*q*N_a (inflow DOFs
+ *   per element, equal to outflow DOFs per element).
+ *   Node nd = b*q + a for the node (x_a, x_b); volume DOF v = k*nn + nd.
+ *   Ordinate k at angle (k + 1/2) 2 pi / N_a, weight 2 pi / N_a.
+ *   Faces f: 0 W (-1,0), 1 E (+1,0), 2 S (0,-1), 3 N (0,+1); face node j runs
+ *   along increasing x or y.  I_f / O_f: ascending ordinates with s.n_f < 0 / > 0.
+ *   Local inflow index iota = f*(N_a/2)*q + r*q + j (r = rank of k in I_f);
+ *   outflow indices likewise with O_f.
+ *   Mesh: element e = j*n_x + i; vertical face V(i,j) = j*(n_x+1) + i,
+ *   horizontal face H(i,j) = (n_x+1)*n_y + j*n_x + i; trace DOF
+ *   (F*N_a + k)*q + jn.
+ *   Coefficients: kappa = absorption, sigma = scattering, both at the element
+ *   LGL nodes; extinction = kappa + sigma (Sec. 2.1).  The square element of
+ *   side h is the reference square with coefficients h*(kappa+sigma)/2 and
+ *   h*sigma/2 (Sec. 2.4.1).
+ *
+ * Pointers are DEVICE pointers unless marked "host".  The caller allocates
+ * and owns every input and output; the library owns only its workspace (kept
+ * in the context, grown on demand) and network state.  No call keeps a
+ * caller pointer after it returns.  Every call is ordered on the context's
+ * stream; calls that report on the host (status flags, GMRES reports)
+ * synchronize that stream before returning.
+ *
+ * Errors: EL_OK = 0; negative values are errors (outputs undefined);
+ * EL_WARN_NOT_CONVERGED = +1 means outputs are valid to the reported
+ * residual.  el_last_error() returns text naming the failing element or mesh.
+ */
+#ifndef EL_H
+#define EL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int el_status;
+#define EL_OK 0
+#define EL_WARN_NOT_CONVERGED 1
+#define EL_ERR_ARG (-1)
+#define EL_ERR_HIP (-2)
+#define EL_ERR_SINGULAR (-3)
+#define EL_ERR_NONFINITE (-4)
+#define EL_ERR_NOMEM (-5)
+#define EL_ERR_STATE (-6)
+
+#define EL_SCATTER_ISO 0
+#define EL_SCATTER_HG 1
+
+/* local-solve precision forms */
+#define EL_FP64 0     /* FP64 LU with partial pivoting */
+#define EL_FP32_IR 1  /* FP32 LU, FP64 residual, iterative refinement */
+
+/* operator storage types for the trace sweep and recovery */
+#define EL_F64 0
+#define EL_BF16 1
+
+typedef struct el_ctx el_ctx;
+
+/* Discretization: Q_p in space, n_a ordinates (n_a % 4 == 0, 1 <= p <= 12),
+ * scattering kind and Henyey-Greenstein asymmetry g_hg in [0, 1) (Sec. 2.1;
+ * exponent 3/2, normalized so that sum_k' w_k' P[k][k'] = 1). */
+typedef struct {
+  int p;
+  int n_a;
+  int scatter;
+  double g_hg;
+} el_disc;
+
+/* Uniform mesh of n_x * n_y squares of side h, lower-left corner (x0, y0). */
+typedef struct {
+  int n_x, n_y;
+  double x0, y0, h;
+} el_mesh;
+
+typedef struct {
+  double tol;     /* relative residual ||b - (I-P)x|| / ||b|| */
+  int restart;    /* Krylov dimension per cycle, 1..128 */
+  int max_iter;   /* total Arnoldi steps */
+} el_gmres_opts;
+
+typedef struct {
+  int iters;
+  int restarts;
+  double relres;  /* true relative residual at exit */
+  int converged;
+} el_gmres_report;
+
+/* ---- context -------------------------------------------------------------- */
+/* Create a context on HIP device `device`, ordered on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+el_status el_create(el_ctx** ctx, int device, void* hip_stream);
+el_status el_destroy(el_ctx* ctx);
+el_status el_set_stream(el_ctx* ctx, void* hip_stream);
+/* Text of the last error on this context (never NULL). */
+const char* el_last_error(const el_ctx* ctx);
+/* Bytes of device workspace currently held by the context. */
+el_status el_workspace_bytes(const el_ctx* ctx, size_t* bytes);
+
+/* ---- discretization queries (host only, no device work) ------------------ */
+/* nn, n, m of a discretization; EL_ERR_ARG if it is not supported. */
+el_status el_disc_sizes(el_disc d, int64_t* nn, int64_t* n, int64_t* m);
+/* LGL nodes and weights on [-1, 1] (Sec. 2.4.1, eq. sigma_se), host [p+1]. */
+el_status el_lgl(int p, double* xi_host, double* w_host);
+/* Volume row of each local inflow / outflow index (host int32 [m] each):
+ * the bit-exact indexing contract above. */
+el_status el_index_tables(el_disc d, int32_t* in_rows_host, int32_t* out_rows_host);
+/* Number of trace DOFs of a mesh. */
+el_status el_trace_size(el_disc d, el_mesh mesh, int64_t* n_trace);
+/* Global trace DOF of every local inflow / outflow index, device int32 [E][m]. */
+el_status el_element_dofs(el_ctx* ctx, el_disc d, el_mesh mesh, int32_t* in_dofs, int32_t* out_dofs);
+
+/* ---- local solve (Alg. 1 step 1; eq. hdg_local_f2u_i2u, hdg_local_f2o_i2o) --
+ * For E elements with side h[E] and nodal kappa, sigma [E][nn] (>= 0, finite,
+ * h > 0): assemble A = B - C + M - S on the fly, factor it (dense LU with
+ * partial pivoting, FP64 or FP32 + FP64 refinement), solve for the m inflow
+ * columns of -B_hat and write any of
+ *   in2out [E][m][m], in2sol [E][n][m], in2mean [E][nn][m]   (NULL = skip),
+ * and for EL_FP32_IR the final relative residual per element rel_resid [E]
+ * (max over columns of ||R||_inf / ||B_hat col||_inf; NULL = skip).
+ * Errors: EL_ERR_ARG (bad sizes / disc), EL_ERR_NONFINITE (non-finite or
+ * negative coefficient; element named), EL_ERR_SINGULAR (zero pivot; element
+ * named).  Synchronizes the stream to read the status flags. */
+el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E,
+                         const double* h, const double* kappa, const double* sigma,
+                         double* in2out, double* in2sol, double* in2mean,
+                         double* rel_resid);
+
+/* ---- skeleton system (eq. hdg_global_mat) --------------------------------- */
+/* Right-hand side b [n_trace]: per-side boundary radiance g_side (host
+ * [4][n_a], sides W, E, S, N, constant along a side) on domain-inflow DOFs
+ * (nodal interpolation = the L2 projection P_M g with collocated LGL,
+ * Sec. 2.2.2), 0 elsewhere. */
+el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_side_host, double* b);
+
+/* y = (I - P) x on one mesh: (P x)[out dofs of e] = in2out_e x[in dofs of e],
+ * P = 0 on domain-inflow rows.  in2out is [E][m][m] FP64 (op_dtype EL_F64)
+ * or bfloat16 bit patterns (EL_BF16); accumulation is FP64. */
+el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out,
+                          int op_dtype, const double* x, double* y);
+
+/* Solve (I - P) t = b for n_mesh independent meshes with restarted GMRES
+ * (Sec. 2.3): x0 = 0, classical Gram-Schmidt applied twice, Givens
+ * rotations, FP64 vectors and reductions.  Stops a mesh when its true
+ * relative residual <= opts->tol.  in2out, b, trace: host arrays of n_mesh
+ * device pointers.  rep: host [n_mesh].  Returns EL_WARN_NOT_CONVERGED if
+ * any mesh did not reach tol within max_iter. */
+el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* meshes_host,
+                         const void* const* in2out, int op_dtype,
+                         const double* const* b, double* const* trace,
+                         const el_gmres_opts* opts_host, el_gmres_report* rep_host);
+
+/* ---- recovery (Alg. 1 step 4, eq. hdg_local_mat_sol, eq. ang_ave) ----------
+ * u [E][n] = in2sol_e t[in dofs of e] (NULL = skip) and the mean intensity
+ * mean [E][nn] = (1/N_a) sum_k u (NULL = skip).  in2sol is [E][n][m] FP64 or
+ * bfloat16 bits (op_dtype). */
+el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
+                     const double* trace, double* u, double* mean);
+/* Mean intensity directly from in2mean [E][nn][m] (FP64 or bfloat16 bits). */
+el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean,
+                          int op_dtype, const double* trace, double* mean);
+
+/* Squared element L2 norms of mean-intensity fields [E][nn] (relative error
+ * measure of Sec. 3.2.1): out_host[0] = sum_e (h_e/2)^2 sum W (a - ref)^2,
+ * out_host[1] = sum_e (h_e/2)^2 sum W ref^2.  Synchronizes. */
+el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h,
+                     const double* a, const double* ref, double* out_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EL_H */

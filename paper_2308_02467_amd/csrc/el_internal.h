@@ -1,0 +1,113 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/el.h"
+
+namespace el {
+
+constexpr int kMaxQ = 13;      // p <= 12
+constexpr int kMaxNa = 64;
+
+// Host-side discretization data (built once per (p, n_a, scatter, g)).
+struct DiscHost {
+  int p = 0, q = 0, n_a = 0, nn = 0, n = 0, m = 0;
+  int scatter = 0;
+  double g = 0.0;
+  std::vector<double> xi, omega;      // [q]
+  std::vector<double> D;              // [q][q], D[i*q+j] = l_j'(x_i)
+  std::vector<double> W;              // [nn]
+  std::vector<double> sx, sy;         // [n_a]
+  std::vector<double> Q;              // [n_a][n_a] = P[k][k'] * w_k'
+  std::vector<double> T;              // [n_a][nn][nn] = B_k - C_k
+  std::vector<int32_t> in_row, out_row;   // [m] volume rows
+  std::vector<double> in_val;             // [m] entry of -B_hat (w_j |s.n_f|)
+  std::vector<int32_t> in_f, in_k, in_j;  // [m]
+  std::vector<int32_t> out_f, out_k, out_j;
+};
+
+// Device view of the same data (pointers into one device allocation).
+struct DiscDev {
+  int p, q, n_a, nn, n, m;
+  const double* W;      // [nn]
+  const double* Q;      // [n_a*n_a]
+  const double* T;      // [n_a*nn*nn]
+  const double* in_val; // [m]
+  const int32_t* in_row;
+  const int32_t* out_row;
+  const int32_t* in_f;
+  const int32_t* in_k;
+  const int32_t* in_j;
+  const int32_t* out_f;
+  const int32_t* out_k;
+  const int32_t* out_j;
+  const double* sx;     // [n_a]
+  const double* sy;
+};
+
+bool build_disc(const el_disc& d, DiscHost& out, std::string& err);
+bool lgl(int p, double* xi, double* w);
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace el
+
+struct el_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  // cached discretizations: key -> (host, device buffer, view)
+  struct DiscEntry {
+    el::DiscHost host;
+    void* dbuf = nullptr;
+    el::DiscDev view{};
+  };
+  std::map<std::string, std::unique_ptr<DiscEntry>> discs;
+  el::Workspace ws_local;    // LU factors
+  el::Workspace ws_gmres;    // Krylov basis and scratch
+  el::Workspace ws_small;    // flags, reductions
+  int num_cus = 256;
+};
+
+namespace el {
+el_status set_error(el_ctx* ctx, el_status code, const std::string& msg);
+el_status hip_check(el_ctx* ctx, hipError_t e, const char* what);
+el_status get_disc(el_ctx* ctx, const el_disc& d, el_ctx::DiscEntry** out);
+el_status ensure_ws(el_ctx* ctx, Workspace& ws, size_t bytes);
+
+// launchers implemented in the .hip files
+el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,
+                             const double* h, const double* kappa, const double* sigma,
+                             double* in2out, double* in2sol, double* in2mean, double* rel_resid);
+el_status launch_trace_rhs(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
+                           const double* g_side_host, double* b);
+el_status launch_trace_matvec(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
+                              const void* in2out, int op_dtype, const double* x, double* y);
+el_status launch_element_dofs(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
+                              int32_t* in_dofs, int32_t* out_dofs);
+el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const el_mesh* meshes,
+                          const void* const* in2out, int op_dtype, const double* const* b,
+                          double* const* trace, const el_gmres_opts& opts, el_gmres_report* rep);
+el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
+                         const void* in2sol, int op_dtype, const double* trace,
+                         double* u, double* mean);
+el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
+                              const void* in2mean, int op_dtype, const double* trace, double* mean);
+el_status launch_mean_l2(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h,
+                         const double* a, const double* ref, double* out_host);
+
+inline int64_t mesh_faces(const el_mesh& m) {
+  return (int64_t)(m.n_x + 1) * m.n_y + (int64_t)m.n_x * (m.n_y + 1);
+}
+
+}  // namespace el

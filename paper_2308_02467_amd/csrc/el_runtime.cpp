@@ -1,0 +1,290 @@
+// Host runtime of the C ABI: context, error text, cached discretization
+// tables on the device, workspace growth, argument checks and dispatch to
+// the kernel launchers.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+
+#include "el_internal.h"
+
+namespace el {
+
+el_status set_error(el_ctx* ctx, el_status code, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return code;
+}
+
+el_status hip_check(el_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return EL_OK;
+  std::ostringstream os;
+  os << what << ": " << hipGetErrorString(e);
+  return set_error(ctx, e == hipErrorOutOfMemory ? EL_ERR_NOMEM : EL_ERR_HIP, os.str());
+}
+
+static std::string disc_key(const el_disc& d) {
+  char buf[96];
+  std::snprintf(buf, sizeof buf, "%d/%d/%d/%.17g", d.p, d.n_a, d.scatter,
+                d.scatter == EL_SCATTER_HG ? d.g_hg : 0.0);
+  return buf;
+}
+
+el_status get_disc(el_ctx* ctx, const el_disc& d, el_ctx::DiscEntry** out) {
+  std::string key = disc_key(d);
+  auto it = ctx->discs.find(key);
+  if (it != ctx->discs.end()) { *out = it->second.get(); return EL_OK; }
+  auto de = std::make_unique<el_ctx::DiscEntry>();
+  std::string err;
+  if (!build_disc(d, de->host, err)) return set_error(ctx, EL_ERR_ARG, "el_disc: " + err);
+  const DiscHost& h = de->host;
+  // one device allocation: doubles first, then int32 tables
+  size_t nd = h.W.size() + h.Q.size() + h.T.size() + h.in_val.size() + h.sx.size() + h.sy.size();
+  size_t ni = 8 * (size_t)h.m;
+  size_t bytes = nd * sizeof(double) + ni * sizeof(int32_t);
+  el_status st = hip_check(ctx, hipMalloc(&de->dbuf, bytes), "hipMalloc(disc tables)");
+  if (st) return st;
+  std::vector<char> staging(bytes);
+  double* dp = reinterpret_cast<double*>(staging.data());
+  auto putd = [&](const std::vector<double>& v) { std::memcpy(dp, v.data(), v.size() * sizeof(double)); dp += v.size(); };
+  double* base = reinterpret_cast<double*>(de->dbuf);
+  size_t off = 0;
+  auto devd = [&](size_t count) { const double* r = base + off; off += count; return r; };
+  de->view.W = devd(h.W.size()); putd(h.W);
+  de->view.Q = devd(h.Q.size()); putd(h.Q);
+  de->view.T = devd(h.T.size()); putd(h.T);
+  de->view.in_val = devd(h.in_val.size()); putd(h.in_val);
+  de->view.sx = devd(h.sx.size()); putd(h.sx);
+  de->view.sy = devd(h.sy.size()); putd(h.sy);
+  int32_t* ip = reinterpret_cast<int32_t*>(dp);
+  int32_t* ibase = reinterpret_cast<int32_t*>(base + off);
+  size_t ioff = 0;
+  auto puti = [&](const std::vector<int32_t>& v) {
+    std::memcpy(ip, v.data(), v.size() * sizeof(int32_t)); ip += v.size();
+    const int32_t* r = ibase + ioff; ioff += v.size(); return r;
+  };
+  de->view.in_row = puti(h.in_row);
+  de->view.out_row = puti(h.out_row);
+  de->view.in_f = puti(h.in_f);
+  de->view.in_k = puti(h.in_k);
+  de->view.in_j = puti(h.in_j);
+  de->view.out_f = puti(h.out_f);
+  de->view.out_k = puti(h.out_k);
+  de->view.out_j = puti(h.out_j);
+  st = hip_check(ctx, hipMemcpy(de->dbuf, staging.data(), bytes, hipMemcpyHostToDevice), "upload disc tables");
+  if (st) return st;
+  de->view.p = h.p; de->view.q = h.q; de->view.n_a = h.n_a; de->view.nn = h.nn; de->view.n = h.n; de->view.m = h.m;
+  *out = de.get();
+  ctx->discs[key] = std::move(de);
+  return EL_OK;
+}
+
+el_status ensure_ws(el_ctx* ctx, Workspace& ws, size_t bytes) {
+  if (ws.bytes >= bytes) return EL_OK;
+  if (ws.ptr) {
+    el_status st = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync before workspace growth");
+    if (st) return st;
+    hipFree(ws.ptr);
+    ws.ptr = nullptr;
+    ws.bytes = 0;
+  }
+  el_status st = hip_check(ctx, hipMalloc(&ws.ptr, bytes), "hipMalloc(workspace)");
+  if (st) return st;
+  ws.bytes = bytes;
+  return EL_OK;
+}
+
+static bool mesh_ok(const el_mesh& m) {
+  return m.n_x > 0 && m.n_y > 0 && std::isfinite(m.h) && m.h > 0 && std::isfinite(m.x0) && std::isfinite(m.y0);
+}
+
+}  // namespace el
+
+using namespace el;
+
+extern "C" {
+
+el_status el_create(el_ctx** ctx, int device, void* hip_stream) {
+  if (!ctx) return EL_ERR_ARG;
+  *ctx = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EL_ERR_HIP;
+  if (hipSetDevice(device) != hipSuccess) return EL_ERR_HIP;
+  el_ctx* c = new el_ctx();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+  *ctx = c;
+  return EL_OK;
+}
+
+el_status el_destroy(el_ctx* ctx) {
+  if (!ctx) return EL_OK;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->discs) hipFree(kv.second->dbuf);
+  hipFree(ctx->ws_local.ptr);
+  hipFree(ctx->ws_gmres.ptr);
+  hipFree(ctx->ws_small.ptr);
+  delete ctx;
+  return EL_OK;
+}
+
+el_status el_set_stream(el_ctx* ctx, void* hip_stream) {
+  if (!ctx) return EL_ERR_ARG;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return EL_OK;
+}
+
+const char* el_last_error(const el_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->last_error.c_str();
+}
+
+el_status el_workspace_bytes(const el_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return EL_ERR_ARG;
+  *bytes = ctx->ws_local.bytes + ctx->ws_gmres.bytes + ctx->ws_small.bytes;
+  return EL_OK;
+}
+
+el_status el_disc_sizes(el_disc d, int64_t* nn, int64_t* n, int64_t* m) {
+  DiscHost h;
+  std::string err;
+  if (d.p < 1 || d.p > 12 || d.n_a < 4 || d.n_a > kMaxNa || d.n_a % 4) return EL_ERR_ARG;
+  int64_t q = d.p + 1;
+  if (nn) *nn = q * q;
+  if (n) *n = q * q * d.n_a;
+  if (m) *m = 2 * q * d.n_a;
+  return EL_OK;
+}
+
+el_status el_lgl(int p, double* xi_host, double* w_host) {
+  if (!xi_host || !w_host) return EL_ERR_ARG;
+  return lgl(p, xi_host, w_host) ? EL_OK : EL_ERR_ARG;
+}
+
+el_status el_index_tables(el_disc d, int32_t* in_rows_host, int32_t* out_rows_host) {
+  DiscHost h;
+  std::string err;
+  if (!build_disc(d, h, err)) return EL_ERR_ARG;
+  if (in_rows_host) std::memcpy(in_rows_host, h.in_row.data(), h.m * sizeof(int32_t));
+  if (out_rows_host) std::memcpy(out_rows_host, h.out_row.data(), h.m * sizeof(int32_t));
+  return EL_OK;
+}
+
+el_status el_trace_size(el_disc d, el_mesh mesh, int64_t* n_trace) {
+  if (!n_trace || !mesh_ok(mesh)) return EL_ERR_ARG;
+  if (d.p < 1 || d.p > 12 || d.n_a < 4 || d.n_a % 4) return EL_ERR_ARG;
+  *n_trace = mesh_faces(mesh) * d.n_a * (d.p + 1);
+  return EL_OK;
+}
+
+el_status el_element_dofs(el_ctx* ctx, el_disc d, el_mesh mesh, int32_t* in_dofs, int32_t* out_dofs) {
+  if (!ctx) return EL_ERR_ARG;
+  if (!mesh_ok(mesh)) return set_error(ctx, EL_ERR_ARG, "el_element_dofs: bad mesh");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_element_dofs(ctx, de, mesh, in_dofs, out_dofs);
+}
+
+el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E, const double* h,
+                         const double* kappa, const double* sigma, double* in2out, double* in2sol,
+                         double* in2mean, double* rel_resid) {
+  if (!ctx) return EL_ERR_ARG;
+  if (E < 0) return set_error(ctx, EL_ERR_ARG, "el_local_solve: E < 0");
+  if (precision != EL_FP64 && precision != EL_FP32_IR)
+    return set_error(ctx, EL_ERR_ARG, "el_local_solve: unknown precision");
+  if (E == 0) return EL_OK;
+  if (!h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_local_solve: null input");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_local_solve(ctx, de, precision, E, h, kappa, sigma, in2out, in2sol, in2mean, rel_resid);
+}
+
+el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_side_host, double* b) {
+  if (!ctx) return EL_ERR_ARG;
+  if (!mesh_ok(mesh) || !g_side_host || !b) return set_error(ctx, EL_ERR_ARG, "el_trace_rhs: bad argument");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_trace_rhs(ctx, de, mesh, g_side_host, b);
+}
+
+el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out, int op_dtype,
+                          const double* x, double* y) {
+  if (!ctx) return EL_ERR_ARG;
+  if (!mesh_ok(mesh) || !in2out || !x || !y || (op_dtype != EL_F64 && op_dtype != EL_BF16))
+    return set_error(ctx, EL_ERR_ARG, "el_trace_matvec: bad argument");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_trace_matvec(ctx, de, mesh, in2out, op_dtype, x, y);
+}
+
+el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* meshes_host,
+                         const void* const* in2out, int op_dtype, const double* const* b,
+                         double* const* trace, const el_gmres_opts* opts_host, el_gmres_report* rep_host) {
+  if (!ctx) return EL_ERR_ARG;
+  if (n_mesh <= 0 || !meshes_host || !in2out || !b || !trace || !opts_host || !rep_host)
+    return set_error(ctx, EL_ERR_ARG, "el_trace_solve: bad argument");
+  if (op_dtype != EL_F64 && op_dtype != EL_BF16) return set_error(ctx, EL_ERR_ARG, "el_trace_solve: op_dtype");
+  const el_gmres_opts& o = *opts_host;
+  if (!(o.tol > 0) || o.restart < 1 || o.restart > 128 || o.max_iter < 1)
+    return set_error(ctx, EL_ERR_ARG, "el_trace_solve: bad GMRES options");
+  for (int i = 0; i < n_mesh; ++i) {
+    if (!mesh_ok(meshes_host[i]) || !in2out[i] || !b[i] || !trace[i]) {
+      std::ostringstream os;
+      os << "el_trace_solve: bad mesh or pointer for mesh " << i;
+      return set_error(ctx, EL_ERR_ARG, os.str());
+    }
+  }
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return run_trace_solve(ctx, de, n_mesh, meshes_host, in2out, op_dtype, b, trace, o, rep_host);
+}
+
+el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
+                     const double* trace, double* u, double* mean) {
+  if (!ctx) return EL_ERR_ARG;
+  if (!mesh_ok(mesh) || !in2sol || !trace || (op_dtype != EL_F64 && op_dtype != EL_BF16))
+    return set_error(ctx, EL_ERR_ARG, "el_recover: bad argument");
+  if (!u && !mean) return EL_OK;
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_recover(ctx, de, mesh, in2sol, op_dtype, trace, u, mean);
+}
+
+el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean, int op_dtype,
+                          const double* trace, double* mean) {
+  if (!ctx) return EL_ERR_ARG;
+  if (!mesh_ok(mesh) || !in2mean || !trace || !mean || (op_dtype != EL_F64 && op_dtype != EL_BF16))
+    return set_error(ctx, EL_ERR_ARG, "el_recover_mean: bad argument");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_recover_mean(ctx, de, mesh, in2mean, op_dtype, trace, mean);
+}
+
+el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* a,
+                     const double* ref, double* out_host) {
+  if (!ctx) return EL_ERR_ARG;
+  if (E <= 0 || !h || !a || !ref || !out_host) return set_error(ctx, EL_ERR_ARG, "el_mean_l2: bad argument");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_mean_l2(ctx, de, E, h, a, ref, out_host);
+}
+
+}  // extern "C"

@@ -1,0 +1,193 @@
+// Element-wise recovery (Alg. 1 step 4, eq. hdg_local_mat_sol) and the mean
+// intensity (eq. ang_ave), plus the element L2 norms used for the relative
+// error of Sec. 3.2.1.
+//
+// k_recover streams in2sol [E][n][m] (FP64 or bfloat16) once: one workgroup
+// per element gathers the m inflow traces into LDS, groups of 8 lanes reduce
+// one operator row each, u is staged in LDS and the ordinate average is taken
+// there.  HBM-bound: n*m operator entries per element.
+#include <cmath>
+#include <sstream>
+
+#include "el_internal.h"
+
+namespace el {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct MeshDev {
+  int n_x, n_y, n_vf;
+};
+
+__device__ inline int face_of(const MeshDev& ms, int i, int j, int f) {
+  switch (f) {
+    case 0: return j * (ms.n_x + 1) + i;
+    case 1: return j * (ms.n_x + 1) + i + 1;
+    case 2: return ms.n_vf + j * ms.n_x + i;
+    default: return ms.n_vf + (j + 1) * ms.n_x + i;
+  }
+}
+
+template <typename OpT>
+__device__ inline double row_dot(const OpT* __restrict__ row, const double* tin, int m, int gl);
+
+template <>
+__device__ inline double row_dot<double>(const double* __restrict__ row, const double* tin, int m, int gl) {
+  double acc = 0.0;
+  for (int c = 2 * gl; c < m; c += 16) {
+    double2 v = *reinterpret_cast<const double2*>(row + c);
+    acc += v.x * tin[c] + v.y * tin[c + 1];
+  }
+  return acc;
+}
+
+template <>
+__device__ inline double row_dot<uint16_t>(const uint16_t* __restrict__ row, const double* tin, int m, int gl) {
+  double acc = 0.0;
+  for (int c = 8 * gl; c < m; c += 64) {
+    if (c + 8 <= m) {
+      uint4 v = *reinterpret_cast<const uint4*>(row + c);
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc += (double)__uint_as_float(w[u] << 16) * tin[c + 2 * u];
+        acc += (double)__uint_as_float(w[u] & 0xffff0000u) * tin[c + 2 * u + 1];
+      }
+    } else {
+      for (int cc = c; cc < m; ++cc) acc += (double)__uint_as_float(((uint32_t)row[cc]) << 16) * tin[cc];
+    }
+  }
+  return acc;
+}
+
+// rows = number of operator rows (n for in2sol, nn for in2mean);
+// mode 0: u (and optional mean over ordinates) from in2sol;
+// mode 1: mean directly from in2mean.
+template <typename OpT>
+__global__ void __launch_bounds__(kThreads) k_recover(DiscDev dv, MeshDev ms, const OpT* __restrict__ op,
+                                                       int rows, int mode, const double* __restrict__ t,
+                                                       double* __restrict__ u, double* __restrict__ mean) {
+  extern __shared__ double sm[];
+  double* tin = sm;             // [m]
+  double* ub = sm + dv.m;       // [rows]
+  const int e = blockIdx.x;
+  const int i = e % ms.n_x, j = e / ms.n_x;
+  const int m = dv.m;
+  for (int c = threadIdx.x; c < m; c += kThreads) {
+    const int F = face_of(ms, i, j, dv.in_f[c]);
+    tin[c] = t[(F * dv.n_a + dv.in_k[c]) * dv.q + dv.in_j[c]];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 3, gl = lane & 7;
+  const OpT* base = op + (size_t)e * rows * m;
+  for (int r = wave * 8 + g; r < rows; r += (kThreads / 64) * 8) {
+    double acc = row_dot<OpT>(base + (size_t)r * m, tin, m, gl);
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (gl == 0) ub[r] = acc;
+  }
+  __syncthreads();
+  if (mode == 1) {
+    for (int r = threadIdx.x; r < rows; r += kThreads) mean[(size_t)e * rows + r] = ub[r];
+    return;
+  }
+  if (u)
+    for (int r = threadIdx.x; r < rows; r += kThreads) u[(size_t)e * rows + r] = ub[r];
+  if (mean) {
+    const int nn = dv.nn;
+    const double s = 1.0 / dv.n_a;
+    for (int nd = threadIdx.x; nd < nn; nd += kThreads) {
+      double acc = 0.0;
+      for (int k = 0; k < dv.n_a; ++k) acc += ub[k * nn + nd];
+      mean[(size_t)e * nn + nd] = acc * s;
+    }
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// partial[blk][0..1] over elements of the block chunk
+__global__ void k_l2_partial(const double* __restrict__ W, int nn, int64_t E, const double* __restrict__ h,
+                             const double* __restrict__ a, const double* __restrict__ ref, double* partial) {
+  __shared__ double s0[4], s1[4];
+  double d2 = 0.0, r2 = 0.0;
+  const int64_t total = E * nn;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx / nn;
+    const int nd = (int)(idx - e * nn);
+    const double hw = 0.25 * h[e] * h[e] * W[nd];
+    const double d = a[idx] - ref[idx];
+    d2 += hw * d * d;
+    r2 += hw * ref[idx] * ref[idx];
+  }
+  d2 = wave_sum(d2);
+  r2 = wave_sum(r2);
+  if ((threadIdx.x & 63) == 0) { s0[threadIdx.x >> 6] = d2; s1[threadIdx.x >> 6] = r2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = s0[0] + s0[1] + s0[2] + s0[3];
+    partial[2 * blockIdx.x + 1] = s1[0] + s1[1] + s1[2] + s1[3];
+  }
+}
+
+}  // namespace
+
+el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const void* in2sol,
+                         int op_dtype, const double* trace, double* u, double* mean) {
+  MeshDev ms{mesh.n_x, mesh.n_y, (mesh.n_x + 1) * mesh.n_y};
+  const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
+  const DiscHost& dh = de->host;
+  const size_t smem = sizeof(double) * (dh.m + dh.n);
+  if (op_dtype == EL_F64)
+    hipLaunchKernelGGL(k_recover<double>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const double*>(in2sol), dh.n, 0, trace, u, mean);
+  else
+    hipLaunchKernelGGL(k_recover<uint16_t>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const uint16_t*>(in2sol), dh.n, 0, trace, u, mean);
+  return hip_check(ctx, hipGetLastError(), "launch k_recover");
+}
+
+el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const void* in2mean,
+                              int op_dtype, const double* trace, double* mean) {
+  MeshDev ms{mesh.n_x, mesh.n_y, (mesh.n_x + 1) * mesh.n_y};
+  const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
+  const DiscHost& dh = de->host;
+  const size_t smem = sizeof(double) * (dh.m + dh.nn);
+  if (op_dtype == EL_F64)
+    hipLaunchKernelGGL(k_recover<double>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const double*>(in2mean), dh.nn, 1, trace, nullptr, mean);
+  else
+    hipLaunchKernelGGL(k_recover<uint16_t>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const uint16_t*>(in2mean), dh.nn, 1, trace, nullptr, mean);
+  return hip_check(ctx, hipGetLastError(), "launch k_recover(mean)");
+}
+
+el_status launch_mean_l2(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* a,
+                         const double* ref, double* out_host) {
+  const int nblk = 512;
+  el_status st = ensure_ws(ctx, ctx->ws_small, sizeof(double) * 2 * nblk + 4096);
+  if (st) return st;
+  double* partial = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ws_small.ptr) + 4096);
+  hipLaunchKernelGGL(k_l2_partial, dim3(nblk), dim3(256), 0, ctx->stream, de->view.W, de->host.nn, E, h, a, ref,
+                     partial);
+  st = hip_check(ctx, hipGetLastError(), "launch k_l2_partial");
+  if (st) return st;
+  std::vector<double> hp(2 * nblk);
+  hipError_t he = hipMemcpyAsync(hp.data(), partial, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, ctx->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return hip_check(ctx, he, "el_mean_l2");
+  double d2 = 0.0, r2 = 0.0;
+  for (int b = 0; b < nblk; ++b) { d2 += hp[2 * b]; r2 += hp[2 * b + 1]; }
+  out_host[0] = d2;
+  out_host[1] = r2;
+  return EL_OK;
+}
+
+}  // namespace el

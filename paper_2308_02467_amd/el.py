@@ -1,0 +1,284 @@
+"""ctypes binding of the C ABI in include/el.h (libel.so, built for gfx950).
+
+Argument marshalling only: torch tensors provide device memory and the
+stream; every step of the hot path runs in the library's HIP kernels.  The
+binding raises if the library is missing -- there is no CPU fallback.
+Function names match the C entry points.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libel.so")
+
+EL_OK = 0
+EL_WARN_NOT_CONVERGED = 1
+EL_ERR_ARG = -1
+EL_ERR_HIP = -2
+EL_ERR_SINGULAR = -3
+EL_ERR_NONFINITE = -4
+EL_ERR_NOMEM = -5
+EL_SCATTER_ISO = 0
+EL_SCATTER_HG = 1
+EL_FP64 = 0
+EL_FP32_IR = 1
+EL_F64 = 0
+EL_BF16 = 1
+
+_ERRNAMES = {EL_ERR_ARG: "EL_ERR_ARG", EL_ERR_HIP: "EL_ERR_HIP", EL_ERR_SINGULAR: "EL_ERR_SINGULAR",
+             EL_ERR_NONFINITE: "EL_ERR_NONFINITE", EL_ERR_NOMEM: "EL_ERR_NOMEM"}
+
+
+class ElError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class el_disc(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("n_a", ctypes.c_int), ("scatter", ctypes.c_int), ("g_hg", ctypes.c_double)]
+
+
+class el_mesh(ctypes.Structure):
+    _fields_ = [("n_x", ctypes.c_int), ("n_y", ctypes.c_int), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("h", ctypes.c_double)]
+
+
+class el_gmres_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int)]
+
+
+class el_gmres_report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("relres", ctypes.c_double),
+                ("converged", ctypes.c_int)]
+
+
+_lib = None
+
+_SIGS = {
+    "el_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p],
+    "el_destroy": [ctypes.c_void_p],
+    "el_set_stream": [ctypes.c_void_p, ctypes.c_void_p],
+    "el_last_error": [ctypes.c_void_p],
+    "el_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "el_disc_sizes": [el_disc, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                      ctypes.POINTER(ctypes.c_int64)],
+    "el_lgl": [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "el_index_tables": [el_disc, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "el_trace_size": [el_disc, el_mesh, ctypes.POINTER(ctypes.c_int64)],
+    "el_element_dofs": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_void_p],
+    "el_local_solve": [ctypes.c_void_p, el_disc, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "el_trace_rhs": [ctypes.c_void_p, el_disc, el_mesh, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
+    "el_trace_matvec": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                        ctypes.c_void_p],
+    "el_trace_solve": [ctypes.c_void_p, el_disc, ctypes.c_int, ctypes.POINTER(el_mesh),
+                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(el_gmres_opts),
+                       ctypes.POINTER(el_gmres_report)],
+    "el_recover": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_void_p],
+    "el_recover_mean": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                        ctypes.c_void_p],
+    "el_mean_l2": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.POINTER(ctypes.c_double)],
+}
+
+
+def lib():
+    """Load libel.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with paper_2308_02467_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "el_last_error" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def disc(p, n_a, g_hg=0.0):
+    return el_disc(int(p), int(n_a), EL_SCATTER_HG if g_hg else EL_SCATTER_ISO, float(g_hg))
+
+
+def mesh(n_x, n_y, h, x0=0.0, y0=0.0):
+    return el_mesh(int(n_x), int(n_y), float(x0), float(y0), float(h))
+
+
+def disc_sizes(d):
+    nn, n, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    st = lib().el_disc_sizes(d, ctypes.byref(nn), ctypes.byref(n), ctypes.byref(m))
+    if st != EL_OK:
+        raise ElError(st, "unsupported discretization")
+    return nn.value, n.value, m.value
+
+
+def lgl(p):
+    import numpy as np
+    xi = (ctypes.c_double * (p + 1))()
+    w = (ctypes.c_double * (p + 1))()
+    st = lib().el_lgl(int(p), xi, w)
+    if st != EL_OK:
+        raise ElError(st, "el_lgl")
+    return np.array(xi[:]), np.array(w[:])
+
+
+def index_tables(d):
+    import numpy as np
+    _, _, m = disc_sizes(d)
+    a = (ctypes.c_int32 * m)()
+    b = (ctypes.c_int32 * m)()
+    st = lib().el_index_tables(d, a, b)
+    if st != EL_OK:
+        raise ElError(st, "el_index_tables")
+    return np.array(a[:], dtype=np.int64), np.array(b[:], dtype=np.int64)
+
+
+def trace_size(d, ms):
+    n = ctypes.c_int64()
+    st = lib().el_trace_size(d, ms, ctypes.byref(n))
+    if st != EL_OK:
+        raise ElError(st, "el_trace_size")
+    return n.value
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _op_dtype(t):
+    if t.dtype == torch.float64:
+        return EL_F64
+    if t.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return EL_BF16
+    raise ValueError(f"operator dtype {t.dtype} not supported (float64 or bfloat16)")
+
+
+class Context:
+    """One library context bound to a device and a HIP stream."""
+
+    def __init__(self, device=0, stream=None):
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib().el_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream.cuda_stream))
+        if st != EL_OK:
+            raise ElError(st, "el_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().el_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow_warn=False):
+        if st == EL_OK or (allow_warn and st == EL_WARN_NOT_CONVERGED):
+            return st
+        raise ElError(st, lib().el_last_error(self.h).decode())
+
+    def last_error(self):
+        return lib().el_last_error(self.h).decode()
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        self._check(lib().el_workspace_bytes(self.h, ctypes.byref(b)))
+        return b.value
+
+    # -- local solve -----------------------------------------------------------
+    def el_local_solve(self, d, h, kappa, sigma, precision=EL_FP64, in2out=None, in2sol=None, in2mean=None,
+                       rel_resid=None):
+        nn, n, m = disc_sizes(d)
+        E = h.numel()
+        args = [_ptr(h, torch.float64, E, "h"), _ptr(kappa, torch.float64, E * nn, "kappa"),
+                _ptr(sigma, torch.float64, E * nn, "sigma"),
+                _ptr(in2out, torch.float64, E * m * m, "in2out"), _ptr(in2sol, torch.float64, E * n * m, "in2sol"),
+                _ptr(in2mean, torch.float64, E * nn * m, "in2mean"),
+                _ptr(rel_resid, torch.float64, E, "rel_resid")]
+        return self._check(lib().el_local_solve(self.h, d, int(precision), E, *args))
+
+    def el_element_dofs(self, d, ms, in_dofs=None, out_dofs=None):
+        _, _, m = disc_sizes(d)
+        E = ms.n_x * ms.n_y
+        return self._check(lib().el_element_dofs(self.h, d, ms, _ptr(in_dofs, torch.int32, E * m, "in_dofs"),
+                                                 _ptr(out_dofs, torch.int32, E * m, "out_dofs")))
+
+    # -- skeleton ----------------------------------------------------------------
+    def el_trace_rhs(self, d, ms, g_side, b):
+        import numpy as np
+        g = np.ascontiguousarray(np.asarray(g_side, dtype=np.float64).reshape(4, d.n_a))
+        nt = trace_size(d, ms)
+        return self._check(lib().el_trace_rhs(self.h, d, ms, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              _ptr(b, torch.float64, nt, "b")))
+
+    def el_trace_matvec(self, d, ms, in2out, x, y):
+        nt = trace_size(d, ms)
+        return self._check(lib().el_trace_matvec(self.h, d, ms, _ptr(in2out, name="in2out"), _op_dtype(in2out),
+                                                 _ptr(x, torch.float64, nt, "x"), _ptr(y, torch.float64, nt, "y")))
+
+    def el_trace_solve(self, d, meshes, in2outs, bs, traces, tol=1e-12, restart=50, max_iter=2000):
+        k = len(meshes)
+        M = (el_mesh * k)(*meshes)
+        ops = (ctypes.c_void_p * k)(*[_ptr(t, name="in2out") for t in in2outs])
+        dt = {_op_dtype(t) for t in in2outs}
+        if len(dt) != 1:
+            raise ValueError("all operators must share one dtype")
+        B = (ctypes.c_void_p * k)(*[_ptr(b, torch.float64, trace_size(d, ms), "b") for b, ms in zip(bs, meshes)])
+        X = (ctypes.c_void_p * k)(*[_ptr(x, torch.float64, trace_size(d, ms), "trace") for x, ms in zip(traces, meshes)])
+        opts = el_gmres_opts(float(tol), int(restart), int(max_iter))
+        rep = (el_gmres_report * k)()
+        st = lib().el_trace_solve(self.h, d, k, M, ops, dt.pop(), B, X, ctypes.byref(opts), rep)
+        self._check(st, allow_warn=True)
+        return st, [dict(iters=r.iters, restarts=r.restarts, relres=r.relres, converged=bool(r.converged))
+                    for r in rep]
+
+    # -- recovery ------------------------------------------------------------------
+    def el_recover(self, d, ms, in2sol, trace, u=None, mean=None):
+        nn, n, _ = disc_sizes(d)
+        E = ms.n_x * ms.n_y
+        return self._check(lib().el_recover(self.h, d, ms, _ptr(in2sol, name="in2sol"), _op_dtype(in2sol),
+                                            _ptr(trace, torch.float64, trace_size(d, ms), "trace"),
+                                            _ptr(u, torch.float64, E * n, "u"),
+                                            _ptr(mean, torch.float64, E * nn, "mean")))
+
+    def el_recover_mean(self, d, ms, in2mean, trace, mean):
+        nn, _, _ = disc_sizes(d)
+        E = ms.n_x * ms.n_y
+        return self._check(lib().el_recover_mean(self.h, d, ms, _ptr(in2mean, name="in2mean"), _op_dtype(in2mean),
+                                                 _ptr(trace, torch.float64, trace_size(d, ms), "trace"),
+                                                 _ptr(mean, torch.float64, E * nn, "mean")))
+
+    def el_mean_l2(self, d, h, a, ref):
+        nn, _, _ = disc_sizes(d)
+        E = h.numel()
+        out = (ctypes.c_double * 2)()
+        self._check(lib().el_mean_l2(self.h, d, E, _ptr(h, torch.float64, E, "h"),
+                                     _ptr(a, torch.float64, E * nn, "a"), _ptr(ref, torch.float64, E * nn, "ref"),
+                                     out))
+        return out[0], out[1]
