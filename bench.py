@@ -39,8 +39,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="elements per side")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="after timing: error of the timed solution and of bfloat16-stored operators "
+                         "against a 1e-12 FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256, help="elements in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=1536, help="elements in the oracle sample")
     return ap.parse_args()
 
 
@@ -87,7 +91,7 @@ def main():
         e1.record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
         e2.record(stream)
-        st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=args.tol, restart=50, max_iter=5000)
+        st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
         e3.record(stream)
         ctx.el_recover(d, ms, i2s, t, u, mean)
         e4.record(stream)
@@ -114,6 +118,10 @@ def main():
     flop_el = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * m
     achieved = flop_el * E / (local_ms * 1e-3) / 1e12
 
+    acc = None
+    if args.accuracy:
+        print("[bench] accuracy diagnostics", file=sys.stderr, flush=True)
+        acc = accuracy(ctx, el, d, ms, hh, i2o, i2s, b, mean, args.restart)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu oracle sample of {args.cpu_sample} elements", file=sys.stderr, flush=True)
@@ -128,11 +136,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"plain FP64 HDG, {nx}x{nx} elements, p=6, N_a=16, Gaussian cloud, left inflow",
-                   "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol, "gmres_restart": 50},
+                   "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol, "gmres_restart": args.restart},
         "phases_ms": {"local_solve": local_ms, "trace_rhs": float(np.median(phases[:, 1])),
                       "gmres": float(np.median(phases[:, 2])), "recover": float(np.median(phases[:, 3]))},
         "local_solve_el_per_s": E / (local_ms * 1e-3),
         "gmres": gm,
+        "accuracy": acc,
         "roofline": {"bound": "mfma", "kernel": "k_local_lu<double>", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": None},
@@ -140,6 +149,36 @@ def main():
     }
     print(json.dumps(out))
     ctx.close()
+
+
+def accuracy(ctx, el, d, ms, hh, i2o, i2s, b, mean_timed, restart):
+    """Relative L2 errors of the mean intensity against the FP64 solve at 1e-12."""
+    import torch
+    E = hh.numel()
+    nn = mean_timed.shape[1]
+    t_ref = torch.empty_like(b)
+    st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t_ref], tol=1e-12, restart=restart, max_iter=40000)
+    mean_ref = torch.empty_like(mean_timed)
+    ctx.el_recover(d, ms, i2s, t_ref, None, mean_ref)
+    d2, r2 = ctx.el_mean_l2(d, hh, mean_timed, mean_ref)
+    out = {"reference_gmres": rep[0], "timed_solution_rel_l2": (d2 / r2) ** 0.5}
+    # storage precision of the exact operators: which part costs accuracy
+    def solve_with(op_o, op_s):
+        tt = torch.empty_like(b)
+        st, rp = ctx.el_trace_solve(d, [ms], [op_o], [b], [tt], tol=1e-12, restart=restart, max_iter=40000)
+        mm_ = torch.empty_like(mean_timed)
+        ctx.el_recover(d, ms, op_s, tt, None, mm_)
+        d2, r2 = ctx.el_mean_l2(d, hh, mm_, mean_ref)
+        return (d2 / r2) ** 0.5
+    o16 = i2o.to(torch.bfloat16)
+    out["bf16_in2out_f64_in2sol_rel_l2"] = solve_with(o16, i2s)
+    s16 = i2s.to(torch.bfloat16)
+    out["bf16_in2out_bf16_in2sol_rel_l2"] = solve_with(o16, s16)
+    del o16
+    o32 = i2o.to(torch.float32)
+    out["f32_in2out_bf16_in2sol_rel_l2"] = solve_with(o32, s16)
+    del o32, s16
+    return out
 
 
 def cpu_baseline(p, n_a, h, kap, sig, count):

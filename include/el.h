@@ -71,6 +71,7 @@ typedef int el_status;
 /* operator storage types for the trace sweep and recovery */
 #define EL_F64 0
 #define EL_BF16 1
+#define EL_F32 2
 
 typedef struct el_ctx el_ctx;
 
@@ -92,7 +93,7 @@ typedef struct {
 
 typedef struct {
   double tol;     /* relative residual ||b - (I-P)x|| / ||b|| */
-  int restart;    /* Krylov dimension per cycle, 1..128 */
+  int restart;    /* Krylov dimension per cycle, 1..256 */
   int max_iter;   /* total Arnoldi steps */
 } el_gmres_opts;
 
@@ -151,8 +152,8 @@ el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E,
 el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_side_host, double* b);
 
 /* y = (I - P) x on one mesh: (P x)[out dofs of e] = in2out_e x[in dofs of e],
- * P = 0 on domain-inflow rows.  in2out is [E][m][m] FP64 (op_dtype EL_F64)
- * or bfloat16 bit patterns (EL_BF16); accumulation is FP64. */
+ * P = 0 on domain-inflow rows.  in2out is [E][m][m] FP64 (op_dtype EL_F64),
+ * FP32 (EL_F32) or bfloat16 bit patterns (EL_BF16); accumulation is FP64. */
 el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out,
                           int op_dtype, const double* x, double* y);
 
@@ -169,11 +170,11 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
 
 /* ---- recovery (Alg. 1 step 4, eq. hdg_local_mat_sol, eq. ang_ave) ----------
  * u [E][n] = in2sol_e t[in dofs of e] (NULL = skip) and the mean intensity
- * mean [E][nn] = (1/N_a) sum_k u (NULL = skip).  in2sol is [E][n][m] FP64 or
- * bfloat16 bits (op_dtype). */
+ * mean [E][nn] = (1/N_a) sum_k u (NULL = skip).  in2sol is [E][n][m] FP64,
+ * FP32 or bfloat16 bits (op_dtype). */
 el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
                      const double* trace, double* u, double* mean);
-/* Mean intensity directly from in2mean [E][nn][m] (FP64 or bfloat16 bits). */
+/* Mean intensity directly from in2mean [E][nn][m] (FP64, FP32 or bfloat16 bits). */
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean,
                           int op_dtype, const double* trace, double* mean);
 
@@ -182,6 +183,84 @@ el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2m
  * out_host[1] = sum_e (h_e/2)^2 sum W ref^2.  Synchronizes. */
 el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h,
                      const double* a, const double* ref, double* out_host);
+
+
+/* ---- element network (Sec. 2.4, eq. param2sol; training Sec. 3.1) ---------
+ * A fully connected network x_i = f_i(A_i x_{i-1} + b_i), f = GELU (exact
+ * erf form) or ELU on the hidden layers and the identity on the output layer
+ * (Sec. 2.4.1), maps the features of one element to its operators
+ * (in2out [m][m] followed by in2sol [n][m], row-major; n_out = m*m + n*m).
+ * Input of one element (raw): x = (h, kappa[nn], sigma[nn]).  Features:
+ * log10 h, log10 max(h kappa/2, 1e-12), log10 max(h sigma/2, 1e-12)
+ * (the reference-element coefficients of Sec. 2.4.1), z-scored with
+ * training statistics.  Targets are z-scored per output entry.  Loss: mean
+ * absolute error (Sec. 3.1; subgradient 0 at 0).  Optimizer: Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8), FP32 master weights, bfloat16 copies
+ * for the matrix-core GEMMs, FP32 accumulation. */
+#define EL_ACT_GELU 0
+#define EL_ACT_ELU 1
+
+typedef struct {
+  int n_in;        /* raw inputs per element, 1 + 2*nn */
+  int width;       /* hidden width */
+  int depth;       /* hidden layers (>= 1) */
+  int act;         /* EL_ACT_GELU or EL_ACT_ELU */
+  int64_t n_out;   /* m*m + n*m */
+  uint64_t seed;   /* initialization: W, b ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) */
+} el_net_desc;
+
+typedef struct el_net el_net;
+
+/* Network state blob (el_net_save / el_net_load), little endian:
+ *   bytes 0..7    magic "ELNET01\0"
+ *   int32  n_in, width, depth, act, k0 (= n_in rounded up to 32), pad
+ *   int64  n_out, step (Adam steps taken), n_params
+ *   double box[6] = h_min, h_max, kappa_min, kappa_max, sigma_min, sigma_max
+ *   (header = 112 bytes), then float32 arrays:
+ *   feat_mean[n_in], feat_std[n_in], y_mean[n_out], y_std[n_out],
+ *   theta[n_params], adam_m[n_params], adam_v[n_params]
+ * theta = for l = 0..depth: W_l [out_l][in_l] row-major then b_l [out_l],
+ * with in_0 = k0 (columns >= n_in are zero), in_l = width (l > 0),
+ * out_l = width (l < depth), out_depth = n_out; every W_l starts at a
+ * multiple of 64 floats (zero gap after the preceding b_l). */
+el_status el_net_create(el_ctx* ctx, const el_net_desc* desc_host, el_net** net);
+el_status el_net_destroy(el_net* net);
+/* host_buf == NULL: *bytes receives the blob size. */
+el_status el_net_save(el_ctx* ctx, const el_net* net, void* host_buf, size_t* bytes);
+el_status el_net_load(el_ctx* ctx, const void* host_buf, size_t bytes, el_net** net);
+/* Feature / target statistics and the training box from N training pairs:
+ * x [N][n_in] float32 raw inputs, y [N][n_out] bfloat16 targets. */
+el_status el_net_fit_normalization(el_ctx* ctx, el_net* net, int64_t N, const float* x, const uint16_t* y);
+/* Copy an FP32 parameter-sized buffer (which: 0 theta, 1 gradient of the
+ * last training step in units of the loss, 2 adam_m, 3 adam_v) to dst [n_params]. */
+el_status el_net_params(el_ctx* ctx, const el_net* net, int which, float* dst);
+el_status el_net_num_params(const el_net* net, int64_t* n_params);
+
+/* Training pairs from the FP64 local solver: y [E][n_out] bfloat16
+ * (round to nearest even) = (in2out, in2sol) of each element. */
+el_status el_make_pairs(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa,
+                        const double* sigma, uint16_t* y);
+
+/* One training step on a batch of B pairs: forward, MAE loss, backward,
+ * Adam with learning rate lr.  loss: device float, receives the batch loss
+ * (mean absolute error in normalized units). */
+el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, const uint16_t* y, float lr,
+                        float* loss);
+
+/* Normalized network outputs y_norm [B][n_out] (float32) for raw inputs x
+ * [B][n_in] (float32); for testing the forward pass. */
+el_status el_net_forward(el_ctx* ctx, const el_net* net, int64_t B, const float* x, float* y_norm);
+
+/* Learned operators for E elements (inference): in2out [E][m][m] and
+ * in2sol [E][n][m] stored as out_dtype (EL_BF16: bfloat16 bits, round to
+ * nearest even; EL_F32: float32); either may be NULL.  in_range [E]
+ * (1 = every input inside the training box; may be NULL).  fallback = 1:
+ * elements outside the box are solved by the plain local solver
+ * (precision) and written, rounded to out_dtype, into the same outputs;
+ * *n_fallback_host receives their count.  Synchronizes. */
+el_status el_infer(el_ctx* ctx, const el_net* net, el_disc d, int64_t E, const double* h,
+                   const double* kappa, const double* sigma, void* in2out, void* in2sol, int out_dtype,
+                   uint8_t* in_range, int fallback, int precision, int64_t* n_fallback_host);
 
 #ifdef __cplusplus
 }

@@ -218,7 +218,7 @@ el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_sid
 el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out, int op_dtype,
                           const double* x, double* y) {
   if (!ctx) return EL_ERR_ARG;
-  if (!mesh_ok(mesh) || !in2out || !x || !y || (op_dtype != EL_F64 && op_dtype != EL_BF16))
+  if (!mesh_ok(mesh) || !in2out || !x || !y || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
     return set_error(ctx, EL_ERR_ARG, "el_trace_matvec: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
@@ -233,9 +233,10 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
   if (!ctx) return EL_ERR_ARG;
   if (n_mesh <= 0 || !meshes_host || !in2out || !b || !trace || !opts_host || !rep_host)
     return set_error(ctx, EL_ERR_ARG, "el_trace_solve: bad argument");
-  if (op_dtype != EL_F64 && op_dtype != EL_BF16) return set_error(ctx, EL_ERR_ARG, "el_trace_solve: op_dtype");
+  if (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32)
+    return set_error(ctx, EL_ERR_ARG, "el_trace_solve: op_dtype");
   const el_gmres_opts& o = *opts_host;
-  if (!(o.tol > 0) || o.restart < 1 || o.restart > 128 || o.max_iter < 1)
+  if (!(o.tol > 0) || o.restart < 1 || o.restart > 256 || o.max_iter < 1)
     return set_error(ctx, EL_ERR_ARG, "el_trace_solve: bad GMRES options");
   for (int i = 0; i < n_mesh; ++i) {
     if (!mesh_ok(meshes_host[i]) || !in2out[i] || !b[i] || !trace[i]) {
@@ -254,7 +255,7 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
 el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
                      const double* trace, double* u, double* mean) {
   if (!ctx) return EL_ERR_ARG;
-  if (!mesh_ok(mesh) || !in2sol || !trace || (op_dtype != EL_F64 && op_dtype != EL_BF16))
+  if (!mesh_ok(mesh) || !in2sol || !trace || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
     return set_error(ctx, EL_ERR_ARG, "el_recover: bad argument");
   if (!u && !mean) return EL_OK;
   hipSetDevice(ctx->device);
@@ -267,7 +268,7 @@ el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, i
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean, int op_dtype,
                           const double* trace, double* mean) {
   if (!ctx) return EL_ERR_ARG;
-  if (!mesh_ok(mesh) || !in2mean || !trace || !mean || (op_dtype != EL_F64 && op_dtype != EL_BF16))
+  if (!mesh_ok(mesh) || !in2mean || !trace || !mean || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
     return set_error(ctx, EL_ERR_ARG, "el_recover_mean: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;

@@ -29,6 +29,7 @@
 #include <sstream>
 
 #include "el_internal.h"
+#include "gemm_bf16.h"
 
 namespace el {
 namespace {
@@ -72,6 +73,12 @@ struct LuArgs {
   double* in2out;
   double* in2sol;
   double* in2mean;
+  uint16_t* b_i2o;        // bfloat16 in2out [E][m][m]
+  uint16_t* b_i2s;        // bfloat16 in2sol [E][n][m]
+  float* f_i2o;           // float32 in2out [E][m][m]
+  float* f_i2s;           // float32 in2sol [E][n][m]
+  uint16_t* pairs;        // bfloat16 (in2out, in2sol) [E][m*m + n*m]
+  const int32_t* emap;    // batch slot -> element index (inputs and outputs), or null
   T* fac;        // [slots][npan][npad][NB]
   T* inv;        // [slots][npan][2][NB][NB]
   int* flags;    // [0] first singular element, [1] first bad-input element
@@ -183,7 +190,8 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   T* fac = a.fac + (size_t)blockIdx.x * npan * npad * NB;
   T* inv = a.inv + (size_t)blockIdx.x * npan * 2 * NB * NB;
 
-  for (int64_t e = blockIdx.x; e < a.E; e += gridDim.x) {
+  for (int64_t eb = blockIdx.x; eb < a.E; eb += gridDim.x) {
+    const int64_t e = a.emap ? (int64_t)a.emap[eb] : eb;
     // ---- coefficients and input check
     const double he = a.h[e];
     __syncthreads();   // every thread has read the previous element's flags
@@ -352,18 +360,31 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         }
       }
       // outputs (pan rows are volume DOFs in natural order)
-      if (a.in2sol) {
-        double* o = a.in2sol + (size_t)e * n * m;
+      const int64_t n_out = (int64_t)m * m + (int64_t)n * m;
+      if (a.in2sol || a.b_i2s || a.f_i2s || a.pairs) {
         for (int idx = tid; idx < n * NB; idx += kThreads) {
           int r = idx >> 4, c = idx & 15;
-          if (P0 + c < m) o[(size_t)r * m + P0 + c] = (double)pan[r * LDP + c];
+          if (P0 + c < m) {
+            const double v = (double)pan[r * LDP + c];
+            const int64_t o = ((int64_t)e * n + r) * m + P0 + c;
+            if (a.in2sol) a.in2sol[o] = v;
+            if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
+            if (a.f_i2s) a.f_i2s[o] = (float)v;
+            if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+          }
         }
       }
-      if (a.in2out) {
-        double* o = a.in2out + (size_t)e * m * m;
+      if (a.in2out || a.b_i2o || a.f_i2o || a.pairs) {
         for (int idx = tid; idx < m * NB; idx += kThreads) {
           int r = idx >> 4, c = idx & 15;
-          if (P0 + c < m) o[(size_t)r * m + P0 + c] = (double)pan[dv.out_row[r] * LDP + c];
+          if (P0 + c < m) {
+            const double v = (double)pan[dv.out_row[r] * LDP + c];
+            const int64_t o = ((int64_t)e * m + r) * m + P0 + c;
+            if (a.in2out) a.in2out[o] = v;
+            if (a.b_i2o) a.b_i2o[o] = gemm::f2bf((float)v);
+            if (a.f_i2o) a.f_i2o[o] = (float)v;
+            if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+          }
         }
       }
       if (a.in2mean) {
@@ -401,9 +422,22 @@ size_t lu_smem_bytes(int npad, int nn) {
 
 }  // namespace
 
-el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,
-                             const double* h, const double* kappa, const double* sigma,
-                             double* in2out, double* in2sol, double* in2mean, double* rel_resid) {
+namespace {
+
+struct LocalOut {
+  double* in2out = nullptr;
+  double* in2sol = nullptr;
+  double* in2mean = nullptr;
+  uint16_t* b_i2o = nullptr;
+  uint16_t* b_i2s = nullptr;
+  float* f_i2o = nullptr;
+  float* f_i2s = nullptr;
+  uint16_t* pairs = nullptr;
+  const int32_t* emap = nullptr;
+};
+
+el_status run_local(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
+                    const double* kappa, const double* sigma, const LocalOut& out, double* rel_resid) {
   const DiscHost& dh = de->host;
   const int npad = (dh.n + NB - 1) / NB * NB;
   const int mpad = (dh.m + NB - 1) / NB * NB;
@@ -426,7 +460,7 @@ el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, 
   size_t inv_bytes = sizeof(double) * (size_t)slots * npan * 2 * NB * NB;
   el_status st = ensure_ws(ctx, ctx->ws_local, fac_bytes + inv_bytes);
   if (st) return st;
-  st = ensure_ws(ctx, ctx->ws_small, 4096);
+  st = ensure_ws(ctx, ctx->ws_small, 8192);
   if (st) return st;
   int* flags = reinterpret_cast<int*>(ctx->ws_small.ptr);
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, flags, 2, INT_MAX);
@@ -436,7 +470,9 @@ el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, 
   args.npad = npad;
   args.mpad = mpad;
   args.h = h; args.kappa = kappa; args.sigma = sigma;
-  args.in2out = in2out; args.in2sol = in2sol; args.in2mean = in2mean;
+  args.in2out = out.in2out; args.in2sol = out.in2sol; args.in2mean = out.in2mean;
+  args.b_i2o = out.b_i2o; args.b_i2s = out.b_i2s; args.pairs = out.pairs; args.emap = out.emap;
+  args.f_i2o = out.f_i2o; args.f_i2s = out.f_i2s;
   args.fac = reinterpret_cast<double*>(ctx->ws_local.ptr);
   args.inv = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ws_local.ptr) + fac_bytes);
   args.flags = flags;
@@ -461,6 +497,29 @@ el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, 
     return set_error(ctx, EL_ERR_SINGULAR, os.str());
   }
   return EL_OK;
+}
+
+}  // namespace
+
+el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,
+                             const double* h, const double* kappa, const double* sigma,
+                             double* in2out, double* in2sol, double* in2mean, double* rel_resid) {
+  LocalOut o;
+  o.in2out = in2out; o.in2sol = in2sol; o.in2mean = in2mean;
+  return run_local(ctx, de, precision, E, h, kappa, sigma, o, rel_resid);
+}
+
+el_status launch_local_solve_ex(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
+                                const double* kappa, const double* sigma, const int32_t* emap,
+                                void* o_i2o, void* o_i2s, int out_dtype, uint16_t* pairs) {
+  LocalOut o;
+  if (out_dtype == EL_F32) {
+    o.f_i2o = reinterpret_cast<float*>(o_i2o); o.f_i2s = reinterpret_cast<float*>(o_i2s);
+  } else {
+    o.b_i2o = reinterpret_cast<uint16_t*>(o_i2o); o.b_i2s = reinterpret_cast<uint16_t*>(o_i2s);
+  }
+  o.pairs = pairs; o.emap = emap;
+  return run_local(ctx, de, precision, E, h, kappa, sigma, o, nullptr);
 }
 
 }  // namespace el

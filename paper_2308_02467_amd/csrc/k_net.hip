@@ -1,0 +1,885 @@
+// Element network (Sec. 2.4.1 architecture, Sec. 2.4.2 / 3.1 training):
+// features, forward, MAE loss, backward, Adam, statistics, inference with
+// range check and plain-solver fallback.  All GEMMs run on the BF16 matrix
+// cores (gemm_bf16.h) with FP32 accumulation; master weights and optimizer
+// state are FP32.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+#include <vector>
+
+#include "el_internal.h"
+#include "gemm_bf16.h"
+
+struct el_net {
+  el_net_desc desc{};
+  int k0 = 0;                       // padded input width
+  int64_t n_params = 0;
+  std::vector<int64_t> w_off, b_off, in_dim, out_dim;   // per layer 0..depth
+  float* theta = nullptr;
+  float* grad = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  uint16_t* wbf = nullptr;          // bfloat16 copy of theta
+  float* feat_mean = nullptr;
+  float* feat_std = nullptr;
+  float* y_mean = nullptr;
+  float* y_std = nullptr;
+  double box[6] = {0, 0, 0, 0, 0, 0};
+  int64_t step = 0;
+  bool fitted = false;
+  int device = 0;
+  el::Workspace scratch;
+};
+
+namespace el {
+namespace {
+
+using gemm::bf2f;
+using gemm::f2bf;
+
+constexpr float kTauFloor = 1e-12f;
+
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void k_init_uniform(float* p, int64_t count, int64_t in_total, int64_t in_valid, float bound,
+                               uint64_t seed, int64_t offset) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  if (in_total > 0 && (i % in_total) >= in_valid) { p[i] = 0.f; return; }
+  uint64_t r = splitmix64(seed ^ splitmix64((uint64_t)(offset + i)));
+  double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);
+  p[i] = (float)((2.0 * u - 1.0) * bound);
+}
+
+__global__ void k_fill_f(float* p, int64_t n, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_to_bf16(const float* __restrict__ s, uint16_t* __restrict__ d, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = f2bf(s[i]);
+}
+
+__device__ inline float feature_value(int f, double h, double v) {
+  // f == 0: log10 h; else log10 max(h v / 2, floor)
+  if (f == 0) return (float)log10(h);
+  return (float)log10(fmax(0.5 * h * v, (double)kTauFloor));
+}
+
+struct Box {
+  double v[6];
+};
+
+// raw inputs (FP32 [B][n_in] or FP64 h/kappa/sigma) -> z-scored bfloat16 X0 [B][k0]
+__global__ void k_features(const float* __restrict__ x32, const double* __restrict__ h64,
+                           const double* __restrict__ kap64, const double* __restrict__ sig64, int64_t B,
+                           int n_in, int k0, const float* __restrict__ mean, const float* __restrict__ stdv,
+                           uint16_t* __restrict__ X0, Box box, uint8_t* __restrict__ in_range) {
+  const int64_t b = blockIdx.x;
+  if (b >= B) return;
+  const int nn = (n_in - 1) / 2;
+  __shared__ int ok;
+  if (threadIdx.x == 0) ok = 1;
+  __syncthreads();
+  double h = x32 ? (double)x32[b * n_in] : h64[b];
+  for (int f = threadIdx.x; f < k0; f += blockDim.x) {
+    uint16_t out = 0;
+    if (f < n_in) {
+      double v = 0.0;
+      bool inside;
+      if (f == 0) {
+        inside = h >= box.v[0] && h <= box.v[1];
+      } else if (f <= nn) {
+        v = x32 ? (double)x32[b * n_in + f] : kap64[b * nn + f - 1];
+        inside = v >= box.v[2] && v <= box.v[3];
+      } else {
+        v = x32 ? (double)x32[b * n_in + f] : sig64[b * nn + f - 1 - nn];
+        inside = v >= box.v[4] && v <= box.v[5];
+      }
+      if (!inside) ok = 0;
+      float z = (feature_value(f, h, v) - mean[f]) / stdv[f];
+      out = f2bf(z);
+    }
+    X0[b * k0 + f] = out;
+  }
+  __syncthreads();
+  if (in_range && threadIdx.x == 0) in_range[b] = (uint8_t)ok;
+}
+
+__device__ inline float act_f(int act, float z) {
+  if (act == EL_ACT_ELU) return z > 0.f ? z : expm1f(z);
+  return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
+}
+__device__ inline float act_df(int act, float z) {
+  if (act == EL_ACT_ELU) return z > 0.f ? 1.f : expf(z);
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// hidden layer epilogue: z = acc + b; Z (optional) = z; H = bf16(act(z))
+struct EpiHidden {
+  const float* bias;
+  float* Z;
+  uint16_t* H;
+  int64_t ld;
+  int act;
+  __device__ void operator()(int m, int n, float acc, int) {
+    float z = acc + bias[n];
+    if (Z) Z[(int64_t)m * ld + n] = z;
+    H[(int64_t)m * ld + n] = f2bf(act_f(act, z));
+  }
+  __device__ void flush() {}
+};
+
+// output layer, normalized FP32 (testing the forward pass)
+struct EpiOutNorm {
+  const float* bias;
+  float* Y;
+  int64_t ld;
+  __device__ void operator()(int m, int n, float acc, int) { Y[(int64_t)m * ld + n] = acc + bias[n]; }
+  __device__ void flush() {}
+};
+
+// output layer, de-normalized operators (bfloat16 or float32): n < mm -> in2out, else in2sol
+template <typename OutT>
+struct EpiOutOps {
+  const float* bias;
+  const float* ymean;
+  const float* ystd;
+  OutT* i2o;
+  OutT* i2s;
+  int64_t mm, nm;
+  __device__ static inline OutT cvt(float y) {
+    if constexpr (sizeof(OutT) == 2) return f2bf(y);
+    else return y;
+  }
+  __device__ void operator()(int e, int n, float acc, int) {
+    float y = (acc + bias[n]) * ystd[n] + ymean[n];
+    if (n < mm) {
+      if (i2o) i2o[(int64_t)e * mm + n] = cvt(y);
+    } else if (i2s) {
+      i2s[(int64_t)e * nm + (n - mm)] = cvt(y);
+    }
+  }
+  __device__ void flush() {}
+};
+
+// output layer in training: MAE against normalized targets; dY = sign(pred - target)
+struct EpiMAE {
+  const float* bias;
+  const uint16_t* y;
+  const float* ymean;
+  const float* ystd;
+  uint16_t* dY;
+  float* loss;
+  int64_t ld;
+  float local;
+  __device__ void operator()(int m, int n, float acc, int) {
+    const int64_t i = (int64_t)m * ld + n;
+    float pred = acc + bias[n];
+    float tgt = (bf2f(y[i]) - ymean[n]) / ystd[n];
+    float d = pred - tgt;
+    local += fabsf(d);
+    dY[i] = d > 0.f ? (uint16_t)0x3f80 : (d < 0.f ? (uint16_t)0xbf80 : (uint16_t)0);
+  }
+  __device__ void flush() {
+    float v = local;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss, v);
+  }
+};
+
+struct EpiF32 {
+  float* C;
+  int64_t ldc, zstride;
+  __device__ void operator()(int m, int n, float acc, int z) { C[z * zstride + (int64_t)m * ldc + n] = acc; }
+  __device__ void flush() {}
+};
+
+template <bool A_KC, bool B_KC, typename Epi>
+__global__ void __launch_bounds__(gemm::kThreads) k_mm(const uint16_t* __restrict__ A, int64_t lda,
+                                                        const uint16_t* __restrict__ B, int64_t ldb, int M, int N,
+                                                        int K, int k_split, Epi epi) {
+  using namespace gemm;
+  __shared__ __align__(16) uint16_t As[2][BM * PITCH];
+  __shared__ __align__(16) uint16_t Bs[2][BN * PITCH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kb = blockIdx.z * k_split;
+  const int ke = min(K, kb + k_split);
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int li = lane & 15, lk = (lane >> 4) * 8;
+  int buf = 0;
+  if (kb < ke) {
+    load_tile<A_KC>(A, lda, M, m0, kb, ke, As[0], tid);
+    load_tile<B_KC>(B, ldb, N, n0, kb, ke, Bs[0], tid);
+  }
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    if (k0 + BK < ke) {
+      load_tile<A_KC>(A, lda, M, m0, k0 + BK, ke, As[buf ^ 1], tid);
+      load_tile<B_KC>(B, ldb, N, n0, k0 + BK, ke, Bs[buf ^ 1], tid);
+    }
+    bf16x8 af[4], bfr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      af[i] = *reinterpret_cast<const bf16x8*>(As[buf] + (wm * 64 + 16 * i + li) * PITCH + lk);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      bfr[j] = *reinterpret_cast<const bf16x8*>(Bs[buf] + (wn * 64 + 16 * j + li) * PITCH + lk);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * 64 + 16 * j + li;
+        if (m < M && n < N) epi(m, n, acc[i][j][r], blockIdx.z);
+      }
+  epi.flush();
+}
+
+template <bool A_KC, bool B_KC, typename Epi>
+el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M, int64_t N,
+             int64_t K, int splits, Epi epi) {
+  if (M <= 0 || N <= 0) return EL_OK;
+  int64_t ks = (K + splits - 1) / splits;
+  ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
+  const int nz = (int)((K + ks - 1) / ks);
+  dim3 grid((unsigned)((N + gemm::BN - 1) / gemm::BN), (unsigned)((M + gemm::BM - 1) / gemm::BM), (unsigned)nz);
+  hipLaunchKernelGGL((k_mm<A_KC, B_KC, Epi>), grid, dim3(gemm::kThreads), 0, ctx->stream, A, lda, B, ldb, (int)M,
+                     (int)N, (int)K, (int)ks, epi);
+  return hip_check(ctx, hipGetLastError(), "launch k_mm");
+}
+
+// out[n] = sum_b X[b][n] (X bfloat16 or float)
+template <typename T>
+__global__ void k_colsum(const T* __restrict__ X, int64_t B, int64_t N, float* __restrict__ out) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float acc = 0.f;
+  for (int64_t b = 0; b < B; ++b) {
+    if constexpr (sizeof(T) == 2) acc += bf2f(X[b * N + n]);
+    else acc += X[b * N + n];
+  }
+  out[n] = acc;
+}
+
+// dZ = (sum_s P[s]) * act'(Z); writes FP32 and bfloat16
+__global__ void k_reduce_dact(const float* __restrict__ P, int S, int64_t count, const float* __restrict__ Z, int act,
+                              float* __restrict__ dZ, uint16_t* __restrict__ dZ16) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float acc = 0.f;
+  for (int s = 0; s < S; ++s) acc += P[s * count + i];
+  float g = acc * act_df(act, Z[i]);
+  dZ[i] = g;
+  dZ16[i] = f2bf(g);
+}
+
+__global__ void k_reduce_sum(const float* __restrict__ P, int S, int64_t count, float* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float acc = 0.f;
+  for (int s = 0; s < S; ++s) acc += P[s * count + i];
+  out[i] = acc;
+}
+
+__global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ wbf, int64_t n, float lr, float gscale,
+                       float bc1, float bc2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  float gi = g[i] * gscale;
+  float mi = b1 * m[i] + (1.f - b1) * gi;
+  float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  float t = th[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  th[i] = t;
+  wbf[i] = f2bf(t);
+}
+
+__global__ void k_loss_out(const float* acc, float scale, float* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = *acc * scale;
+}
+
+// feature statistics: one block per feature, FP64 accumulation over N samples
+__global__ void k_feat_stats(const float* __restrict__ x, int64_t N, int n_in, float* mean, float* stdv) {
+  const int f = blockIdx.x;
+  double s = 0.0, s2 = 0.0;
+  for (int64_t b = threadIdx.x; b < N; b += blockDim.x) {
+    double h = x[b * n_in];
+    double v = f == 0 ? 0.0 : x[b * n_in + f];
+    double z = feature_value(f, h, v);
+    s += z;
+    s2 += z * z;
+  }
+  __shared__ double r1[256], r2[256];
+  r1[threadIdx.x] = s;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) { r1[threadIdx.x] += r1[threadIdx.x + o]; r2[threadIdx.x] += r2[threadIdx.x + o]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double mu = r1[0] / N;
+    double var = fmax(r2[0] / N - mu * mu, 0.0);
+    mean[f] = (float)mu;
+    stdv[f] = (float)fmax(sqrt(var), 1e-6);
+  }
+}
+
+// min / max of raw h (f == 0), kappa (1..nn), sigma (nn+1..2nn): block 0..2
+__global__ void k_box(const float* __restrict__ x, int64_t N, int n_in, double* box) {
+  const int which = blockIdx.x;
+  const int nn = (n_in - 1) / 2;
+  const int f0 = which == 0 ? 0 : (which == 1 ? 1 : 1 + nn);
+  const int f1 = which == 0 ? 1 : (which == 1 ? 1 + nn : n_in);
+  double lo = INFINITY, hi = -INFINITY;
+  for (int64_t i = threadIdx.x; i < N * (f1 - f0); i += blockDim.x) {
+    int64_t b = i / (f1 - f0);
+    int f = f0 + (int)(i % (f1 - f0));
+    double v = x[b * n_in + f];
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+  __shared__ double rl[256], rh[256];
+  rl[threadIdx.x] = lo;
+  rh[threadIdx.x] = hi;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      rl[threadIdx.x] = fmin(rl[threadIdx.x], rl[threadIdx.x + o]);
+      rh[threadIdx.x] = fmax(rh[threadIdx.x], rh[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { box[2 * which] = rl[0]; box[2 * which + 1] = rh[0]; }
+}
+
+// per-output mean / std of bfloat16 targets (FP64 accumulation)
+__global__ void k_y_stats(const uint16_t* __restrict__ y, int64_t N, int64_t n_out, float* mean, float* stdv) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_out) return;
+  double s = 0.0, s2 = 0.0;
+  for (int64_t b = 0; b < N; ++b) {
+    double v = bf2f(y[b * n_out + c]);
+    s += v;
+    s2 += v * v;
+  }
+  double mu = s / N;
+  double var = fmax(s2 / N - mu * mu, 0.0);
+  mean[c] = (float)mu;
+  stdv[c] = (float)fmax(sqrt(var), 1e-6 * fmax(fabs(mu), 1e-30) + 1e-12);
+}
+
+__global__ void k_fill_int32(int* p, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_count_out(const uint8_t* in_range, int64_t E, int32_t* idx, int* count) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  if (!in_range[e]) {
+    int pos = atomicAdd(count, 1);
+    idx[pos] = (int32_t)e;
+  }
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+int64_t layer_count(const el_net* net) { return net->desc.depth + 1; }
+
+void layout(el_net* net) {
+  const el_net_desc& d = net->desc;
+  net->k0 = (d.n_in + 31) / 32 * 32;
+  const int L = d.depth + 1;
+  net->w_off.resize(L); net->b_off.resize(L); net->in_dim.resize(L); net->out_dim.resize(L);
+  int64_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    net->in_dim[l] = l == 0 ? net->k0 : d.width;
+    net->out_dim[l] = l == d.depth ? d.n_out : d.width;
+    net->w_off[l] = off;
+    off += net->in_dim[l] * net->out_dim[l];
+    net->b_off[l] = off;
+    off += net->out_dim[l];
+    off = (off + 63) / 64 * 64;   // keep every W_l 128-byte aligned
+  }
+  net->n_params = off;
+}
+
+el_status alloc_net(el_ctx* ctx, el_net* net) {
+  const int64_t P = net->n_params;
+  const int64_t nin = net->desc.n_in, nout = net->desc.n_out;
+  void* p;
+  size_t bytes = (size_t)P * (4 * 4 + 2) + (size_t)(2 * nin + 2 * nout) * 4 + 1024;
+  el_status st = hip_check(ctx, hipMalloc(&p, bytes), "hipMalloc(network)");
+  if (st) return st;
+  char* c = reinterpret_cast<char*>(p);
+  auto take = [&](size_t b) { char* r = c; c += (b + 255) / 256 * 256; return r; };
+  net->theta = reinterpret_cast<float*>(take(P * 4));
+  net->grad = reinterpret_cast<float*>(take(P * 4));
+  net->adam_m = reinterpret_cast<float*>(take(P * 4));
+  net->adam_v = reinterpret_cast<float*>(take(P * 4));
+  net->wbf = reinterpret_cast<uint16_t*>(take(P * 2));
+  net->feat_mean = reinterpret_cast<float*>(take(nin * 4));
+  net->feat_std = reinterpret_cast<float*>(take(nin * 4));
+  net->y_mean = reinterpret_cast<float*>(take(nout * 4));
+  net->y_std = reinterpret_cast<float*>(take(nout * 4));
+  return EL_OK;
+}
+
+bool desc_ok(const el_net_desc& d) {
+  return d.n_in >= 3 && d.n_in % 2 == 1 && d.width >= 16 && d.width % 8 == 0 && d.depth >= 1 && d.depth <= 16 &&
+         d.n_out >= 1 && d.n_out % 8 == 0 && (d.act == EL_ACT_GELU || d.act == EL_ACT_ELU);
+}
+
+// scratch layout for a batch of B rows
+struct Scratch {
+  uint16_t* X0;      // [B][k0]
+  float* Z;          // [depth][B][width]
+  uint16_t* H;       // [depth][B][width]
+  uint16_t* dY;      // [B][n_out] (training only)
+  float* part;       // split-K partials
+  float* dZ;         // [B][width]
+  uint16_t* dZ16;    // [B][width]
+  float* loss;       // [1]
+  int64_t part_elems;
+};
+
+constexpr int kSplitOut = 32;   // split-K of dY * W_out (K = n_out)
+constexpr int kSplitW = 8;      // split-K of the hidden dW GEMMs (K = batch)
+
+el_status get_scratch(el_ctx* ctx, el_net* net, int64_t B, bool train, Scratch& s) {
+  const int64_t W = net->desc.width, D = net->desc.depth, nout = net->desc.n_out;
+  int64_t part = std::max<int64_t>((int64_t)kSplitOut * B * W, (int64_t)kSplitW * W * std::max<int64_t>(W, net->k0));
+  size_t need = 0;
+  auto add = [&](size_t b) { size_t r = need; need += (b + 255) / 256 * 256; return r; };
+  size_t oX0 = add((size_t)B * net->k0 * 2), oZ = add((size_t)D * B * W * 4), oH = add((size_t)D * B * W * 2);
+  size_t odY = train ? add((size_t)B * nout * 2) : 0;
+  size_t opart = train ? add((size_t)part * 4) : 0;
+  size_t odZ = train ? add((size_t)B * W * 4) : 0, odZ16 = train ? add((size_t)B * W * 2) : 0;
+  size_t oloss = add(256);
+  if (net->scratch.bytes < need) {
+    if (net->scratch.ptr) {
+      hipStreamSynchronize(ctx->stream);
+      hipFree(net->scratch.ptr);
+      net->scratch.ptr = nullptr;
+      net->scratch.bytes = 0;
+    }
+    el_status st = hip_check(ctx, hipMalloc(&net->scratch.ptr, need), "hipMalloc(network scratch)");
+    if (st) return st;
+    net->scratch.bytes = need;
+  }
+  char* b = reinterpret_cast<char*>(net->scratch.ptr);
+  s.X0 = reinterpret_cast<uint16_t*>(b + oX0);
+  s.Z = reinterpret_cast<float*>(b + oZ);
+  s.H = reinterpret_cast<uint16_t*>(b + oH);
+  s.dY = train ? reinterpret_cast<uint16_t*>(b + odY) : nullptr;
+  s.part = train ? reinterpret_cast<float*>(b + opart) : nullptr;
+  s.dZ = train ? reinterpret_cast<float*>(b + odZ) : nullptr;
+  s.dZ16 = train ? reinterpret_cast<uint16_t*>(b + odZ16) : nullptr;
+  s.loss = reinterpret_cast<float*>(b + oloss);
+  s.part_elems = part;
+  return EL_OK;
+}
+
+Box make_box(const el_net* net) {
+  Box b;
+  for (int i = 0; i < 6; ++i) b.v[i] = net->box[i];
+  return b;
+}
+
+// hidden layers: X0 -> H[depth-1]; Z saved when save_z
+el_status forward_hidden(el_ctx* ctx, el_net* net, int64_t B, const Scratch& s, bool save_z) {
+  const int64_t W = net->desc.width;
+  for (int l = 0; l < net->desc.depth; ++l) {
+    const uint16_t* X = l == 0 ? s.X0 : s.H + (size_t)(l - 1) * B * W;
+    const int64_t in = net->in_dim[l];
+    EpiHidden epi{net->theta + net->b_off[l], save_z ? s.Z + (size_t)l * B * W : nullptr, s.H + (size_t)l * B * W, W,
+                  net->desc.act};
+    el_status st = mm<true, true>(ctx, X, in, net->wbf + net->w_off[l], in, B, W, in, 1, epi);
+    if (st) return st;
+  }
+  return EL_OK;
+}
+
+}  // namespace
+
+el_status launch_local_solve_ex(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
+                                const double* kappa, const double* sigma, const int32_t* emap,
+                                void* o_i2o, void* o_i2s, int out_dtype, uint16_t* pairs);
+
+}  // namespace el
+
+using namespace el;
+
+extern "C" {
+
+el_status el_net_create(el_ctx* ctx, const el_net_desc* desc, el_net** out) {
+  if (!ctx || !desc || !out) return EL_ERR_ARG;
+  *out = nullptr;
+  if (!desc_ok(*desc)) return set_error(ctx, EL_ERR_ARG, "el_net_create: bad network description");
+  hipSetDevice(ctx->device);
+  el_net* net = new el_net();
+  net->desc = *desc;
+  net->device = ctx->device;
+  layout(net);
+  el_status st = alloc_net(ctx, net);
+  if (st) { delete net; return st; }
+  for (int l = 0; l <= desc->depth; ++l) {
+    const int64_t fan_in = l == 0 ? desc->n_in : desc->width;
+    const float bound = (float)(1.0 / std::sqrt((double)fan_in));
+    const int64_t nw = net->in_dim[l] * net->out_dim[l];
+    hipLaunchKernelGGL(k_init_uniform, dim3(nblk(nw)), dim3(256), 0, ctx->stream, net->theta + net->w_off[l], nw,
+                       net->in_dim[l], (int64_t)(l == 0 ? desc->n_in : desc->width), bound, desc->seed,
+                       net->w_off[l]);
+    hipLaunchKernelGGL(k_init_uniform, dim3(nblk(net->out_dim[l])), dim3(256), 0, ctx->stream,
+                       net->theta + net->b_off[l], net->out_dim[l], (int64_t)0, (int64_t)0, bound, desc->seed,
+                       net->b_off[l]);
+  }
+  const int64_t P = net->n_params;
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(P)), dim3(256), 0, ctx->stream, net->adam_m, P, 0.f);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(P)), dim3(256), 0, ctx->stream, net->adam_v, P, 0.f);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(P)), dim3(256), 0, ctx->stream, net->grad, P, 0.f);
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(P)), dim3(256), 0, ctx->stream, net->theta, net->wbf, P);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(desc->n_in)), dim3(256), 0, ctx->stream, net->feat_mean,
+                     (int64_t)desc->n_in, 0.f);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(desc->n_in)), dim3(256), 0, ctx->stream, net->feat_std,
+                     (int64_t)desc->n_in, 1.f);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(desc->n_out)), dim3(256), 0, ctx->stream, net->y_mean, desc->n_out, 0.f);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(desc->n_out)), dim3(256), 0, ctx->stream, net->y_std, desc->n_out, 1.f);
+  net->box[0] = net->box[2] = net->box[4] = 0.0;
+  net->box[1] = net->box[3] = net->box[5] = 0.0;
+  st = hip_check(ctx, hipGetLastError(), "el_net_create init");
+  if (st) { el_net_destroy(net); return st; }
+  *out = net;
+  return EL_OK;
+}
+
+el_status el_net_destroy(el_net* net) {
+  if (!net) return EL_OK;
+  hipSetDevice(net->device);
+  hipDeviceSynchronize();
+  hipFree(net->theta);
+  hipFree(net->scratch.ptr);
+  delete net;
+  return EL_OK;
+}
+
+el_status el_net_num_params(const el_net* net, int64_t* n) {
+  if (!net || !n) return EL_ERR_ARG;
+  *n = net->n_params;
+  return EL_OK;
+}
+
+static const size_t kHeader = 112;
+
+el_status el_net_save(el_ctx* ctx, const el_net* net, void* host_buf, size_t* bytes) {
+  if (!ctx || !net || !bytes) return EL_ERR_ARG;
+  const int64_t P = net->n_params, nin = net->desc.n_in, nout = net->desc.n_out;
+  const size_t need = kHeader + 4 * (size_t)(2 * nin + 2 * nout + 3 * P);
+  if (!host_buf) { *bytes = need; return EL_OK; }
+  if (*bytes < need) return set_error(ctx, EL_ERR_ARG, "el_net_save: buffer too small");
+  char* b = reinterpret_cast<char*>(host_buf);
+  std::memset(b, 0, kHeader);
+  std::memcpy(b, "ELNET01", 8);
+  int32_t hi[6] = {net->desc.n_in, net->desc.width, net->desc.depth, net->desc.act, net->k0, 0};
+  std::memcpy(b + 8, hi, sizeof hi);
+  int64_t hl[3] = {nout, net->step, P};
+  std::memcpy(b + 32, hl, sizeof hl);
+  std::memcpy(b + 56, net->box, sizeof net->box);
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  char* o = b + kHeader;
+  auto get = [&](const float* src, int64_t cnt) {
+    hipError_t e = hipMemcpy(o, src, cnt * 4, hipMemcpyDeviceToHost);
+    o += cnt * 4;
+    return e;
+  };
+  hipError_t e = get(net->feat_mean, nin);
+  if (e == hipSuccess) e = get(net->feat_std, nin);
+  if (e == hipSuccess) e = get(net->y_mean, nout);
+  if (e == hipSuccess) e = get(net->y_std, nout);
+  if (e == hipSuccess) e = get(net->theta, P);
+  if (e == hipSuccess) e = get(net->adam_m, P);
+  if (e == hipSuccess) e = get(net->adam_v, P);
+  if (e != hipSuccess) return hip_check(ctx, e, "el_net_save");
+  *bytes = need;
+  return EL_OK;
+}
+
+el_status el_net_load(el_ctx* ctx, const void* host_buf, size_t bytes, el_net** out) {
+  if (!ctx || !host_buf || !out) return EL_ERR_ARG;
+  *out = nullptr;
+  const char* b = reinterpret_cast<const char*>(host_buf);
+  if (bytes < kHeader || std::memcmp(b, "ELNET01", 8) != 0) return set_error(ctx, EL_ERR_ARG, "el_net_load: bad magic");
+  int32_t hi[6];
+  int64_t hl[3];
+  std::memcpy(hi, b + 8, sizeof hi);
+  std::memcpy(hl, b + 32, sizeof hl);
+  el_net_desc d{};
+  d.n_in = hi[0]; d.width = hi[1]; d.depth = hi[2]; d.act = hi[3]; d.n_out = hl[0]; d.seed = 0;
+  if (!desc_ok(d)) return set_error(ctx, EL_ERR_ARG, "el_net_load: bad header");
+  hipSetDevice(ctx->device);
+  el_net* net = new el_net();
+  net->desc = d;
+  net->device = ctx->device;
+  layout(net);
+  if (net->k0 != hi[4] || net->n_params != hl[2]) { delete net; return set_error(ctx, EL_ERR_ARG, "el_net_load: layout mismatch"); }
+  const int64_t P = net->n_params, nin = d.n_in, nout = d.n_out;
+  if (bytes < kHeader + 4 * (size_t)(2 * nin + 2 * nout + 3 * P)) {
+    delete net;
+    return set_error(ctx, EL_ERR_ARG, "el_net_load: truncated blob");
+  }
+  el_status st = alloc_net(ctx, net);
+  if (st) { delete net; return st; }
+  net->step = hl[1];
+  std::memcpy(net->box, b + 56, sizeof net->box);
+  net->fitted = true;
+  const char* o = b + kHeader;
+  auto put = [&](float* dst, int64_t cnt) {
+    hipError_t e = hipMemcpy(dst, o, cnt * 4, hipMemcpyHostToDevice);
+    o += cnt * 4;
+    return e;
+  };
+  hipError_t e = put(net->feat_mean, nin);
+  if (e == hipSuccess) e = put(net->feat_std, nin);
+  if (e == hipSuccess) e = put(net->y_mean, nout);
+  if (e == hipSuccess) e = put(net->y_std, nout);
+  if (e == hipSuccess) e = put(net->theta, P);
+  if (e == hipSuccess) e = put(net->adam_m, P);
+  if (e == hipSuccess) e = put(net->adam_v, P);
+  if (e != hipSuccess) { el_net_destroy(net); return hip_check(ctx, e, "el_net_load"); }
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(P)), dim3(256), 0, ctx->stream, net->theta, net->wbf, P);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(P)), dim3(256), 0, ctx->stream, net->grad, P, 0.f);
+  *out = net;
+  return hip_check(ctx, hipGetLastError(), "el_net_load");
+}
+
+el_status el_net_params(el_ctx* ctx, const el_net* net, int which, float* dst) {
+  if (!ctx || !net || !dst || which < 0 || which > 3) return EL_ERR_ARG;
+  const float* src = which == 0 ? net->theta : which == 1 ? net->grad : which == 2 ? net->adam_m : net->adam_v;
+  return hip_check(ctx, hipMemcpyAsync(dst, src, net->n_params * 4, hipMemcpyDeviceToDevice, ctx->stream),
+                   "el_net_params");
+}
+
+el_status el_net_fit_normalization(el_ctx* ctx, el_net* net, int64_t N, const float* x, const uint16_t* y) {
+  if (!ctx || !net || N <= 0 || !x || !y) return set_error(ctx, EL_ERR_ARG, "el_net_fit_normalization: bad argument");
+  hipSetDevice(ctx->device);
+  const int nin = net->desc.n_in;
+  hipLaunchKernelGGL(k_feat_stats, dim3(nin), dim3(256), 0, ctx->stream, x, N, nin, net->feat_mean, net->feat_std);
+  hipLaunchKernelGGL(k_y_stats, dim3(nblk(net->desc.n_out)), dim3(256), 0, ctx->stream, y, N, net->desc.n_out,
+                     net->y_mean, net->y_std);
+  el_status st = ensure_ws(ctx, ctx->ws_small, 4096 + 1024);
+  if (st) return st;
+  double* dbox = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ws_small.ptr) + 4096);
+  hipLaunchKernelGGL(k_box, dim3(3), dim3(256), 0, ctx->stream, x, N, nin, dbox);
+  hipError_t e = hipMemcpyAsync(net->box, dbox, sizeof net->box, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_check(ctx, e, "el_net_fit_normalization");
+  net->fitted = true;
+  return EL_OK;
+}
+
+el_status el_make_pairs(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa,
+                        const double* sigma, uint16_t* y) {
+  if (!ctx) return EL_ERR_ARG;
+  if (E <= 0 || !h || !kappa || !sigma || !y) return set_error(ctx, EL_ERR_ARG, "el_make_pairs: bad argument");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_local_solve_ex(ctx, de, EL_FP64, E, h, kappa, sigma, nullptr, nullptr, nullptr, EL_BF16, y);
+}
+
+el_status el_net_forward(el_ctx* ctx, const el_net* cnet, int64_t B, const float* x, float* y_norm) {
+  if (!ctx || !cnet || B <= 0 || !x || !y_norm) return set_error(ctx, EL_ERR_ARG, "el_net_forward: bad argument");
+  el_net* net = const_cast<el_net*>(cnet);
+  hipSetDevice(ctx->device);
+  Scratch s;
+  el_status st = get_scratch(ctx, net, B, false, s);
+  if (st) return st;
+  Box open{{-1e300, 1e300, -1e300, 1e300, -1e300, 1e300}};
+  hipLaunchKernelGGL(k_features, dim3((unsigned)B), dim3(128), 0, ctx->stream, x, nullptr, nullptr, nullptr, B,
+                     net->desc.n_in, net->k0, net->feat_mean, net->feat_std, s.X0, open, nullptr);
+  st = forward_hidden(ctx, net, B, s, false);
+  if (st) return st;
+  const int D = net->desc.depth;
+  const int64_t W = net->desc.width;
+  EpiOutNorm epi{net->theta + net->b_off[D], y_norm, net->desc.n_out};
+  return mm<true, true>(ctx, s.H + (size_t)(D - 1) * B * W, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1,
+                        epi);
+}
+
+el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, const uint16_t* y, float lr,
+                        float* loss) {
+  if (!ctx || !net || B <= 0 || !x || !y) return set_error(ctx, EL_ERR_ARG, "el_train_step: bad argument");
+  if (!(lr >= 0.f)) return set_error(ctx, EL_ERR_ARG, "el_train_step: lr must be >= 0");
+  hipSetDevice(ctx->device);
+  Scratch s;
+  el_status st = get_scratch(ctx, net, B, true, s);
+  if (st) return st;
+  hipStream_t str = ctx->stream;
+  const int D = net->desc.depth;
+  const int64_t W = net->desc.width, nout = net->desc.n_out;
+  Box open{{-1e300, 1e300, -1e300, 1e300, -1e300, 1e300}};
+  hipLaunchKernelGGL(k_features, dim3((unsigned)B), dim3(128), 0, str, x, nullptr, nullptr, nullptr, B,
+                     net->desc.n_in, net->k0, net->feat_mean, net->feat_std, s.X0, open, nullptr);
+  st = forward_hidden(ctx, net, B, s, true);
+  if (st) return st;
+  hipLaunchKernelGGL(k_fill_f, dim3(1), dim3(64), 0, str, s.loss, (int64_t)1, 0.f);
+  const uint16_t* Hlast = s.H + (size_t)(D - 1) * B * W;
+  EpiMAE mae{net->theta + net->b_off[D], y, net->y_mean, net->y_std, s.dY, s.loss, nout, 0.f};
+  st = mm<true, true>(ctx, Hlast, W, net->wbf + net->w_off[D], W, B, nout, W, 1, mae);
+  if (st) return st;
+  // output layer gradients
+  hipLaunchKernelGGL(k_colsum<uint16_t>, dim3(nblk(nout)), dim3(256), 0, str, s.dY, B, nout, net->grad + net->b_off[D]);
+  st = mm<false, false>(ctx, s.dY, nout, Hlast, W, nout, W, B, 1, EpiF32{net->grad + net->w_off[D], W, 0});
+  if (st) return st;
+  st = mm<true, false>(ctx, s.dY, nout, net->wbf + net->w_off[D], W, B, W, nout, kSplitOut,
+                       EpiF32{s.part, W, B * W});
+  if (st) return st;
+  {
+    int64_t ks = (nout + kSplitOut - 1) / kSplitOut;
+    ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
+    const int S = (int)((nout + ks - 1) / ks);
+    hipLaunchKernelGGL(k_reduce_dact, dim3(nblk(B * W)), dim3(256), 0, str, s.part, S, B * W,
+                       s.Z + (size_t)(D - 1) * B * W, net->desc.act, s.dZ, s.dZ16);
+  }
+  for (int l = D - 1; l >= 0; --l) {
+    const int64_t in = net->in_dim[l];
+    const uint16_t* X = l == 0 ? s.X0 : s.H + (size_t)(l - 1) * B * W;
+    hipLaunchKernelGGL(k_colsum<float>, dim3(nblk(W)), dim3(256), 0, str, s.dZ, B, W, net->grad + net->b_off[l]);
+    st = mm<false, false>(ctx, s.dZ16, W, X, in, W, in, B, kSplitW, EpiF32{s.part, in, W * in});
+    if (st) return st;
+    {
+      int64_t ks = (B + kSplitW - 1) / kSplitW;
+      ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
+      const int S = (int)((B + ks - 1) / ks);
+      hipLaunchKernelGGL(k_reduce_sum, dim3(nblk(W * in)), dim3(256), 0, str, s.part, S, W * in,
+                         net->grad + net->w_off[l]);
+    }
+    if (l > 0) {
+      st = mm<true, false>(ctx, s.dZ16, W, net->wbf + net->w_off[l], in, B, in, W, 1, EpiF32{s.part, in, 0});
+      if (st) return st;
+      hipLaunchKernelGGL(k_reduce_dact, dim3(nblk(B * W)), dim3(256), 0, str, s.part, 1, B * W,
+                         s.Z + (size_t)(l - 1) * B * W, net->desc.act, s.dZ, s.dZ16);
+    }
+  }
+  net->step += 1;
+  const double t = (double)net->step;
+  const float bc1 = (float)(1.0 - std::pow(0.9, t)), bc2 = (float)(1.0 - std::pow(0.999, t));
+  const float gscale = (float)(1.0 / ((double)B * (double)nout));
+  hipLaunchKernelGGL(k_adam, dim3(nblk(net->n_params)), dim3(256), 0, str, net->theta, net->grad, net->adam_m,
+                     net->adam_v, net->wbf, net->n_params, lr, gscale, bc1, bc2);
+  if (loss) hipLaunchKernelGGL(k_loss_out, dim3(1), dim3(64), 0, str, s.loss, gscale, loss);
+  return hip_check(ctx, hipGetLastError(), "el_train_step");
+}
+
+el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const double* h, const double* kappa,
+                   const double* sigma, void* in2out, void* in2sol, int out_dtype, uint8_t* in_range, int fallback,
+                   int precision, int64_t* n_fallback_host) {
+  if (!ctx || !cnet) return EL_ERR_ARG;
+  if (E <= 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer: bad argument");
+  if (out_dtype != EL_BF16 && out_dtype != EL_F32) return set_error(ctx, EL_ERR_ARG, "el_infer: out_dtype");
+  const size_t osz = out_dtype == EL_F32 ? 4 : 2;
+  el_net* net = const_cast<el_net*>(cnet);
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  const DiscHost& dh = de->host;
+  const int64_t mm_ = (int64_t)dh.m * dh.m, nm = (int64_t)dh.n * dh.m;
+  if (net->desc.n_out != mm_ + nm || net->desc.n_in != 1 + 2 * dh.nn)
+    return set_error(ctx, EL_ERR_ARG, "el_infer: network sizes do not match the discretization");
+  if (!net->fitted) return set_error(ctx, EL_ERR_STATE, "el_infer: network has no training statistics");
+  const int D = net->desc.depth;
+  const int64_t W = net->desc.width;
+  // chunk the batch so that scratch stays bounded
+  const int64_t chunk = 16384;
+  el_status st2 = ensure_ws(ctx, ctx->ws_small, 4096 + 1024);
+  if (st2) return st2;
+  int* dcount = reinterpret_cast<int*>(reinterpret_cast<char*>(ctx->ws_small.ptr) + 4096 + 512);
+  uint8_t* mask = in_range;
+  void* mask_alloc = nullptr;
+  if (!mask) {
+    st = hip_check(ctx, hipMalloc(&mask_alloc, E), "hipMalloc(mask)");
+    if (st) return st;
+    mask = reinterpret_cast<uint8_t*>(mask_alloc);
+  }
+  for (int64_t e0 = 0; e0 < E; e0 += chunk) {
+    const int64_t B = std::min(chunk, E - e0);
+    Scratch s;
+    st = get_scratch(ctx, net, B, false, s);
+    if (st) break;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)B), dim3(128), 0, ctx->stream, nullptr, h + e0,
+                       kappa + e0 * dh.nn, sigma + e0 * dh.nn, B, net->desc.n_in, net->k0, net->feat_mean,
+                       net->feat_std, s.X0, make_box(net), mask + e0);
+    st = forward_hidden(ctx, net, B, s, false);
+    if (st) break;
+    char* po = in2out ? reinterpret_cast<char*>(in2out) + (size_t)e0 * mm_ * osz : nullptr;
+    char* ps = in2sol ? reinterpret_cast<char*>(in2sol) + (size_t)e0 * nm * osz : nullptr;
+    const uint16_t* Hl = s.H + (size_t)(D - 1) * B * W;
+    if (out_dtype == EL_F32) {
+      EpiOutOps<float> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<float*>(po),
+                           reinterpret_cast<float*>(ps), mm_, nm};
+      st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi);
+    } else {
+      EpiOutOps<uint16_t> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<uint16_t*>(po),
+                              reinterpret_cast<uint16_t*>(ps), mm_, nm};
+      st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi);
+    }
+    if (st) break;
+  }
+  int64_t nfb = 0;
+  if (!st) {
+    // count and compact the elements outside the training box
+    void* idx = nullptr;
+    st = hip_check(ctx, hipMalloc(&idx, sizeof(int32_t) * E), "hipMalloc(fallback index)");
+    if (!st) {
+      hipLaunchKernelGGL(k_fill_int32, dim3(1), dim3(64), 0, ctx->stream, dcount, 1, 0);
+      hipLaunchKernelGGL(k_count_out, dim3(nblk(E)), dim3(256), 0, ctx->stream, mask, E,
+                         reinterpret_cast<int32_t*>(idx), dcount);
+      int hc = 0;
+      hipError_t e = hipMemcpyAsync(&hc, dcount, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      st = hip_check(ctx, e, "el_infer count");
+      nfb = hc;
+      if (!st && fallback && hc > 0)
+        st = launch_local_solve_ex(ctx, de, precision, hc, h, kappa, sigma, reinterpret_cast<int32_t*>(idx), in2out,
+                                   in2sol, out_dtype, nullptr);
+      hipStreamSynchronize(ctx->stream);
+      hipFree(idx);
+    }
+  }
+  if (mask_alloc) { hipStreamSynchronize(ctx->stream); hipFree(mask_alloc); }
+  if (n_fallback_host) *n_fallback_host = nfb;
+  return st;
+}
+
+}  // extern "C"

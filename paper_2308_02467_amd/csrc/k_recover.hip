@@ -43,6 +43,20 @@ __device__ inline double row_dot<double>(const double* __restrict__ row, const d
 }
 
 template <>
+__device__ inline double row_dot<float>(const float* __restrict__ row, const double* tin, int m, int gl) {
+  double acc = 0.0;
+  for (int c = 4 * gl; c < m; c += 32) {
+    if (c + 4 <= m) {
+      float4 v = *reinterpret_cast<const float4*>(row + c);
+      acc += (double)v.x * tin[c] + (double)v.y * tin[c + 1] + (double)v.z * tin[c + 2] + (double)v.w * tin[c + 3];
+    } else {
+      for (int cc = c; cc < m; ++cc) acc += (double)row[cc] * tin[cc];
+    }
+  }
+  return acc;
+}
+
+template <>
 __device__ inline double row_dot<uint16_t>(const uint16_t* __restrict__ row, const double* tin, int m, int gl) {
   double acc = 0.0;
   for (int c = 8 * gl; c < m; c += 64) {
@@ -148,6 +162,9 @@ el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh
   if (op_dtype == EL_F64)
     hipLaunchKernelGGL(k_recover<double>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
                        reinterpret_cast<const double*>(in2sol), dh.n, 0, trace, u, mean);
+  else if (op_dtype == EL_F32)
+    hipLaunchKernelGGL(k_recover<float>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const float*>(in2sol), dh.n, 0, trace, u, mean);
   else
     hipLaunchKernelGGL(k_recover<uint16_t>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
                        reinterpret_cast<const uint16_t*>(in2sol), dh.n, 0, trace, u, mean);
@@ -163,6 +180,9 @@ el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh&
   if (op_dtype == EL_F64)
     hipLaunchKernelGGL(k_recover<double>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
                        reinterpret_cast<const double*>(in2mean), dh.nn, 1, trace, nullptr, mean);
+  else if (op_dtype == EL_F32)
+    hipLaunchKernelGGL(k_recover<float>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const float*>(in2mean), dh.nn, 1, trace, nullptr, mean);
   else
     hipLaunchKernelGGL(k_recover<uint16_t>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
                        reinterpret_cast<const uint16_t*>(in2mean), dh.nn, 1, trace, nullptr, mean);

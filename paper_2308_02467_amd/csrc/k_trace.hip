@@ -30,7 +30,7 @@ constexpr int kMVThreads = 256;
 constexpr int kVec = 8;                       // values per thread in vector kernels
 constexpr int kVThreads = 256;
 constexpr int kChunk = kVThreads * kVec;      // elements per block
-constexpr int kMaxCnt = 130;
+constexpr int kMaxCnt = 258;
 
 struct MeshDev {
   int n_x, n_y, n_vf;
@@ -109,6 +109,20 @@ __device__ inline double row_dot<double>(const double* __restrict__ row, const d
   for (int c = 2 * gl; c < m; c += 16) {
     double2 v = *reinterpret_cast<const double2*>(row + c);
     acc += v.x * tin[c] + v.y * tin[c + 1];
+  }
+  return acc;
+}
+
+template <>
+__device__ inline double row_dot<float>(const float* __restrict__ row, const double* tin, int m, int gl) {
+  double acc = 0.0;
+  for (int c = 4 * gl; c < m; c += 32) {
+    if (c + 4 <= m) {
+      float4 v = *reinterpret_cast<const float4*>(row + c);
+      acc += (double)v.x * tin[c] + (double)v.y * tin[c + 1] + (double)v.z * tin[c + 2] + (double)v.w * tin[c + 3];
+    } else {
+      for (int cc = c; cc < m; ++cc) acc += (double)row[cc] * tin[cc];
+    }
   }
   return acc;
 }
@@ -327,6 +341,9 @@ el_status launch_trace_matvec(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh&
   if (op_dtype == EL_F64)
     hipLaunchKernelGGL(k_matvec<double>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,
                        reinterpret_cast<const double*>(in2out), x, y);
+  else if (op_dtype == EL_F32)
+    hipLaunchKernelGGL(k_matvec<float>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const float*>(in2out), x, y);
   else
     hipLaunchKernelGGL(k_matvec<uint16_t>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,
                        reinterpret_cast<const uint16_t*>(in2out), x, y);

@@ -26,6 +26,7 @@ EL_FP64 = 0
 EL_FP32_IR = 1
 EL_F64 = 0
 EL_BF16 = 1
+EL_F32 = 2
 
 _ERRNAMES = {EL_ERR_ARG: "EL_ERR_ARG", EL_ERR_HIP: "EL_ERR_HIP", EL_ERR_SINGULAR: "EL_ERR_SINGULAR",
              EL_ERR_NONFINITE: "EL_ERR_NONFINITE", EL_ERR_NOMEM: "EL_ERR_NOMEM"}
@@ -44,6 +45,15 @@ class el_disc(ctypes.Structure):
 class el_mesh(ctypes.Structure):
     _fields_ = [("n_x", ctypes.c_int), ("n_y", ctypes.c_int), ("x0", ctypes.c_double),
                 ("y0", ctypes.c_double), ("h", ctypes.c_double)]
+
+
+class el_net_desc(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int), ("width", ctypes.c_int), ("depth", ctypes.c_int), ("act", ctypes.c_int),
+                ("n_out", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+
+
+EL_ACT_GELU = 0
+EL_ACT_ELU = 1
 
 
 class el_gmres_opts(ctypes.Structure):
@@ -84,6 +94,22 @@ _SIGS = {
                         ctypes.c_void_p],
     "el_mean_l2": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                    ctypes.POINTER(ctypes.c_double)],
+    "el_net_create": [ctypes.c_void_p, ctypes.POINTER(el_net_desc), ctypes.POINTER(ctypes.c_void_p)],
+    "el_net_destroy": [ctypes.c_void_p],
+    "el_net_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "el_net_load": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
+    "el_net_fit_normalization": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                 ctypes.c_void_p],
+    "el_net_params": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
+    "el_net_num_params": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
+    "el_make_pairs": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p],
+    "el_train_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_float, ctypes.c_void_p],
+    "el_net_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+    "el_infer": [ctypes.c_void_p, ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                 ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
 }
 
 
@@ -168,9 +194,11 @@ def _ptr(t, dtype=None, numel=None, name="tensor"):
 def _op_dtype(t):
     if t.dtype == torch.float64:
         return EL_F64
+    if t.dtype == torch.float32:
+        return EL_F32
     if t.dtype in (torch.bfloat16, torch.int16, torch.uint16):
         return EL_BF16
-    raise ValueError(f"operator dtype {t.dtype} not supported (float64 or bfloat16)")
+    raise ValueError(f"operator dtype {t.dtype} not supported (float64, float32 or bfloat16)")
 
 
 class Context:
@@ -282,3 +310,160 @@ class Context:
                                      _ptr(a, torch.float64, E * nn, "a"), _ptr(ref, torch.float64, E * nn, "ref"),
                                      out))
         return out[0], out[1]
+
+
+def _bf16_ptr(t, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if t.dtype not in (torch.bfloat16, torch.int16, torch.uint16):
+        raise ValueError(f"{name} must hold bfloat16 bits (bfloat16 or int16 tensor), got {t.dtype}")
+    return _ptr(t, None, numel, name)
+
+
+class Net:
+    """Element network state on one context (el_net_*)."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.h = handle
+        n = ctypes.c_int64()
+        lib().el_net_num_params(self.h, ctypes.byref(n))
+        self.n_params = n.value
+
+    @classmethod
+    def create(cls, ctx, n_in, width, depth, n_out, act=EL_ACT_GELU, seed=0):
+        d = el_net_desc(int(n_in), int(width), int(depth), int(act), int(n_out), int(seed))
+        h = ctypes.c_void_p()
+        ctx._check(lib().el_net_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
+    def load(cls, ctx, blob):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        h = ctypes.c_void_p()
+        ctx._check(lib().el_net_load(ctx.h, buf, len(blob), ctypes.byref(h)))
+        return cls(ctx, h)
+
+    def save(self):
+        n = ctypes.c_size_t()
+        self.ctx._check(lib().el_net_save(self.ctx.h, self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self.ctx._check(lib().el_net_save(self.ctx.h, self.h, buf, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def close(self):
+        if self.h:
+            lib().el_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self, which=0):
+        out = torch.empty(self.n_params, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        self.ctx._check(lib().el_net_params(self.ctx.h, self.h, int(which), _ptr(out)))
+        return out
+
+    def fit_normalization(self, x, y):
+        N = x.shape[0]
+        self.ctx._check(lib().el_net_fit_normalization(self.ctx.h, self.h, N, _ptr(x, torch.float32, name="x"),
+                                                        _bf16_ptr(y, name="y")))
+
+    def train_step(self, x, y, lr, loss=None):
+        B = x.shape[0]
+        self.ctx._check(lib().el_train_step(self.ctx.h, self.h, B, _ptr(x, torch.float32, name="x"),
+                                            _bf16_ptr(y, name="y"), ctypes.c_float(lr),
+                                            _ptr(loss, torch.float32, 1, "loss")))
+
+    def forward(self, x, y_norm):
+        self.ctx._check(lib().el_net_forward(self.ctx.h, self.h, x.shape[0], _ptr(x, torch.float32, name="x"),
+                                             _ptr(y_norm, torch.float32, name="y_norm")))
+
+    def infer(self, d, h, kappa, sigma, in2out=None, in2sol=None, in_range=None, fallback=True,
+              precision=EL_FP64):
+        """in2out / in2sol: bfloat16 or float32 device tensors (same dtype)."""
+        nn, n, m = disc_sizes(d)
+        E = h.numel()
+        ref = in2out if in2out is not None else in2sol
+        dt = _op_dtype(ref) if ref is not None else EL_BF16
+        if dt not in (EL_BF16, EL_F32):
+            raise ValueError("learned operators are stored as bfloat16 or float32")
+        for t, cnt, name in ((in2out, E * m * m, "in2out"), (in2sol, E * n * m, "in2sol")):
+            if t is not None and (_op_dtype(t) != dt or t.numel() != cnt):
+                raise ValueError(f"{name}: expected {cnt} elements of the common dtype")
+        nfb = ctypes.c_int64()
+        self.ctx._check(lib().el_infer(self.ctx.h, self.h, d, E, _ptr(h, torch.float64, E, "h"),
+                                       _ptr(kappa, torch.float64, E * nn, "kappa"),
+                                       _ptr(sigma, torch.float64, E * nn, "sigma"),
+                                       _ptr(in2out, name="in2out"), _ptr(in2sol, name="in2sol"), int(dt),
+                                       _ptr(in_range, torch.uint8, E, "in_range"), int(bool(fallback)),
+                                       int(precision), ctypes.byref(nfb)))
+        return nfb.value
+
+
+def el_make_pairs(ctx, d, h, kappa, sigma, y):
+    nn, n, m = disc_sizes(d)
+    E = h.numel()
+    ctx._check(lib().el_make_pairs(ctx.h, d, E, _ptr(h, torch.float64, E, "h"),
+                                   _ptr(kappa, torch.float64, E * nn, "kappa"),
+                                   _ptr(sigma, torch.float64, E * nn, "sigma"),
+                                   _bf16_ptr(y, E * (m * m + n * m), "y")))
+
+
+# ---- network state blob (format documented in include/el.h) -------------------
+import struct as _struct
+
+_HDR = "<8s6i3q6d"
+HEADER_BYTES = 112
+
+
+def net_layout(n_in, width, depth, n_out):
+    """(k0, [(w_off, b_off, out, in) per layer], n_params) of the theta vector."""
+    k0 = (n_in + 31) // 32 * 32
+    layers = []
+    off = 0
+    for l in range(depth + 1):
+        fin = k0 if l == 0 else width
+        fout = n_out if l == depth else width
+        w_off = off
+        off += fin * fout
+        b_off = off
+        off += fout
+        off = (off + 63) // 64 * 64
+        layers.append((w_off, b_off, fout, fin))
+    return k0, layers, off
+
+
+def pack_net_blob(n_in, width, depth, act, n_out, theta, feat_mean, feat_std, y_mean, y_std, box,
+                  step=0, adam_m=None, adam_v=None):
+    import numpy as np
+    k0, _, P = net_layout(n_in, width, depth, n_out)
+    theta = np.asarray(theta, dtype=np.float32)
+    assert theta.size == P
+    adam_m = np.zeros(P, np.float32) if adam_m is None else np.asarray(adam_m, np.float32)
+    adam_v = np.zeros(P, np.float32) if adam_v is None else np.asarray(adam_v, np.float32)
+    hdr = _struct.pack(_HDR, b"ELNET01\0", n_in, width, depth, act, k0, 0, n_out, step, P, *[float(b) for b in box])
+    hdr = hdr + b"\0" * (HEADER_BYTES - len(hdr))
+    parts = [np.asarray(a, dtype=np.float32).tobytes() for a in (feat_mean, feat_std, y_mean, y_std)]
+    return hdr + b"".join(parts) + theta.tobytes() + adam_m.tobytes() + adam_v.tobytes()
+
+
+def unpack_net_blob(blob):
+    import numpy as np
+    magic, n_in, width, depth, act, k0, _, n_out, step, P, *box = _struct.unpack_from(_HDR, blob, 0)
+    if magic != b"ELNET01\0":
+        raise ValueError("bad network blob")
+    o = HEADER_BYTES
+    def take(cnt):
+        nonlocal o
+        a = np.frombuffer(blob, dtype=np.float32, count=cnt, offset=o)
+        o += 4 * cnt
+        return a
+    out = dict(n_in=n_in, width=width, depth=depth, act=act, k0=k0, n_out=n_out, step=step, n_params=P, box=box)
+    out["feat_mean"], out["feat_std"] = take(n_in), take(n_in)
+    out["y_mean"], out["y_std"] = take(n_out), take(n_out)
+    out["theta"], out["adam_m"], out["adam_v"] = take(P), take(P), take(P)
+    return out

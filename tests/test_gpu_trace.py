@@ -84,6 +84,11 @@ def test_matvec_f64_and_bf16(ctx, p, n_a, nx, ny):
     ctx.el_trace_matvec(d, ms, op16, T(x), y)
     ref16 = otrace.matvec(op16.to(torch.float64).cpu().numpy(), ind, outd, x)
     assert rel_err(y.cpu().numpy(), ref16) <= 1e-13
+    op32 = T(i2o).to(torch.float32)
+    print(f"[el_trace_matvec] p={p} n_a={n_a} {nx}x{ny} f32", flush=True)
+    ctx.el_trace_matvec(d, ms, op32, T(x), y)
+    ref32 = otrace.matvec(op32.to(torch.float64).cpu().numpy(), ind, outd, x)
+    assert rel_err(y.cpu().numpy(), ref32) <= 1e-13
 
 
 def _gpu_pipeline(ctx, p, n_a, g, nx, ny, hh, kap, sig, g_side, tol=1e-12, outputs=True):

@@ -1,0 +1,115 @@
+"""Pins of the FP64 network oracle (Sec. 2.4.1 network, Sec. 3.1 MAE + Adam).
+
+* gradients against central finite differences (FP64, small widths);
+* one Adam step from a zero state moves every weight by exactly lr * g / (|g| + eps);
+* the bfloat16 rounding used to mimic the kernels equals torch's
+  float32 -> bfloat16 conversion (round to nearest even);
+* the network blob packer round-trips.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.mlp import MLP, act, dact, adam_step, bf16_round, features
+
+
+def _rand_mlp(rng, n_in, width, depth, n_out, kind):
+    dims = [n_in] + [width] * depth + [n_out]
+    Ws = [rng.uniform(-1, 1, (dims[l + 1], dims[l])) / np.sqrt(dims[l]) for l in range(depth + 1)]
+    bs = [rng.uniform(-0.1, 0.1, dims[l + 1]) for l in range(depth + 1)]
+    return MLP(Ws, bs, kind)
+
+
+@pytest.mark.parametrize("kind", ["gelu", "elu"])
+def test_activation_derivative_fd(kind):
+    z = np.linspace(-4, 4, 101)
+    z = z[np.abs(z) > 1e-3]
+    eps = 1e-6
+    fd = (act(kind, z + eps) - act(kind, z - eps)) / (2 * eps)
+    assert np.abs(fd - dact(kind, z)).max() < 1e-8
+    if kind == "gelu":                     # closed values: GELU(0) = 0, GELU(z) -> z for large z
+        assert act(kind, np.array([0.0]))[0] == 0.0
+        assert abs(act(kind, np.array([10.0]))[0] - 10.0) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["gelu", "elu"])
+def test_mae_gradients_match_finite_differences(kind):
+    rng = np.random.default_rng(4)
+    net = _rand_mlp(rng, 7, 12, 3, 5, kind)
+    X = rng.standard_normal((6, 7))
+    T = rng.standard_normal((6, 5))
+    loss, gW, gb = net.mae_grad(X, T)
+    eps = 1e-6
+    for l in range(len(net.Ws)):
+        for (i, j) in [(0, 0), (1, 2), (net.Ws[l].shape[0] - 1, net.Ws[l].shape[1] - 1)]:
+            W0 = net.Ws[l][i, j]
+            net.Ws[l][i, j] = W0 + eps
+            lp = net.mae_grad(X, T)[0]
+            net.Ws[l][i, j] = W0 - eps
+            lm = net.mae_grad(X, T)[0]
+            net.Ws[l][i, j] = W0
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - gW[l][i, j]) <= 1e-7 * max(1.0, abs(fd)), (l, i, j, fd, gW[l][i, j])
+        b0 = net.bs[l][1]
+        net.bs[l][1] = b0 + eps
+        lp = net.mae_grad(X, T)[0]
+        net.bs[l][1] = b0 - eps
+        lm = net.mae_grad(X, T)[0]
+        net.bs[l][1] = b0
+        assert abs((lp - lm) / (2 * eps) - gb[l][1]) <= 1e-7
+
+
+def test_mae_is_mean_absolute_error():
+    rng = np.random.default_rng(1)
+    net = _rand_mlp(rng, 4, 8, 1, 3, "gelu")
+    X = rng.standard_normal((5, 4))
+    out, _ = net.forward(X)
+    T = out + np.array([1.0, -2.0, 0.5])
+    loss, _, gb = net.mae_grad(X, T)
+    assert abs(loss - 3.5 / 3) < 1e-12
+    # d loss / d b_out = mean over the batch of sign(out - T) / n_out
+    assert np.allclose(gb[-1], np.array([-1.0, 1.0, -1.0]) * 5 / 15)
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(2)
+    th = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    t1, m, v = adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-3)
+    assert np.allclose(t1, th - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(3)
+    a = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-30, 30, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.005859375, 3.4e38]])
+    ref = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(bf16_round(a), ref)
+
+
+def test_features_are_reference_element_coefficients():
+    """Scaling invariance of Sec. 2.4.1: (h, kappa, sigma) and (2h, kappa/2, sigma/2)
+    give the same kappa/sigma features; only the log10 h feature moves."""
+    rng = np.random.default_rng(5)
+    nn = 4
+    x = np.concatenate([[0.1], rng.uniform(0.1, 1, nn), rng.uniform(1, 10, nn)])[None, :]
+    x2 = np.concatenate([[0.2], x[0, 1:] / 2])[None, :]
+    mean, std = np.zeros(9), np.ones(9)
+    f1, f2 = features(x, mean, std, 32), features(x2, mean, std, 32)
+    assert np.allclose(f1[0, 1:9], f2[0, 1:9], atol=1e-14)
+    assert abs(f2[0, 0] - f1[0, 0] - np.log10(2)) < 1e-14
+    assert np.all(f1[0, 9:] == 0)
+
+
+def test_blob_roundtrip():
+    from paper_2308_02467_amd import el
+    k0, layers, P = el.net_layout(9, 16, 2, 24)
+    assert k0 == 32 and all(w % 64 == 0 for (w, b, o, i) in layers)
+    rng = np.random.default_rng(0)
+    th = rng.standard_normal(P).astype(np.float32)
+    blob = el.pack_net_blob(9, 16, 2, 0, 24, th, np.zeros(9), np.ones(9), np.zeros(24), np.ones(24),
+                            [1, 2, 3, 4, 5, 6], step=7)
+    u = el.unpack_net_blob(blob)
+    assert u["step"] == 7 and u["box"] == [1, 2, 3, 4, 5, 6] and np.array_equal(u["theta"], th)
+    assert len(blob) == el.HEADER_BYTES + 4 * (2 * 9 + 2 * 24 + 3 * P)
