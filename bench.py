@@ -44,6 +44,12 @@ def parse():
                     help="after timing: error of the timed solution and of bfloat16-stored operators "
                          "against a 1e-12 FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-samples", type=int, default=200000)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--train-time-limit", type=float, default=240.0, help="seconds")
+    ap.add_argument("--width", type=int, default=1024)
+    ap.add_argument("--depth", type=int, default=4)
     ap.add_argument("--cpu-sample", type=int, default=1536, help="elements in the oracle sample")
     return ap.parse_args()
 
@@ -114,14 +120,36 @@ def main():
     local_ms = float(np.median(phases[:, 0]))
     gm = reports[-1][5]
 
+    i2o_ir = torch.empty_like(i2o)
     # roofline of the dominant kernel: FP64 LU + solves on the matrix cores
     flop_el = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * m
     achieved = flop_el * E / (local_ms * 1e-3) / 1e12
 
+    # FP32 LU + FP64 refinement on the same workload (local solve only)
+    rr = torch.empty(E, dtype=torch.float64, device=dev)
+    ir_times = []
+    for it in range(2):
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        ctx.el_local_solve(d, hh, kap, sig, precision=el.EL_FP32_IR, in2out=i2o_ir, in2sol=None, rel_resid=rr)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ir_times.append(e0.elapsed_time(e1))
+    num = (i2o_ir - i2o).flatten(1).abs().amax(dim=1)
+    den = i2o.flatten(1).abs().amax(dim=1)
+    fp32_ir = {"local_solve_ms": ir_times[-1], "local_solve_el_per_s": E / (ir_times[-1] * 1e-3),
+               "max_rel_residual": float(rr.max()), "in2out_max_rel_diff_vs_fp64": float((num / den).max()),
+               "tflops_fp64_equivalent": flop_el * E / (ir_times[-1] * 1e-3) / 1e12}
+    del i2o_ir
     acc = None
     if args.accuracy:
         print("[bench] accuracy diagnostics", file=sys.stderr, flush=True)
         acc = accuracy(ctx, el, d, ms, hh, i2o, i2s, b, mean, args.restart)
+    learned = None
+    if not args.no_learned:
+        del i2s, i2m
+        torch.cuda.empty_cache()
+        learned = learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o, mean, stream)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu oracle sample of {args.cpu_sample} elements", file=sys.stderr, flush=True)
@@ -142,6 +170,8 @@ def main():
         "local_solve_el_per_s": E / (local_ms * 1e-3),
         "gmres": gm,
         "accuracy": acc,
+        "learned": learned,
+        "fp32_ir": fp32_ir,
         "roofline": {"bound": "mfma", "kernel": "k_local_lu<double>", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": None},
@@ -149,6 +179,83 @@ def main():
     }
     print(json.dumps(out))
     ctx.close()
+
+
+def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_plain, stream):
+    """Train the element network on pairs from the GPU local solver, then time
+    the learned solve (inference + skeleton GMRES + recovery) on the same
+    workload and compare its mean intensity with the plain FP64 solve."""
+    import torch
+    from paper_2308_02467_amd import learned
+    nn, n, m = el.disc_sizes(d)
+    E = hh.numel()
+    dev = hh.device
+    net = el.Net.create(ctx, 1 + 2 * nn, args.width, args.depth, m * m + n * m, seed=0)
+    t0 = time.perf_counter()
+    x, y = learned.training_set(ctx, d, args.train_samples)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    net.fit_normalization(x, y)
+    t0 = time.perf_counter()
+    hist = learned.train(net, x, y, args.epochs, batch=4096, lr=1e-3, time_limit=args.train_time_limit)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, y
+    torch.cuda.empty_cache()
+    lo = torch.empty((E, m, m), dtype=torch.float32, device=dev)
+    ls = torch.empty((E, n, m), dtype=torch.float32, device=dev)
+    mask = torch.empty(E, dtype=torch.uint8, device=dev)
+    t = torch.empty_like(b)
+    mean = torch.empty_like(mean_plain)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    rec = []
+
+    def step(record):
+        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0.record(stream)
+        nfb = net.infer(d, hh, kap, sig, lo, ls, mask, fallback=True)
+        e1.record(stream)
+        ctx.el_trace_rhs(d, ms, g_side, b)
+        st, rep = ctx.el_trace_solve(d, [ms], [lo], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
+        e2.record(stream)
+        ctx.el_recover(d, ms, ls, t, None, mean)
+        e3.record(stream)
+        if record:
+            rec.append((e0, e1, e2, e3, rep[0], nfb))
+
+    print("[bench] learned solve", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - w0) * 1e3 / args.steps
+    ph = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[2]), r[2].elapsed_time(r[3])] for r in rec])
+    d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_plain)
+    # per-element relative error of the learned in2out (diagnostic)
+    num = (lo.double() - i2o_plain).flatten(1).norm(dim=1)
+    den = i2o_plain.flatten(1).norm(dim=1)
+    op_err = (num / den).cpu().numpy()
+    n_in = 1 + 2 * nn
+    flop_el = 2.0 * (n_in * args.width + (args.depth - 1) * args.width ** 2 + args.width * (m * m + n * m))
+    inf_ms = float(np.median(ph[:, 0]))
+    out = {
+        "network": f"{n_in}-{args.width}x{args.depth}-{m * m + n * m} GELU, BF16 MFMA, FP32 accumulate",
+        "train_samples": args.train_samples, "epochs_run": len(hist), "loss_history": hist,
+        "pair_generation_s": t_gen, "training_s": t_train,
+        "ms_per_step": ms_step, "value": E / (ms_step * 1e-3), "unit": "element solves/s (whole learned step)",
+        "phases_ms": {"infer": inf_ms, "gmres": float(np.median(ph[:, 1])), "recover": float(np.median(ph[:, 2]))},
+        "infer_el_per_s": E / (inf_ms * 1e-3),
+        "infer_tflops": flop_el * E / (inf_ms * 1e-3) / 1e12,
+        "fallback_elements": rec[-1][5], "gmres": rec[-1][4],
+        "mean_intensity_rel_l2_vs_plain": (d2 / r2) ** 0.5,
+        "in2out_rel_err_median": float(np.median(op_err)), "in2out_rel_err_max": float(op_err.max()),
+        "operator_storage": "float32",
+    }
+    net.close()
+    return out
 
 
 def accuracy(ctx, el, d, ms, hh, i2o, i2s, b, mean_timed, restart):
@@ -162,6 +269,16 @@ def accuracy(ctx, el, d, ms, hh, i2o, i2s, b, mean_timed, restart):
     ctx.el_recover(d, ms, i2s, t_ref, None, mean_ref)
     d2, r2 = ctx.el_mean_l2(d, hh, mean_timed, mean_ref)
     out = {"reference_gmres": rep[0], "timed_solution_rel_l2": (d2 / r2) ** 0.5}
+    # GMRES tolerance against the error of the mean intensity
+    sweep = {}
+    for tol in (1e-4, 1e-5, 1e-6):
+        tt = torch.empty_like(b)
+        st, rp = ctx.el_trace_solve(d, [ms], [i2o], [b], [tt], tol=tol, restart=restart, max_iter=40000)
+        mm_ = torch.empty_like(mean_timed)
+        ctx.el_recover(d, ms, i2s, tt, None, mm_)
+        d2, r2 = ctx.el_mean_l2(d, hh, mm_, mean_ref)
+        sweep[f"{tol:g}"] = {"iters": rp[0]["iters"], "rel_l2": (d2 / r2) ** 0.5}
+    out["gmres_tol_sweep"] = sweep
     # storage precision of the exact operators: which part costs accuracy
     def solve_with(op_o, op_s):
         tt = torch.empty_like(b)

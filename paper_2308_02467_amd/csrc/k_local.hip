@@ -82,6 +82,11 @@ struct LuArgs {
   T* fac;        // [slots][npan][npad][NB]
   T* inv;        // [slots][npan][2][NB][NB]
   int* flags;    // [0] first singular element, [1] first bad-input element
+  // iterative refinement (T = float): FP64 solution panel per slot, report
+  double* xbuf;       // [slots][npad][NB] or null
+  double* rel_resid;  // [E] or null
+  int ir_steps;
+  double ir_tol;
 };
 
 // Entry (i, j) of the padded local matrix A (identity outside n x n).
@@ -167,6 +172,30 @@ __device__ inline void block_update(T* pan, const T* __restrict__ F, const int* 
   }
 }
 
+// pan = U^{-1} L^{-1} pan for a right-hand-side panel already in logical
+// (pivoted) row order; the forward sweep starts at block Istart (rows above
+// it are zero).  All threads of the workgroup call this.
+template <typename T>
+__device__ inline void panel_solve(T* pan, const T* fac, const T* inv, const int* perm, int npad, int Istart,
+                                   int wave, int lane) {
+  for (int I = Istart; I < npad; I += NB) {
+    if (wave == 0) tri_apply<T>(pan, inv + (size_t)(I / NB) * 2 * NB * NB, I, lane);
+    __syncthreads();
+    if (I + NB < npad) {
+      block_update<T>(pan, fac + (size_t)(I / NB) * npad * NB, perm, I, (I + NB) / 16, npad / 16, wave, lane);
+      __syncthreads();
+    }
+  }
+  for (int I = npad - NB; I >= 0; I -= NB) {
+    if (wave == 0) tri_apply<T>(pan, inv + (size_t)(I / NB) * 2 * NB * NB + NB * NB, I, lane);
+    __syncthreads();
+    if (I > 0) {
+      block_update<T>(pan, fac + (size_t)(I / NB) * npad * NB, perm, I, 0, I / 16, wave, lane);
+      __syncthreads();
+    }
+  }
+}
+
 __device__ inline void argmax_combine(double& v, int& i, double v2, int i2) {
   if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
 }
@@ -185,6 +214,13 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   double* redv = tau_s + nn;                                             // [kWaves]
   int* redi = reinterpret_cast<int*>(redv + kWaves);                     // [kWaves]
   int* sflag = redi + kWaves;                                            // [2]
+  // iterative refinement scratch (only allocated when a.xbuf != null)
+  unsigned long long* colmax = reinterpret_cast<unsigned long long*>(
+      smem + ((sizeof(T) * npad * LDP + 2 * sizeof(int) * npad + 2 * sizeof(double) * nn +
+               kWaves * (sizeof(double) + sizeof(int)) + 2 * sizeof(int) + 15) / 16) * 16);   // [NB]
+  double* xs = reinterpret_cast<double*>(colmax + NB);                    // [npad][8]
+  const bool ir = a.xbuf != nullptr;
+  double* xg = ir ? a.xbuf + (size_t)blockIdx.x * npad * NB : nullptr;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   T* fac = a.fac + (size_t)blockIdx.x * npan * npad * NB;
@@ -326,6 +362,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     __syncthreads();
 
     // ---- right-hand side panels: X = U^{-1} L^{-1} P (-B_hat)
+    double elem_res = 0.0;
     for (int P0 = 0; P0 < mpad; P0 += NB) {
       for (int idx = tid; idx < npad * NB; idx += kThreads) {
         int r = idx >> 4, c = idx & 15;
@@ -342,20 +379,75 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         sflag[1] = (mn / NB) * NB;
       }
       __syncthreads();
-      const int Istart = sflag[1];
-      for (int I = Istart; I < npad; I += NB) {
-        if (wave == 0) tri_apply<T>(pan, inv + (size_t)(I / NB) * 2 * NB * NB, I, lane);
-        __syncthreads();
-        if (I + NB < npad) {
-          block_update<T>(pan, fac + (size_t)(I / NB) * npad * NB, perm, I, (I + NB) / 16, npad / 16, wave, lane);
-          __syncthreads();
+      panel_solve<T>(pan, fac, inv, perm, npad, sflag[1], wave, lane);
+      if (ir) {
+        // FP64 solution panel in HBM, refined with FP64 residuals and FP32 corrections
+        for (int idx = tid; idx < npad * NB; idx += kThreads) {
+          int r = idx >> 4, c = idx & 15;
+          xg[r * NB + c] = (double)pan[r * LDP + c];
         }
-      }
-      for (int I = npad - NB; I >= 0; I -= NB) {
-        if (wave == 0) tri_apply<T>(pan, inv + (size_t)(I / NB) * 2 * NB * NB + NB * NB, I, lane);
+        __threadfence_block();
         __syncthreads();
-        if (I > 0) {
-          block_update<T>(pan, fac + (size_t)(I / NB) * npad * NB, perm, I, 0, I / 16, wave, lane);
+        for (int it = 0;; ++it) {
+          if (tid < NB) colmax[tid] = 0ull;
+          __syncthreads();
+          for (int half = 0; half < 2; ++half) {
+            for (int idx = tid; idx < npad * 8; idx += kThreads) {
+              int r = idx >> 3, c = idx & 7;
+              xs[idx] = xg[r * NB + half * 8 + c];
+            }
+            __syncthreads();
+            for (int i = tid; i < npad; i += kThreads) {
+              const int q = perm[i];
+              double acc[8];
+              if (q >= n) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] = -xs[q * 8 + c];
+              } else {
+                const int k = q / nn, nd = q - k * nn;
+                const double* Trow = dv.T + ((size_t)k * nn + nd) * nn;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+                for (int j = 0; j < nn; ++j) {
+                  const double t = Trow[j];
+                  if (t != 0.0) {
+                    const double* xr = xs + (k * nn + j) * 8;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc[c] += t * xr[c];
+                  }
+                }
+                const double wd = dv.W[nd] * tau_e[nd], ws = dv.W[nd] * tau_s[nd];
+                const double* Qr = dv.Q + k * dv.n_a;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                  double sc = 0.0;
+                  for (int kp = 0; kp < dv.n_a; ++kp) sc += Qr[kp] * xs[(kp * nn + nd) * 8 + c];
+                  const int col = P0 + half * 8 + c;
+                  const double rv = (col < m && q == dv.in_row[col]) ? dv.in_val[col] : 0.0;
+                  acc[c] = rv - (acc[c] + wd * xs[q * 8 + c] - ws * sc);
+                }
+              }
+#pragma unroll
+              for (int c = 0; c < 8; ++c) {
+                pan[i * LDP + half * 8 + c] = (T)acc[c];
+                atomicMax(&colmax[half * 8 + c], (unsigned long long)__double_as_longlong(fabs(acc[c])));
+              }
+            }
+            __syncthreads();
+          }
+          double worst = 0.0;
+          for (int c = 0; c < NB; ++c)
+            if (P0 + c < m) worst = fmax(worst, __longlong_as_double((long long)colmax[c]) / dv.in_val[P0 + c]);
+          if (worst <= a.ir_tol || it >= a.ir_steps) {
+            elem_res = fmax(elem_res, worst);
+            break;
+          }
+          panel_solve<T>(pan, fac, inv, perm, npad, 0, wave, lane);
+          for (int idx = tid; idx < npad * NB; idx += kThreads) {
+            int r = idx >> 4, c = idx & 15;
+            xg[r * NB + c] += (double)pan[r * LDP + c];
+          }
+          __threadfence_block();
           __syncthreads();
         }
       }
@@ -365,7 +457,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         for (int idx = tid; idx < n * NB; idx += kThreads) {
           int r = idx >> 4, c = idx & 15;
           if (P0 + c < m) {
-            const double v = (double)pan[r * LDP + c];
+            const double v = ir ? xg[r * NB + c] : (double)pan[r * LDP + c];
             const int64_t o = ((int64_t)e * n + r) * m + P0 + c;
             if (a.in2sol) a.in2sol[o] = v;
             if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
@@ -378,7 +470,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         for (int idx = tid; idx < m * NB; idx += kThreads) {
           int r = idx >> 4, c = idx & 15;
           if (P0 + c < m) {
-            const double v = (double)pan[dv.out_row[r] * LDP + c];
+            const double v = ir ? xg[dv.out_row[r] * NB + c] : (double)pan[dv.out_row[r] * LDP + c];
             const int64_t o = ((int64_t)e * m + r) * m + P0 + c;
             if (a.in2out) a.in2out[o] = v;
             if (a.b_i2o) a.b_i2o[o] = gemm::f2bf((float)v);
@@ -394,13 +486,15 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
           int r = idx >> 4, c = idx & 15;
           if (P0 + c < m) {
             double acc = 0.0;
-            for (int k = 0; k < dv.n_a; ++k) acc += (double)pan[(k * nn + r) * LDP + c];
+            for (int k = 0; k < dv.n_a; ++k)
+              acc += ir ? xg[(k * nn + r) * NB + c] : (double)pan[(k * nn + r) * LDP + c];
             o[(size_t)r * m + P0 + c] = acc * s;
           }
         }
       }
       __syncthreads();
     }
+    if (ir && tid == 0 && a.rel_resid) a.rel_resid[e] = elem_res;
   }
 }
 
@@ -415,9 +509,12 @@ __global__ void k_fill_int(int* p, int n, int v) {
 }
 
 template <typename T>
-size_t lu_smem_bytes(int npad, int nn) {
-  return sizeof(T) * (size_t)npad * LDP + 2 * sizeof(int) * (size_t)npad + 2 * sizeof(double) * nn +
-         kWaves * (sizeof(double) + sizeof(int)) + 2 * sizeof(int) + 16;
+size_t lu_smem_bytes(int npad, int nn, bool ir) {
+  size_t base = sizeof(T) * (size_t)npad * LDP + 2 * sizeof(int) * (size_t)npad + 2 * sizeof(double) * nn +
+                kWaves * (sizeof(double) + sizeof(int)) + 2 * sizeof(int);
+  base = (base + 15) / 16 * 16;
+  if (ir) base += NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * 8;
+  return base + 16;
 }
 
 }  // namespace
@@ -436,17 +533,16 @@ struct LocalOut {
   const int32_t* emap = nullptr;
 };
 
-el_status run_local(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
-                    const double* kappa, const double* sigma, const LocalOut& out, double* rel_resid) {
+template <typename T>
+el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, const double* h,
+                      const double* kappa, const double* sigma, const LocalOut& out, double* rel_resid) {
   const DiscHost& dh = de->host;
   const int npad = (dh.n + NB - 1) / NB * NB;
   const int mpad = (dh.m + NB - 1) / NB * NB;
-  if (precision != EL_FP64)
-    return set_error(ctx, EL_ERR_ARG, "el_local_solve: EL_FP32_IR is not available in this build");
   if (rel_resid) {
     hipLaunchKernelGGL(k_fill_double, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, ctx->stream, rel_resid, E, 0.0);
   }
-  size_t smem = lu_smem_bytes<double>(npad, dh.nn);
+  size_t smem = lu_smem_bytes<T>(npad, dh.nn, ir);
   int max_smem = 0;
   hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
   if ((int)smem > max_smem) {
@@ -456,15 +552,16 @@ el_status run_local(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E
   }
   const int npan = npad / NB;
   const int64_t slots = std::min<int64_t>(E, (int64_t)ctx->num_cus * 2);
-  size_t fac_bytes = sizeof(double) * (size_t)slots * npan * npad * NB;
-  size_t inv_bytes = sizeof(double) * (size_t)slots * npan * 2 * NB * NB;
-  el_status st = ensure_ws(ctx, ctx->ws_local, fac_bytes + inv_bytes);
+  size_t fac_bytes = sizeof(T) * (size_t)slots * npan * npad * NB;
+  size_t inv_bytes = sizeof(T) * (size_t)slots * npan * 2 * NB * NB;
+  size_t x_bytes = ir ? sizeof(double) * (size_t)slots * npad * NB : 0;
+  el_status st = ensure_ws(ctx, ctx->ws_local, fac_bytes + inv_bytes + x_bytes + 256);
   if (st) return st;
   st = ensure_ws(ctx, ctx->ws_small, 8192);
   if (st) return st;
   int* flags = reinterpret_cast<int*>(ctx->ws_small.ptr);
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, flags, 2, INT_MAX);
-  LuArgs<double> args;
+  LuArgs<T> args;
   args.dv = de->view;
   args.E = E;
   args.npad = npad;
@@ -473,13 +570,18 @@ el_status run_local(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E
   args.in2out = out.in2out; args.in2sol = out.in2sol; args.in2mean = out.in2mean;
   args.b_i2o = out.b_i2o; args.b_i2s = out.b_i2s; args.pairs = out.pairs; args.emap = out.emap;
   args.f_i2o = out.f_i2o; args.f_i2s = out.f_i2s;
-  args.fac = reinterpret_cast<double*>(ctx->ws_local.ptr);
-  args.inv = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ws_local.ptr) + fac_bytes);
+  char* base = reinterpret_cast<char*>(ctx->ws_local.ptr);
+  args.fac = reinterpret_cast<T*>(base);
+  args.inv = reinterpret_cast<T*>(base + fac_bytes);
+  args.xbuf = ir ? reinterpret_cast<double*>(base + ((fac_bytes + inv_bytes + 255) / 256) * 256) : nullptr;
+  args.rel_resid = rel_resid;
+  args.ir_steps = 3;
+  args.ir_tol = 1e-13;
   args.flags = flags;
-  hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local_lu<double>),
+  hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local_lu<T>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (he != hipSuccess) return hip_check(ctx, he, "hipFuncSetAttribute(k_local_lu)");
-  hipLaunchKernelGGL(k_local_lu<double>, dim3((unsigned)slots), dim3(kThreads), smem, ctx->stream, args);
+  hipLaunchKernelGGL(k_local_lu<T>, dim3((unsigned)slots), dim3(kThreads), smem, ctx->stream, args);
   he = hipGetLastError();
   if (he != hipSuccess) return hip_check(ctx, he, "launch k_local_lu");
   int hflags[2];
@@ -497,6 +599,12 @@ el_status run_local(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E
     return set_error(ctx, EL_ERR_SINGULAR, os.str());
   }
   return EL_OK;
+}
+
+el_status run_local(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
+                    const double* kappa, const double* sigma, const LocalOut& out, double* rel_resid) {
+  if (precision == EL_FP32_IR) return run_local_t<float>(ctx, de, true, E, h, kappa, sigma, out, rel_resid);
+  return run_local_t<double>(ctx, de, false, E, h, kappa, sigma, out, rel_resid);
 }
 
 }  // namespace

@@ -1,0 +1,64 @@
+"""Learned local solve ("element learning", Sec. 2.4 and 3.1) on the GPU.
+
+* ``training_set``: seeded element draws (inputs.training_draws) and their
+  operators from the FP64 GPU local solver (el_make_pairs), stored as
+  bfloat16 targets (in2out followed by in2sol) on the device;
+* ``train``: epochs of el_train_step over contiguous batches in a seeded
+  random batch order;
+* ``learned_solve``: el_infer (with plain fallback outside the training box)
+  -> el_trace_solve -> el_recover.
+
+Every numerical step runs in the library's HIP kernels; this module only
+sequences calls and holds device buffers.
+"""
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import el, inputs
+
+
+def training_set(ctx, d, N, seed=1234, chunk=8192, log=True):
+    """(x [N, 1+2nn] float32 raw inputs, y [N, n_out] bfloat16 targets), on the device."""
+    nn, n, m = el.disc_sizes(d)
+    n_out = m * m + n * m
+    xi, _ = el.lgl(d.p)
+    h, kap, sig = inputs.training_draws(N, xi, seed=seed)
+    dev = torch.device(f"cuda:{ctx.device}")
+    x = torch.as_tensor(np.concatenate([h[:, None], kap, sig], axis=1), dtype=torch.float32, device=dev)
+    y = torch.empty((N, n_out), dtype=torch.bfloat16, device=dev)
+    H = torch.as_tensor(h, dtype=torch.float64, device=dev)
+    K = torch.as_tensor(kap, dtype=torch.float64, device=dev)
+    S = torch.as_tensor(sig, dtype=torch.float64, device=dev)
+    for c0 in range(0, N, chunk):
+        c1 = min(N, c0 + chunk)
+        el.el_make_pairs(ctx, d, H[c0:c1], K[c0:c1], S[c0:c1], y[c0:c1])
+        if log:
+            print(f"[learned] training pairs {c1}/{N}", file=sys.stderr, flush=True)
+    return x, y
+
+
+def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=None):
+    """Adam on the MAE loss; returns the per-epoch mean loss (normalized units)."""
+    N = x.shape[0]
+    nb = N // batch
+    rng = np.random.default_rng(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+    acc = torch.zeros(1, dtype=torch.float32, device=x.device)
+    hist = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        acc.zero_()
+        for b in rng.permutation(nb):
+            b0 = int(b) * batch
+            net.train_step(x[b0:b0 + batch], y[b0:b0 + batch], lr, loss)
+            acc += loss
+        hist.append(acc.item() / nb)
+        if log:
+            print(f"[learned] epoch {ep + 1}/{epochs} loss {hist[-1]:.4e} ({time.perf_counter() - t0:.1f} s)",
+                  file=sys.stderr, flush=True)
+        if time_limit is not None and time.perf_counter() - t0 > time_limit:
+            break
+    return hist
