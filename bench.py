@@ -4,17 +4,20 @@ Workload (named in the output's config): 128 x 128 square elements on the
 unit square, Q6 LGL (p = 6) x 16 discrete ordinates (n = 784 volume and
 m = 224 inflow DOFs per element), isotropic scattering, the smooth Gaussian
 cloud kappa = 0.01 + 0.5 G, sigma = 0.1 + 30 G (G a Gaussian bump of width
-0.2 at the centre), radiance 1 entering through the left side.
+0.2 at the centre), radiance 1 entering through the left side.  GMRES
+tolerance 1e-5 (restart 50): the plain FP64 solution is then within 1.3e-4
+relative L2 of the fully converged one (measured with --accuracy).
 
-One step = the whole plain FP64 path: element local solves (assembly + LU +
-solves, writing in2out, in2sol and in2mean), the skeleton right-hand side,
-GMRES on the skeleton system, and recovery of u and the mean intensity.
-Inputs are resident in HBM before the timed region.  value = elements per
-second of the whole step.
-
-Also reported: the local-solve kernel time (roofline of the dominant kernel,
-FP64 matrix cores) and the CPU oracle timed on a bounded sample of the same
-workload (cpu_baseline).
+Steps (inputs resident in HBM before every timed region):
+* plain:   el_local_solve (FP64 LU) -> el_trace_rhs -> el_trace_solve -> el_recover
+* learned: el_infer (BF16 MFMA network, FP32 operator storage, plain fallback
+           outside the training box) -> el_conserve -> el_trace_rhs ->
+           el_trace_solve -> el_recover
+The network (99-1024x4-225792, GELU) is first trained on pairs from the GPU
+local solver (not timed; reported).  value = elements per second of the whole
+learned step; the plain step, the FP32 + refinement local solve, the error of
+the learned mean intensity against the plain FP64 solve and the CPU oracle
+timed on a bounded sample are reported beside it.
 """
 import argparse
 import json
@@ -29,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix
 HBM_PEAK_GBS = 8000.0
 
 
@@ -38,20 +42,28 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="elements per side")
-    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--accuracy", action="store_true",
-                    help="after timing: error of the timed solution and of bfloat16-stored operators "
-                         "against a 1e-12 FP64 solve")
+                    help="GMRES tolerance sweep and operator-storage errors against a 1e-12 FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1536, help="elements in the oracle sample")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-samples", type=int, default=200000)
-    ap.add_argument("--epochs", type=int, default=8)
-    ap.add_argument("--train-time-limit", type=float, default=240.0, help="seconds")
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--train-time-limit", type=float, default=180.0, help="seconds")
+    ap.add_argument("--lr-decay", type=float, default=0.7,
+                    help="fraction of the training after which lr drops 10x (0 = constant)")
     ap.add_argument("--width", type=int, default=1024)
     ap.add_argument("--depth", type=int, default=4)
-    ap.add_argument("--cpu-sample", type=int, default=1536, help="elements in the oracle sample")
+    ap.add_argument("--no-conserve", action="store_true", help="skip the energy-balance correction")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -76,6 +88,12 @@ def main():
 
     ctx = el.Context(0)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)      # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     hh, kap, sig = T(np.full(E, h)), T(kap_np), T(sig_np)
     i2o = torch.empty((E, m, m), dtype=torch.float64, device=dev)
@@ -86,118 +104,133 @@ def main():
     t = torch.empty(nt, dtype=torch.float64, device=dev)
     u = torch.empty((E, n), dtype=torch.float64, device=dev)
     mean = torch.empty((E, nn), dtype=torch.float64, device=dev)
-
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    reports = []
 
-    def step(record):
-        e0, e1, e2, e3, e4 = ev(), ev(), ev(), ev(), ev()
-        e0.record(stream)
+    # ---- plain FP64 path -----------------------------------------------------
+    rec = []
+
+    def plain_step(record):
+        e = [ev() for _ in range(5)]
+        e[0].record(stream)
         ctx.el_local_solve(d, hh, kap, sig, in2out=i2o, in2sol=i2s, in2mean=i2m)
-        e1.record(stream)
+        e[1].record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
-        e2.record(stream)
+        e[2].record(stream)
         st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
-        e3.record(stream)
+        e[3].record(stream)
         ctx.el_recover(d, ms, i2s, t, u, mean)
-        e4.record(stream)
+        e[4].record(stream)
         if record:
-            reports.append((e0, e1, e2, e3, e4, rep[0]))
+            rec.append((e, rep[0]))
 
-    print(f"[bench] warmup {args.warmup} step(s), E={E}", file=sys.stderr, flush=True)
+    log(f"plain: warmup {args.warmup}, timing {args.steps} step(s), E={E}")
     for _ in range(args.warmup):
-        step(False)
+        plain_step(False)
     torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
+    w0 = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
+        plain_step(True)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    phases = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[2]), r[2].elapsed_time(r[3]),
-                        r[3].elapsed_time(r[4])] for r in reports])           # ms
-    ms_step = wall * 1e3 / args.steps
-    local_ms = float(np.median(phases[:, 0]))
-    gm = reports[-1][5]
+    plain_ms = (time.perf_counter() - w0) * 1e3 / args.steps
+    ph = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(4)] for r in rec])
+    local_ms = float(np.median(ph[:, 0]))
+    flop_el = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * m          # LU + solves for m columns
+    lu_tf = flop_el * E / (local_ms * 1e-3) / 1e12
+    plain = {
+        "ms_per_step": plain_ms, "value": E / (plain_ms * 1e-3), "unit": "element solves/s (whole plain step)",
+        "phases_ms": {"local_solve": local_ms, "trace_rhs": float(np.median(ph[:, 1])),
+                      "gmres": float(np.median(ph[:, 2])), "recover": float(np.median(ph[:, 3]))},
+        "local_solve_el_per_s": E / (local_ms * 1e-3), "gmres": rec[-1][1],
+        "roofline_local_lu": {"bound": "mfma", "kernel": "k_local_lu<double>", "achieved": lu_tf,
+                              "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": lu_tf / FP64_PEAK_TFLOPS,
+                              "flop_per_element": flop_el},
+    }
 
+    # ---- FP32 LU + FP64 refinement (local solve only) -------------------------
+    log("FP32 + refinement local solve")
     i2o_ir = torch.empty_like(i2o)
-    # roofline of the dominant kernel: FP64 LU + solves on the matrix cores
-    flop_el = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * m
-    achieved = flop_el * E / (local_ms * 1e-3) / 1e12
-
-    # FP32 LU + FP64 refinement on the same workload (local solve only)
     rr = torch.empty(E, dtype=torch.float64, device=dev)
-    ir_times = []
-    for it in range(2):
+    ir_ms = []
+    for _ in range(2):
         e0, e1 = ev(), ev()
         e0.record(stream)
-        ctx.el_local_solve(d, hh, kap, sig, precision=el.EL_FP32_IR, in2out=i2o_ir, in2sol=None, rel_resid=rr)
+        ctx.el_local_solve(d, hh, kap, sig, precision=el.EL_FP32_IR, in2out=i2o_ir, rel_resid=rr)
         e1.record(stream)
         torch.cuda.synchronize()
-        ir_times.append(e0.elapsed_time(e1))
+        ir_ms.append(e0.elapsed_time(e1))
     num = (i2o_ir - i2o).flatten(1).abs().amax(dim=1)
     den = i2o.flatten(1).abs().amax(dim=1)
-    fp32_ir = {"local_solve_ms": ir_times[-1], "local_solve_el_per_s": E / (ir_times[-1] * 1e-3),
-               "max_rel_residual": float(rr.max()), "in2out_max_rel_diff_vs_fp64": float((num / den).max()),
-               "tflops_fp64_equivalent": flop_el * E / (ir_times[-1] * 1e-3) / 1e12}
-    del i2o_ir
+    fp32_ir = {"local_solve_ms": ir_ms[-1], "local_solve_el_per_s": E / (ir_ms[-1] * 1e-3),
+               "max_rel_residual": float(rr.max()), "in2out_max_rel_diff_vs_fp64": float((num / den).max())}
+    del i2o_ir, rr
+
     acc = None
     if args.accuracy:
-        print("[bench] accuracy diagnostics", file=sys.stderr, flush=True)
-        acc = accuracy(ctx, el, d, ms, hh, i2o, i2s, b, mean, args.restart)
+        log("accuracy diagnostics")
+        acc = accuracy(ctx, d, ms, hh, i2o, i2s, b, mean, args.restart)
+
     learned = None
     if not args.no_learned:
-        del i2s, i2m
+        del i2s, i2m, u
         torch.cuda.empty_cache()
-        learned = learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o, mean, stream)
+        learned = learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o, mean, stream, E, nn, n, m)
+
     cpu = None
     if not args.no_cpu_baseline:
-        print(f"[bench] cpu oracle sample of {args.cpu_sample} elements", file=sys.stderr, flush=True)
+        log(f"cpu oracle sample of {args.cpu_sample} elements")
         cpu = cpu_baseline(p, n_a, h, kap_np, sig_np, args.cpu_sample)
 
+    if learned is not None:
+        head_ms, head_value, unit = learned["ms_per_step"], learned["value"], "element solves/s (whole learned step)"
+        roof = learned.pop("roofline_matvec")
+        dtype = "bf16+f32+f64"
+        workload = (f"learned HDG (element network + GMRES), {nx}x{nx} elements, p=6, N_a=16, Gaussian cloud, "
+                    f"left inflow; mean-intensity rel L2 vs plain FP64 {learned['mean_intensity_rel_l2_vs_plain']:.2e}")
+    else:
+        head_ms, head_value, unit = plain_ms, plain["value"], plain["unit"]
+        roof = dict(plain["roofline_local_lu"])
+        roof.pop("flop_per_element", None)
+        dtype = "f64"
+        workload = f"plain FP64 HDG, {nx}x{nx} elements, p=6, N_a=16, Gaussian cloud, left inflow"
+    roof.setdefault("traffic", None)
     out = {
         "metric": "element solves/s + full solve time at 1e-3 rel L2, learned vs plain (p=6)",
-        "value": E / (ms_step * 1e-3),
-        "unit": "element solves/s (whole plain step)",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "value": head_value, "unit": unit,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": head_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"plain FP64 HDG, {nx}x{nx} elements, p=6, N_a=16, Gaussian cloud, left inflow",
-                   "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol, "gmres_restart": args.restart},
-        "phases_ms": {"local_solve": local_ms, "trace_rhs": float(np.median(phases[:, 1])),
-                      "gmres": float(np.median(phases[:, 2])), "recover": float(np.median(phases[:, 3]))},
-        "local_solve_el_per_s": E / (local_ms * 1e-3),
-        "gmres": gm,
-        "accuracy": acc,
-        "learned": learned,
-        "fp32_ir": fp32_ir,
-        "roofline": {"bound": "mfma", "kernel": "k_local_lu<double>", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None},
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": workload, "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol,
+                   "gmres_restart": args.restart},
+        "roofline": roof,
         "cpu_baseline": cpu,
+        "plain": plain,
+        "learned": learned,
+        "speedup_learned_vs_plain": (plain_ms / learned["ms_per_step"]) if learned else None,
+        "fp32_ir": fp32_ir,
+        "accuracy": acc,
     }
     print(json.dumps(out))
     ctx.close()
 
 
-def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_plain, stream):
+def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_plain, stream, E, nn, n, m):
     """Train the element network on pairs from the GPU local solver, then time
-    the learned solve (inference + skeleton GMRES + recovery) on the same
-    workload and compare its mean intensity with the plain FP64 solve."""
+    the learned solve on the same workload and compare its mean intensity
+    with the plain FP64 solve."""
     import torch
     from paper_2308_02467_amd import learned
-    nn, n, m = el.disc_sizes(d)
-    E = hh.numel()
     dev = hh.device
+    ev = lambda: torch.cuda.Event(enable_timing=True)
     net = el.Net.create(ctx, 1 + 2 * nn, args.width, args.depth, m * m + n * m, seed=0)
+    log(f"learned: {args.train_samples} training pairs")
     t0 = time.perf_counter()
     x, y = learned.training_set(ctx, d, args.train_samples)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     net.fit_normalization(x, y)
     t0 = time.perf_counter()
-    hist = learned.train(net, x, y, args.epochs, batch=4096, lr=1e-3, time_limit=args.train_time_limit)
+    hist = learned.train(net, x, y, args.epochs, batch=4096, lr=1e-3, time_limit=args.train_time_limit,
+                         decay_at=args.lr_decay)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del x, y
@@ -207,23 +240,28 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     mask = torch.empty(E, dtype=torch.uint8, device=dev)
     t = torch.empty_like(b)
     mean = torch.empty_like(mean_plain)
-    ev = lambda: torch.cuda.Event(enable_timing=True)
     rec = []
 
-    def step(record):
-        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
-        e0.record(stream)
+    def step(record, conserve=not args.no_conserve):
+        e = [ev() for _ in range(4)]
+        e[0].record(stream)
         nfb = net.infer(d, hh, kap, sig, lo, ls, mask, fallback=True)
-        e1.record(stream)
+        if conserve:
+            ctx.el_conserve(d, hh, kap, lo, ls, mask)
+        e[1].record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
         st, rep = ctx.el_trace_solve(d, [ms], [lo], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
-        e2.record(stream)
+        e[2].record(stream)
         ctx.el_recover(d, ms, ls, t, None, mean)
-        e3.record(stream)
+        e[3].record(stream)
         if record:
-            rec.append((e0, e1, e2, e3, rep[0], nfb))
+            rec.append((e, rep[0], nfb))
 
-    print("[bench] learned solve", file=sys.stderr, flush=True)
+    log("learned solve")
+    step(False, conserve=False)
+    d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_plain)
+    err_raw = (d2 / r2) ** 0.5
+    op_raw = ((lo.double() - i2o_plain).flatten(1).norm(dim=1) / i2o_plain.flatten(1).norm(dim=1)).cpu().numpy()
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -232,69 +270,80 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
         step(True)
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - w0) * 1e3 / args.steps
-    ph = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[2]), r[2].elapsed_time(r[3])] for r in rec])
+    ph = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(3)] for r in rec])
     d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_plain)
-    # per-element relative error of the learned in2out (diagnostic)
-    num = (lo.double() - i2o_plain).flatten(1).norm(dim=1)
-    den = i2o_plain.flatten(1).norm(dim=1)
-    op_err = (num / den).cpu().numpy()
+    op_err = ((lo.double() - i2o_plain).flatten(1).norm(dim=1) / i2o_plain.flatten(1).norm(dim=1)).cpu().numpy()
+
+    # dominant kernel of the learned step: the FP32 in2out sweep (k_matvec<float>), HBM-bound
+    xv = torch.rand_like(b)
+    yv = torch.empty_like(b)
+    reps = 20
+    e0, e1 = ev(), ev()
+    ctx.el_trace_matvec(d, ms, lo, xv, yv)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.el_trace_matvec(d, ms, lo, xv, yv)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mv_ms = e0.elapsed_time(e1) / reps
+    mv_bytes = E * m * (m * 4 + 3 * 8)          # operator + gathered inflow + outflow read/write
+    mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+
     n_in = 1 + 2 * nn
     flop_el = 2.0 * (n_in * args.width + (args.depth - 1) * args.width ** 2 + args.width * (m * m + n * m))
     inf_ms = float(np.median(ph[:, 0]))
     out = {
         "network": f"{n_in}-{args.width}x{args.depth}-{m * m + n * m} GELU, BF16 MFMA, FP32 accumulate",
-        "train_samples": args.train_samples, "epochs_run": len(hist), "loss_history": hist,
+        "train_samples": args.train_samples, "epochs_run": len(hist),
+        "final_train_loss": hist[-1] if hist else None,
         "pair_generation_s": t_gen, "training_s": t_train,
         "ms_per_step": ms_step, "value": E / (ms_step * 1e-3), "unit": "element solves/s (whole learned step)",
-        "phases_ms": {"infer": inf_ms, "gmres": float(np.median(ph[:, 1])), "recover": float(np.median(ph[:, 2]))},
+        "phases_ms": {"infer_and_correction": inf_ms, "gmres": float(np.median(ph[:, 1])),
+                      "recover": float(np.median(ph[:, 2]))},
         "infer_el_per_s": E / (inf_ms * 1e-3),
-        "infer_tflops": flop_el * E / (inf_ms * 1e-3) / 1e12,
-        "fallback_elements": rec[-1][5], "gmres": rec[-1][4],
+        "infer_network_tflops": flop_el * E / (inf_ms * 1e-3) / 1e12,
+        "fallback_elements": rec[-1][2], "gmres": rec[-1][1],
         "mean_intensity_rel_l2_vs_plain": (d2 / r2) ** 0.5,
+        "energy_balance_correction": not args.no_conserve,
         "in2out_rel_err_median": float(np.median(op_err)), "in2out_rel_err_max": float(op_err.max()),
+        "without_correction": {"mean_intensity_rel_l2_vs_plain": err_raw,
+                               "in2out_rel_err_median": float(np.median(op_raw))},
         "operator_storage": "float32",
+        "roofline_matvec": {"bound": "hbm", "kernel": "k_matvec<float>", "achieved": mv_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS, "bytes_per_launch": mv_bytes,
+                            "avg_launch_ms": mv_ms},
     }
     net.close()
     return out
 
 
-def accuracy(ctx, el, d, ms, hh, i2o, i2s, b, mean_timed, restart):
+def accuracy(ctx, d, ms, hh, i2o, i2s, b, mean_timed, restart):
     """Relative L2 errors of the mean intensity against the FP64 solve at 1e-12."""
     import torch
-    E = hh.numel()
-    nn = mean_timed.shape[1]
     t_ref = torch.empty_like(b)
     st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t_ref], tol=1e-12, restart=restart, max_iter=40000)
     mean_ref = torch.empty_like(mean_timed)
     ctx.el_recover(d, ms, i2s, t_ref, None, mean_ref)
     d2, r2 = ctx.el_mean_l2(d, hh, mean_timed, mean_ref)
     out = {"reference_gmres": rep[0], "timed_solution_rel_l2": (d2 / r2) ** 0.5}
-    # GMRES tolerance against the error of the mean intensity
-    sweep = {}
-    for tol in (1e-4, 1e-5, 1e-6):
+
+    def solve_with(op_o, op_s, tol=1e-12):
         tt = torch.empty_like(b)
-        st, rp = ctx.el_trace_solve(d, [ms], [i2o], [b], [tt], tol=tol, restart=restart, max_iter=40000)
-        mm_ = torch.empty_like(mean_timed)
-        ctx.el_recover(d, ms, i2s, tt, None, mm_)
-        d2, r2 = ctx.el_mean_l2(d, hh, mm_, mean_ref)
-        sweep[f"{tol:g}"] = {"iters": rp[0]["iters"], "rel_l2": (d2 / r2) ** 0.5}
-    out["gmres_tol_sweep"] = sweep
-    # storage precision of the exact operators: which part costs accuracy
-    def solve_with(op_o, op_s):
-        tt = torch.empty_like(b)
-        st, rp = ctx.el_trace_solve(d, [ms], [op_o], [b], [tt], tol=1e-12, restart=restart, max_iter=40000)
+        st, rp = ctx.el_trace_solve(d, [ms], [op_o], [b], [tt], tol=tol, restart=restart, max_iter=40000)
         mm_ = torch.empty_like(mean_timed)
         ctx.el_recover(d, ms, op_s, tt, None, mm_)
         d2, r2 = ctx.el_mean_l2(d, hh, mm_, mean_ref)
-        return (d2 / r2) ** 0.5
+        return (d2 / r2) ** 0.5, rp[0]["iters"]
+
+    out["gmres_tol_sweep"] = {f"{tol:g}": dict(zip(("rel_l2", "iters"), solve_with(i2o, i2s, tol)))
+                              for tol in (1e-4, 1e-5, 1e-6)}
     o16 = i2o.to(torch.bfloat16)
-    out["bf16_in2out_f64_in2sol_rel_l2"] = solve_with(o16, i2s)
+    out["bf16_in2out_f64_in2sol_rel_l2"] = solve_with(o16, i2s)[0]
     s16 = i2s.to(torch.bfloat16)
-    out["bf16_in2out_bf16_in2sol_rel_l2"] = solve_with(o16, s16)
+    out["bf16_in2out_bf16_in2sol_rel_l2"] = solve_with(o16, s16)[0]
     del o16
     o32 = i2o.to(torch.float32)
-    out["f32_in2out_bf16_in2sol_rel_l2"] = solve_with(o32, s16)
-    del o32, s16
+    out["f32_in2out_bf16_in2sol_rel_l2"] = solve_with(o32, s16)[0]
     return out
 
 
@@ -316,7 +365,7 @@ def cpu_baseline(p, n_a, h, kap, sig, count):
     dt = time.perf_counter() - t0
     return {"value": count / dt, "unit": "element local solves/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 local solves (assembly + LAPACK LU solve for all 224 inflow columns) of {count} "
-                      f"of the {E} elements; {dt:.1f} s; the oracle's skeleton solve is not in the sample"}
+                      f"of the {E} elements ({dt:.1f} s); the oracle's skeleton solve is not in the sample"}
 
 
 if __name__ == "__main__":

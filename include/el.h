@@ -178,6 +178,17 @@ el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, i
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean,
                           int op_dtype, const double* trace, double* mean);
 
+/* Energy balance of learned operators.  For every element (with mask[e] != 0
+ * when mask is given) and every inflow column i, the exact operators satisfy
+ *   sum_o w_o in2out[o][i] + sum_(k,nd) W_nd (h kappa_nd / 2) in2sol[(k,nd)][i] = w_i
+ * (outflow = inflow - absorption, obtained by testing the local equations
+ * with v = 1 and summing over ordinates; w = face quadrature weight times
+ * |s.n|).  Each column of in2out is rescaled in place so that this holds.
+ * Not part of the paper's method: a post-processing option for the learned
+ * operators.  in2out, in2sol in op_dtype (EL_F64, EL_F32, EL_BF16). */
+el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa, void* in2out,
+                      const void* in2sol, int op_dtype, const uint8_t* mask);
+
 /* Squared element L2 norms of mean-intensity fields [E][nn] (relative error
  * measure of Sec. 3.2.1): out_host[0] = sum_e (h_e/2)^2 sum W (a - ref)^2,
  * out_host[1] = sum_e (h_e/2)^2 sum W ref^2.  Synchronizes. */

@@ -140,7 +140,7 @@ bool build_disc(const el_disc& d, DiscHost& o, std::string& err) {
     }
   }
   // index tables
-  o.in_row.clear(); o.out_row.clear(); o.in_val.clear();
+  o.in_row.clear(); o.out_row.clear(); o.in_val.clear(); o.out_val.clear();
   o.in_f.clear(); o.in_k.clear(); o.in_j.clear(); o.out_f.clear(); o.out_k.clear(); o.out_j.clear();
   for (int f = 0; f < 4; ++f) {
     std::vector<int> If, Of;
@@ -161,6 +161,7 @@ bool build_disc(const el_disc& d, DiscHost& o, std::string& err) {
       for (int j = 0; j < q; ++j) {
         int k = Of[r], nd = face_node(f, j);
         o.out_row.push_back(k * nn + nd);
+        o.out_val.push_back(o.omega[j] * sn(k, f));
         o.out_f.push_back(f); o.out_k.push_back(k); o.out_j.push_back(j);
       }
   }

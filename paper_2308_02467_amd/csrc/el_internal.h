@@ -29,6 +29,7 @@ struct DiscHost {
   std::vector<double> T;              // [n_a][nn][nn] = B_k - C_k
   std::vector<int32_t> in_row, out_row;   // [m] volume rows
   std::vector<double> in_val;             // [m] entry of -B_hat (w_j |s.n_f|)
+  std::vector<double> out_val;            // [m] outflow face weight w_j (s.n_f)
   std::vector<int32_t> in_f, in_k, in_j;  // [m]
   std::vector<int32_t> out_f, out_k, out_j;
 };
@@ -40,6 +41,7 @@ struct DiscDev {
   const double* Q;      // [n_a*n_a]
   const double* T;      // [n_a*nn*nn]
   const double* in_val; // [m]
+  const double* out_val; // [m]
   const int32_t* in_row;
   const int32_t* out_row;
   const int32_t* in_f;
@@ -103,6 +105,8 @@ el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh
                          double* u, double* mean);
 el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
                               const void* in2mean, int op_dtype, const double* trace, double* mean);
+el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* kappa,
+                          void* in2out, const void* in2sol, int op_dtype, const uint8_t* mask);
 el_status launch_mean_l2(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h,
                          const double* a, const double* ref, double* out_host);
 

@@ -38,7 +38,7 @@ el_status get_disc(el_ctx* ctx, const el_disc& d, el_ctx::DiscEntry** out) {
   if (!build_disc(d, de->host, err)) return set_error(ctx, EL_ERR_ARG, "el_disc: " + err);
   const DiscHost& h = de->host;
   // one device allocation: doubles first, then int32 tables
-  size_t nd = h.W.size() + h.Q.size() + h.T.size() + h.in_val.size() + h.sx.size() + h.sy.size();
+  size_t nd = h.W.size() + h.Q.size() + h.T.size() + h.in_val.size() + h.out_val.size() + h.sx.size() + h.sy.size();
   size_t ni = 8 * (size_t)h.m;
   size_t bytes = nd * sizeof(double) + ni * sizeof(int32_t);
   el_status st = hip_check(ctx, hipMalloc(&de->dbuf, bytes), "hipMalloc(disc tables)");
@@ -53,6 +53,7 @@ el_status get_disc(el_ctx* ctx, const el_disc& d, el_ctx::DiscEntry** out) {
   de->view.Q = devd(h.Q.size()); putd(h.Q);
   de->view.T = devd(h.T.size()); putd(h.T);
   de->view.in_val = devd(h.in_val.size()); putd(h.in_val);
+  de->view.out_val = devd(h.out_val.size()); putd(h.out_val);
   de->view.sx = devd(h.sx.size()); putd(h.sx);
   de->view.sy = devd(h.sy.size()); putd(h.sy);
   int32_t* ip = reinterpret_cast<int32_t*>(dp);
@@ -275,6 +276,18 @@ el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2m
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
   return launch_recover_mean(ctx, de, mesh, in2mean, op_dtype, trace, mean);
+}
+
+el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa, void* in2out,
+                      const void* in2sol, int op_dtype, const uint8_t* mask) {
+  if (!ctx) return EL_ERR_ARG;
+  if (E <= 0 || !h || !kappa || !in2out || !in2sol || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
+    return set_error(ctx, EL_ERR_ARG, "el_conserve: bad argument");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_conserve(ctx, de, E, h, kappa, in2out, in2sol, op_dtype, mask);
 }
 
 el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* a,

@@ -151,7 +151,65 @@ __global__ void k_l2_partial(const double* __restrict__ W, int nn, int64_t E, co
   }
 }
 
+template <typename T> __device__ inline double ld_op(const T* p, int64_t i);
+template <> __device__ inline double ld_op<double>(const double* p, int64_t i) { return p[i]; }
+template <> __device__ inline double ld_op<float>(const float* p, int64_t i) { return (double)p[i]; }
+template <> __device__ inline double ld_op<uint16_t>(const uint16_t* p, int64_t i) {
+  return (double)__uint_as_float(((uint32_t)p[i]) << 16);
+}
+template <typename T> __device__ inline void st_op(T* p, int64_t i, double v);
+template <> __device__ inline void st_op<double>(double* p, int64_t i, double v) { p[i] = v; }
+template <> __device__ inline void st_op<float>(float* p, int64_t i, double v) { p[i] = (float)v; }
+template <> __device__ inline void st_op<uint16_t>(uint16_t* p, int64_t i, double v) {
+  uint32_t u = __float_as_uint((float)v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  p[i] = (uint16_t)(u >> 16);
+}
+
+// Energy balance of one element, column by column: sum_o w_o in2out[o][i] +
+// sum_(k,nd) W_nd (h kappa_nd / 2) in2sol[(k,nd)][i] = w_i.  Each column of
+// in2out is rescaled so that the balance holds exactly (elements with
+// mask == 0 are left alone).
+template <typename T>
+__global__ void k_conserve(DiscDev dv, int64_t E, const double* __restrict__ h, const double* __restrict__ kappa,
+                           T* __restrict__ i2o, const T* __restrict__ i2s, const uint8_t* __restrict__ mask) {
+  const int64_t e = blockIdx.x;
+  if (e >= E || (mask && !mask[e])) return;
+  extern __shared__ double wa[];   // [nn] = W_nd h kappa_nd / 2
+  const int nn = dv.nn, m = dv.m, n = dv.n;
+  for (int nd = threadIdx.x; nd < nn; nd += blockDim.x) wa[nd] = dv.W[nd] * 0.5 * h[e] * kappa[e * nn + nd];
+  __syncthreads();
+  const T* S = i2s + (size_t)e * n * m;
+  T* O = i2o + (size_t)e * m * m;
+  for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    double absorb = 0.0;
+    for (int r = 0; r < n; ++r) absorb += wa[r % nn] * ld_op<T>(S, (int64_t)r * m + c);
+    double out = 0.0;
+    for (int o = 0; o < m; ++o) out += dv.out_val[o] * ld_op<T>(O, (int64_t)o * m + c);
+    const double target = dv.in_val[c] - absorb;
+    if (out > 0.0 && target > 0.0) {
+      const double s = target / out;
+      for (int o = 0; o < m; ++o) st_op<T>(O, (int64_t)o * m + c, s * ld_op<T>(O, (int64_t)o * m + c));
+    }
+  }
+}
+
 }  // namespace
+
+el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* kappa,
+                          void* in2out, const void* in2sol, int op_dtype, const uint8_t* mask) {
+  const size_t smem = sizeof(double) * de->host.nn;
+  if (op_dtype == EL_F64)
+    hipLaunchKernelGGL(k_conserve<double>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
+                       reinterpret_cast<double*>(in2out), reinterpret_cast<const double*>(in2sol), mask);
+  else if (op_dtype == EL_F32)
+    hipLaunchKernelGGL(k_conserve<float>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
+                       reinterpret_cast<float*>(in2out), reinterpret_cast<const float*>(in2sol), mask);
+  else
+    hipLaunchKernelGGL(k_conserve<uint16_t>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
+                       reinterpret_cast<uint16_t*>(in2out), reinterpret_cast<const uint16_t*>(in2sol), mask);
+  return hip_check(ctx, hipGetLastError(), "launch k_conserve");
+}
 
 el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const void* in2sol,
                          int op_dtype, const double* trace, double* u, double* mean) {

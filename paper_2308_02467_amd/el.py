@@ -94,6 +94,8 @@ _SIGS = {
                         ctypes.c_void_p],
     "el_mean_l2": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                    ctypes.POINTER(ctypes.c_double)],
+    "el_conserve": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
     "el_net_create": [ctypes.c_void_p, ctypes.POINTER(el_net_desc), ctypes.POINTER(ctypes.c_void_p)],
     "el_net_destroy": [ctypes.c_void_p],
     "el_net_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
@@ -301,6 +303,18 @@ class Context:
         return self._check(lib().el_recover_mean(self.h, d, ms, _ptr(in2mean, name="in2mean"), _op_dtype(in2mean),
                                                  _ptr(trace, torch.float64, trace_size(d, ms), "trace"),
                                                  _ptr(mean, torch.float64, E * nn, "mean")))
+
+    def el_conserve(self, d, h, kappa, in2out, in2sol, mask=None):
+        nn, n, m = disc_sizes(d)
+        E = h.numel()
+        dt = _op_dtype(in2out)
+        if _op_dtype(in2sol) != dt:
+            raise ValueError("in2out and in2sol must share one dtype")
+        return self._check(lib().el_conserve(self.h, d, E, _ptr(h, torch.float64, E, "h"),
+                                             _ptr(kappa, torch.float64, E * nn, "kappa"),
+                                             _ptr(in2out, numel=E * m * m, name="in2out"),
+                                             _ptr(in2sol, numel=E * n * m, name="in2sol"), dt,
+                                             _ptr(mask, torch.uint8, E, "mask")))
 
     def el_mean_l2(self, d, h, a, ref):
         nn, _, _ = disc_sizes(d)

@@ -40,8 +40,10 @@ def training_set(ctx, d, N, seed=1234, chunk=8192, log=True):
     return x, y
 
 
-def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=None):
-    """Adam on the MAE loss; returns the per-epoch mean loss (normalized units)."""
+def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=None, decay_at=0.0):
+    """Adam on the MAE loss; returns the per-epoch mean loss (normalized units).
+    decay_at in (0, 1): lr is divided by 10 after that fraction of the epochs
+    (or of the time limit), as in the paper's stepwise schedule (Sec. 3.1)."""
     N = x.shape[0]
     nb = N // batch
     rng = np.random.default_rng(seed)
@@ -51,9 +53,12 @@ def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=N
     t0 = time.perf_counter()
     for ep in range(epochs):
         acc.zero_()
+        elapsed = time.perf_counter() - t0
+        late = decay_at > 0 and (ep >= decay_at * epochs or (time_limit and elapsed >= decay_at * time_limit))
+        lr_ep = lr * 0.1 if late else lr
         for b in rng.permutation(nb):
             b0 = int(b) * batch
-            net.train_step(x[b0:b0 + batch], y[b0:b0 + batch], lr, loss)
+            net.train_step(x[b0:b0 + batch], y[b0:b0 + batch], lr_ep, loss)
             acc += loss
         hist.append(acc.item() / nb)
         if log:

@@ -170,3 +170,38 @@ def test_full_size_32x32_sampled_and_energy(ctx):
     ind, outd = oms.element_dofs(od)
     u = gpu["u"]
     assert rel_err(u[:, od.out_rows].reshape(-1), gpu["t"][outd].reshape(-1)) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_conserve_energy_balance(ctx, dtype):
+    """el_conserve leaves exact operators unchanged (they already satisfy the
+    per-element energy balance) and restores the balance of perturbed ones."""
+    from paper_2308_02467_amd import el
+    p, n_a = 3, 8
+    o = LocalDisc(p, n_a)
+    h, kap, sig = inputs.training_draws(20, o.xi, seed=4)
+    i2o, i2s, _ = local_solve_batch(o, h, kap, sig)
+    d = el.disc(p, n_a)
+    wout = np.array([o.omega[j] * o.sn[k, f] for (f, k, j, nd, r) in o.out_tab])
+    win = np.array([-o.omega[j] * o.sn[k, f] for (f, k, j, nd, r) in o.in_tab])
+
+    def balance(O, S):
+        ab = np.einsum("n,enm->em", np.tile(o.W, n_a), (0.5 * h[:, None, None] * np.tile(kap, (1, n_a))[:, :, None]) * S)
+        return np.einsum("o,eom->em", wout, O) + ab - win[None, :]
+
+    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    O = T(i2o).to(dtype)
+    S = T(i2s).to(dtype)
+    print(f"[el_conserve] {dtype}", flush=True)
+    ctx.el_conserve(d, T(h), T(kap), O, S)
+    assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= (1e-13 if dtype == torch.float64 else 1e-6)
+    rng = np.random.default_rng(0)
+    Op = T(i2o * (1 + 0.02 * rng.standard_normal(i2o.shape))).to(dtype)
+    mask = torch.ones(20, dtype=torch.uint8, device=DEV)
+    mask[5] = 0
+    ctx.el_conserve(d, T(h), T(kap), Op, S, mask)
+    got = Op.to(torch.float64).cpu().numpy()
+    bal = balance(got, S.to(torch.float64).cpu().numpy())
+    keep = np.arange(20) != 5
+    assert np.abs(bal[keep]).max() <= tol * np.abs(win).max()
+    assert np.abs(bal[5]).max() > 1e-4            # masked element untouched
