@@ -158,8 +158,9 @@ el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2o
                           int op_dtype, const double* x, double* y);
 
 /* Solve (I - P) t = b for n_mesh independent meshes with restarted GMRES
- * (Sec. 2.3): x0 = 0, classical Gram-Schmidt applied twice, Givens
- * rotations, FP64 vectors and reductions.  Stops a mesh when its true
+ * (Sec. 2.3): x0 = 0, classical Gram-Schmidt with DGKS reorthogonalization
+ * (second pass when the norm drops below 1/sqrt(2)), Givens rotations, FP64
+ * vectors and reductions.  Stops a mesh when its true
  * relative residual <= opts->tol.  in2out, b, trace: host arrays of n_mesh
  * device pointers.  rep: host [n_mesh].  Returns EL_WARN_NOT_CONVERGED if
  * any mesh did not reach tol within max_iter. */

@@ -206,13 +206,16 @@ struct EpiF32 {
 template <bool A_KC, bool B_KC, typename Epi>
 __global__ void __launch_bounds__(gemm::kThreads) k_mm(const uint16_t* __restrict__ A, int64_t lda,
                                                         const uint16_t* __restrict__ B, int64_t ldb, int M, int N,
-                                                        int K, int k_split, Epi epi) {
+                                                        int K, int k_split, int m_fast, Epi epi) {
   using namespace gemm;
   __shared__ __align__(16) uint16_t As[2][BM * PITCH];
   __shared__ __align__(16) uint16_t Bs[2][BN * PITCH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // m_fast: consecutive workgroups walk down M for a fixed N tile, so one
+  // panel of B (the large weight matrix) is read once while the small A
+  // operand stays cache resident
+  const int m0 = (m_fast ? blockIdx.x : blockIdx.y) * BM, n0 = (m_fast ? blockIdx.y : blockIdx.x) * BN;
   const int kb = blockIdx.z * k_split;
   const int ke = min(K, kb + k_split);
   f32x4 acc[4][4];
@@ -261,28 +264,39 @@ __global__ void __launch_bounds__(gemm::kThreads) k_mm(const uint16_t* __restric
 
 template <bool A_KC, bool B_KC, typename Epi>
 el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M, int64_t N,
-             int64_t K, int splits, Epi epi) {
+             int64_t K, int splits, Epi epi, bool m_fast = false) {
   if (M <= 0 || N <= 0) return EL_OK;
   int64_t ks = (K + splits - 1) / splits;
   ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
   const int nz = (int)((K + ks - 1) / ks);
-  dim3 grid((unsigned)((N + gemm::BN - 1) / gemm::BN), (unsigned)((M + gemm::BM - 1) / gemm::BM), (unsigned)nz);
+  const unsigned tm = (unsigned)((M + gemm::BM - 1) / gemm::BM), tn = (unsigned)((N + gemm::BN - 1) / gemm::BN);
+  dim3 grid(m_fast ? tm : tn, m_fast ? tn : tm, (unsigned)nz);
   hipLaunchKernelGGL((k_mm<A_KC, B_KC, Epi>), grid, dim3(gemm::kThreads), 0, ctx->stream, A, lda, B, ldb, (int)M,
-                     (int)N, (int)K, (int)ks, epi);
+                     (int)N, (int)K, (int)ks, (int)m_fast, epi);
   return hip_check(ctx, hipGetLastError(), "launch k_mm");
 }
 
-// out[n] = sum_b X[b][n] (X bfloat16 or float)
+// out[n] = sum_b X[b][n] (X bfloat16 or float).  256 threads = 16 columns x
+// 16 row groups; fixed summation order (deterministic).
 template <typename T>
 __global__ void k_colsum(const T* __restrict__ X, int64_t B, int64_t N, float* __restrict__ out) {
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+  __shared__ float part[16][17];
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t n = (int64_t)blockIdx.x * 16 + c;
   float acc = 0.f;
-  for (int64_t b = 0; b < B; ++b) {
-    if constexpr (sizeof(T) == 2) acc += bf2f(X[b * N + n]);
-    else acc += X[b * N + n];
+  if (n < N) {
+    for (int64_t b = g; b < B; b += 16) {
+      if constexpr (sizeof(T) == 2) acc += bf2f(X[b * N + n]);
+      else acc += X[b * N + n];
+    }
   }
-  out[n] = acc;
+  part[g][c] = acc;
+  __syncthreads();
+  if (g == 0 && n < N) {
+    float t = 0.f;
+    for (int i = 0; i < 16; ++i) t += part[i][c];
+    out[n] = t;
+  }
 }
 
 // dZ = (sum_s P[s]) * act'(Z); writes FP32 and bfloat16
@@ -733,7 +747,7 @@ el_status el_net_forward(el_ctx* ctx, const el_net* cnet, int64_t B, const float
   const int64_t W = net->desc.width;
   EpiOutNorm epi{net->theta + net->b_off[D], y_norm, net->desc.n_out};
   return mm<true, true>(ctx, s.H + (size_t)(D - 1) * B * W, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1,
-                        epi);
+                        epi, true);
 }
 
 el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, const uint16_t* y, float lr,
@@ -755,10 +769,10 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
   hipLaunchKernelGGL(k_fill_f, dim3(1), dim3(64), 0, str, s.loss, (int64_t)1, 0.f);
   const uint16_t* Hlast = s.H + (size_t)(D - 1) * B * W;
   EpiMAE mae{net->theta + net->b_off[D], y, net->y_mean, net->y_std, s.dY, s.loss, nout, 0.f};
-  st = mm<true, true>(ctx, Hlast, W, net->wbf + net->w_off[D], W, B, nout, W, 1, mae);
+  st = mm<true, true>(ctx, Hlast, W, net->wbf + net->w_off[D], W, B, nout, W, 1, mae, true);
   if (st) return st;
   // output layer gradients
-  hipLaunchKernelGGL(k_colsum<uint16_t>, dim3(nblk(nout)), dim3(256), 0, str, s.dY, B, nout, net->grad + net->b_off[D]);
+  hipLaunchKernelGGL(k_colsum<uint16_t>, dim3(nblk(nout, 16)), dim3(256), 0, str, s.dY, B, nout, net->grad + net->b_off[D]);
   st = mm<false, false>(ctx, s.dY, nout, Hlast, W, nout, W, B, 1, EpiF32{net->grad + net->w_off[D], W, 0});
   if (st) return st;
   st = mm<true, false>(ctx, s.dY, nout, net->wbf + net->w_off[D], W, B, W, nout, kSplitOut,
@@ -774,7 +788,7 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
   for (int l = D - 1; l >= 0; --l) {
     const int64_t in = net->in_dim[l];
     const uint16_t* X = l == 0 ? s.X0 : s.H + (size_t)(l - 1) * B * W;
-    hipLaunchKernelGGL(k_colsum<float>, dim3(nblk(W)), dim3(256), 0, str, s.dZ, B, W, net->grad + net->b_off[l]);
+    hipLaunchKernelGGL(k_colsum<float>, dim3(nblk(W, 16)), dim3(256), 0, str, s.dZ, B, W, net->grad + net->b_off[l]);
     st = mm<false, false>(ctx, s.dZ16, W, X, in, W, in, B, kSplitW, EpiF32{s.part, in, W * in});
     if (st) return st;
     {
@@ -848,11 +862,11 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
     if (out_dtype == EL_F32) {
       EpiOutOps<float> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<float*>(po),
                            reinterpret_cast<float*>(ps), mm_, nm};
-      st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi);
+      st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi, true);
     } else {
       EpiOutOps<uint16_t> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<uint16_t*>(po),
                               reinterpret_cast<uint16_t*>(ps), mm_, nm};
-      st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi);
+      st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi, true);
     }
     if (st) break;
   }

@@ -9,11 +9,12 @@
 // DOF is written by its unique upwind element (no atomics).  Domain-inflow
 // DOFs are copied through by the boundary element that sees them.
 //
-// GMRES(restart): x0 = 0, classical Gram-Schmidt applied twice (the update of
-// the first pass is fused with the dot products of the second, the update of
-// the second with the norm), Givens rotations on the host from the scalars of
-// each step, true residual checked at every restart.  Vectors and reductions
-// are FP64.
+// GMRES(restart): x0 = 0, classical Gram-Schmidt with the DGKS
+// reorthogonalization test (a second pass only when the norm of the new
+// vector drops below 1/sqrt(2) of its value before the projection; the norms
+// are fused into the dot-product and update passes), Givens rotations on the
+// host from the scalars of each step, true residual checked at every
+// restart.  Vectors and reductions are FP64.
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -200,9 +201,10 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// partials[blk][i] = sum over the block chunk of V[i] . w, i < cnt
+// partials[blk][i] = sum over the block chunk of V[i] . w, i < cnt; with
+// self_dot also partials[blk][cnt] = w . w
 __global__ void __launch_bounds__(kVThreads) k_mdot(const double* __restrict__ V, int64_t ldv, int cnt,
-                                                     const double* __restrict__ w, int64_t n,
+                                                     const double* __restrict__ w, int64_t n, int self_dot,
                                                      double* __restrict__ partials) {
   __shared__ double s[kVThreads / 64][kMaxCnt];
   const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x;
@@ -224,11 +226,19 @@ __global__ void __launch_bounds__(kVThreads) k_mdot(const double* __restrict__ V
     acc = wave_sum(acc);
     if (lane == 0) s[wave][i] = acc;
   }
+  if (self_dot) {
+    double acc = 0.0;
+#pragma unroll
+    for (int v = 0; v < kVec; ++v) acc += wr[v] * wr[v];
+    acc = wave_sum(acc);
+    if (lane == 0) s[wave][cnt] = acc;
+  }
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += kVThreads) {
+  const int outc = cnt + (self_dot ? 1 : 0);
+  for (int i = threadIdx.x; i < outc; i += kVThreads) {
     double t = 0.0;
     for (int wv = 0; wv < kVThreads / 64; ++wv) t += s[wv][i];
-    partials[(size_t)blockIdx.x * cnt + i] = t;
+    partials[(size_t)blockIdx.x * outc + i] = t;
   }
 }
 
@@ -362,10 +372,10 @@ struct Gm {
 
   el_status err(const char* what) { return hip_check(ctx, hipGetLastError(), what); }
 
-  // out_dev[0..cnt) = V[0..cnt) . w
-  el_status mdot(const double* V, int64_t ldv, int cnt, const double* w, double* out_dev) {
-    hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(kVThreads), 0, s, V, ldv, cnt, w, n, partials);
-    hipLaunchKernelGGL(k_reduce, dim3(cnt), dim3(256), 0, s, partials, nblk, cnt, out_dev);
+  // out_dev[0..cnt) = V[0..cnt) . w; with self_dot also out_dev[cnt] = w . w
+  el_status mdot(const double* V, int64_t ldv, int cnt, const double* w, double* out_dev, int self_dot = 0) {
+    hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(kVThreads), 0, s, V, ldv, cnt, w, n, self_dot, partials);
+    hipLaunchKernelGGL(k_reduce, dim3(cnt + self_dot), dim3(256), 0, s, partials, nblk, cnt + self_dot, out_dev);
     return err("gmres mdot");
   }
   // w -= sign * V h; then dots (mode 0) or norm^2 (mode 1) into out_dev
@@ -404,7 +414,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
     const unsigned nb256 = blocks_for(N, 256);
     hipLaunchKernelGGL(k_fill_d, dim3(nb256), dim3(256), 0, s, x, N, 0.0);
     // ||b||
-    st = g.mdot(b[mi], 0, 1, b[mi], g.hdev);
+    st = g.mdot(b[mi], 0, 1, b[mi], g.hdev, 0);
     if (st) return st;
     double bnorm2 = 0.0;
     hipMemcpyAsync(&bnorm2, g.hdev, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -431,7 +441,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
         if (st) return st;
         hipLaunchKernelGGL(k_sub, dim3(nb256), dim3(256), 0, s, b[mi], tmp, V, N);
       }
-      st = g.mdot(V, 0, 1, V, g.hdev);
+      st = g.mdot(V, 0, 1, V, g.hdev, 0);
       if (st) return st;
       double beta2 = 0.0;
       hipMemcpyAsync(&beta2, g.hdev, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -455,21 +465,35 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
         st = launch_trace_matvec(ctx, de, mesh, in2out[mi], op_dtype, V + (size_t)j * N, vj1);
         if (st) return st;
         const int cnt = j + 1;
-        double* h1 = g.hdev;
+        double* h1 = g.hdev;                    // [cnt] coefficients, [cnt] = ||w||^2 before
         double* h2 = g.hdev + kMaxCnt;
         double* nrm = g.hdev + 2 * kMaxCnt;
-        st = g.mdot(V, N, cnt, vj1, h1);
+        // classical Gram-Schmidt, one pass; a second pass when the norm drops
+        // below 1/sqrt(2) of its value before the projection (DGKS criterion)
+        st = g.mdot(V, N, cnt, vj1, h1, 1);
         if (st) return st;
-        st = g.update(V, N, cnt, h1, vj1, 1.0, 0, h2);
+        st = g.update(V, N, cnt, h1, vj1, 1.0, 1, nrm);
         if (st) return st;
-        st = g.update(V, N, cnt, h2, vj1, 1.0, 1, nrm);
-        if (st) return st;
-        hipMemcpyAsync(hh.data(), g.hdev, sizeof(double) * (2 * kMaxCnt + 1), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(hh.data(), h1, sizeof(double) * (cnt + 1), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(hh.data() + kMaxCnt, nrm, sizeof(double), hipMemcpyDeviceToHost, s);
         st = hip_check(ctx, hipStreamSynchronize(s), "gmres step");
         if (st) return st;
         double* Hc = H.data();  // column-major: H[i + j*(R+1)]
-        for (int i = 0; i <= j; ++i) Hc[i + (size_t)j * (R + 1)] = hh[i] + hh[kMaxCnt + i];
-        const double hn = std::sqrt(std::max(hh[2 * kMaxCnt], 0.0));
+        for (int i = 0; i <= j; ++i) Hc[i + (size_t)j * (R + 1)] = hh[i];
+        const double w0 = std::sqrt(std::max(hh[cnt], 0.0));
+        double hn = std::sqrt(std::max(hh[kMaxCnt], 0.0));
+        if (hn < 0.70710678118654752 * w0) {
+          st = g.mdot(V, N, cnt, vj1, h2, 0);
+          if (st) return st;
+          st = g.update(V, N, cnt, h2, vj1, 1.0, 1, nrm);
+          if (st) return st;
+          hipMemcpyAsync(hh.data(), h2, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
+          hipMemcpyAsync(hh.data() + kMaxCnt, nrm, sizeof(double), hipMemcpyDeviceToHost, s);
+          st = hip_check(ctx, hipStreamSynchronize(s), "gmres reorthogonalization");
+          if (st) return st;
+          for (int i = 0; i <= j; ++i) Hc[i + (size_t)j * (R + 1)] += hh[i];
+          hn = std::sqrt(std::max(hh[kMaxCnt], 0.0));
+        }
         Hc[j + 1 + (size_t)j * (R + 1)] = hn;
         if (hn > 0.0) hipLaunchKernelGGL(k_scale, dim3(nb256), dim3(256), 0, s, vj1, N, 1.0 / hn);
         for (int i = 0; i < j; ++i) {
