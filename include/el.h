@@ -95,6 +95,8 @@ typedef struct {
   double tol;     /* relative residual ||b - (I-P)x|| / ||b|| */
   int restart;    /* Krylov dimension per cycle, 1..256 */
   int max_iter;   /* total Arnoldi steps */
+  int graph;      /* 1: replay each restart cycle as a captured HIP graph;
+                     0: launch its kernels one by one (same kernels, same results) */
 } el_gmres_opts;
 
 typedef struct {
@@ -157,13 +159,19 @@ el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_sid
 el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out,
                           int op_dtype, const double* x, double* y);
 
-/* Solve (I - P) t = b for n_mesh independent meshes with restarted GMRES
- * (Sec. 2.3): x0 = 0, classical Gram-Schmidt with DGKS reorthogonalization
- * (second pass when the norm drops below 1/sqrt(2)), Givens rotations, FP64
- * vectors and reductions.  Stops a mesh when its true
- * relative residual <= opts->tol.  in2out, b, trace: host arrays of n_mesh
- * device pointers.  rep: host [n_mesh].  Returns EL_WARN_NOT_CONVERGED if
- * any mesh did not reach tol within max_iter. */
+/* Solve (I - P) t = b for n_mesh independent meshes of any sizes together
+ * with restarted GMRES (Sec. 2.3): x0 = 0, classical Gram-Schmidt with DGKS
+ * reorthogonalization (second pass when the norm drops below 1/sqrt(2)),
+ * Givens rotations, FP64 vectors and reductions.  All meshes share every
+ * launch; the Arnoldi scalars stay on the device and the host synchronizes
+ * once per restart cycle.  A mesh stops when its true relative residual
+ * <= opts->tol (checked at each cycle start) or after max_iter steps.
+ * in2out, b, trace: host arrays of n_mesh device pointers (all operators
+ * of one op_dtype).  rep: host [n_mesh].  Returns EL_WARN_NOT_CONVERGED if
+ * any mesh did not reach tol within max_iter, EL_ERR_NONFINITE (mesh named)
+ * for a non-finite right-hand side or residual.  The workspace holds
+ * (restart + 4) concatenated trace vectors.  Calls on one context must not
+ * overlap (the captured cycle and the workspace are per context). */
 el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* meshes_host,
                          const void* const* in2out, int op_dtype,
                          const double* const* b, double* const* trace,

@@ -79,6 +79,10 @@ struct el_ctx {
   el::Workspace ws_gmres;    // Krylov basis and scratch
   el::Workspace ws_small;    // flags, reductions
   int num_cus = 256;
+  // captured GMRES restart cycle (rebuilt when the batch shape changes)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gm_exec = nullptr;
+  std::string gm_key;
 };
 
 namespace el {

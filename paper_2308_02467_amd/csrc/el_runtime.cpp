@@ -123,6 +123,8 @@ el_status el_destroy(el_ctx* ctx) {
   if (!ctx) return EL_OK;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  if (ctx->gm_exec) hipGraphExecDestroy(ctx->gm_exec);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   for (auto& kv : ctx->discs) hipFree(kv.second->dbuf);
   hipFree(ctx->ws_local.ptr);
   hipFree(ctx->ws_gmres.ptr);

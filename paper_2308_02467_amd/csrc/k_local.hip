@@ -14,18 +14,25 @@
 //    transport blocks B_k - C_k plus the node-diagonal M and S terms;
 //  * row interchanges never move data in HBM: factor rows stay at their
 //    physical (original) row and a permutation perm[logical] = physical is
-//    kept in LDS, so reading the factors through perm gives the
-//    LAPACK-ordered L and U;
-//  * the block updates pan[I+16:] -= L[I+16:, I] * U[I, panel] run on the
-//    FP64 matrix cores (v_mfma_f64_16x16x4f64), L streamed from HBM, U and
-//    the panel from LDS; triangular diagonal blocks are applied as products
-//    with their precomputed inverses (also on the matrix cores);
+//    kept in LDS;
+//  * each factor panel is stored pre-multiplied by the inverse of its
+//    diagonal block and negated (-L inv(L_II) below, -U inv(U_II) above the
+//    block), so that a block sweep step is a single rank-16 update
+//        rows += F_I pan[I]
+//    with one barrier per step, and the 16x16 diagonal-block solves of a
+//    whole sweep run afterwards, independently, on all waves;
+//  * the sweep updates run on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+//    factor tiles are streamed from HBM two steps ahead of their use with
+//    16-byte loads, the panel tiles are read-modified-written in LDS;
 //  * the right-hand side -B_hat (one nonzero per column) is generated in
-//    panels of 16 columns, forward-substituted (skipping the leading zero
-//    blocks) and back-substituted in LDS, and the solution panel is written
-//    straight to in2sol / in2out / in2mean.
+//    panels of 16 columns, forward-swept (skipping the leading zero blocks)
+//    and back-swept, and the solution panel is written straight to in2sol /
+//    in2out / in2mean (FP64, FP32 or bfloat16).
+// With NB = 16 each factor byte feeds 4 flops, so the sweeps are bound by
+// HBM bandwidth rather than by the matrix cores.
 #include <climits>
 #include <cstdio>
+#include <cstdlib>
 #include <sstream>
 
 #include "el_internal.h"
@@ -105,8 +112,8 @@ __device__ inline T amat(const DiscDev& dv, const double* tau_e, const double* t
   return (T)v;
 }
 
-// pan[I..I+16) = Tinv * pan[I..I+16), Tinv a 16x16 block in global memory
-// (row-major).  Executed by one wave.
+// pan[I..I+16) = Tinv * pan[I..I+16), Tinv a 16x16 block (row-major).
+// Executed by one wave.
 template <typename T>
 __device__ inline void tri_apply(T* pan, const T* tinv, int I, int lane) {
   typedef typename Acc<T>::type A4;
@@ -115,8 +122,8 @@ __device__ inline void tri_apply(T* pan, const T* tinv, int I, int lane) {
   T a[4], b[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
-    a[kk] = tinv[li * NB + 4 * kk + lk];
-    b[kk] = pan[(I + 4 * kk + lk) * LDP + li];
+    a[kk] = tinv[li * NB + 4 * lk + kk];
+    b[kk] = pan[(I + 4 * lk + kk) * LDP + li];
   }
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) c = mfma16(a[kk], b[kk], c);
@@ -124,84 +131,240 @@ __device__ inline void tri_apply(T* pan, const T* tinv, int I, int lane) {
   for (int r = 0; r < 4; ++r) pan[(I + Acc<T>::row(lk, r)) * LDP + li] = c[r];
 }
 
-// pan[rows of tiles t in [t_begin, t_end)] -= F[perm[row]][0..16) * pan[I..I+16)
-// F = one factor panel (physical rows, 16 columns), read from HBM.
+// pan[I] = inv_I pan[I] for the 16-row blocks I in [tb, te), spread over the
+// waves (the blocks are independent).  which = 0: unit-lower inverse,
+// 1: upper inverse.
 template <typename T>
-__device__ inline void block_update(T* pan, const T* __restrict__ F, const int* perm, int I,
-                                    int t_begin, int t_end, int wave, int lane) {
+__device__ inline void transform_blocks(T* pan, const T* inv, int which, int tb, int te, int wave, int lane) {
+  for (int t = tb + wave; t < te; t += kWaves) tri_apply<T>(pan, inv + (size_t)t * 2 * NB * NB + which * NB * NB, 16 * t, lane);
+}
+
+// Address-space-qualified pointers for the out-of-line sweep: without them
+// its pointer arguments are generic and every access becomes a FLAT
+// instruction, whose completion the LDS wait counter also tracks.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+
+__device__ inline uintptr_t uniform_ptr(uintptr_t p) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+  return ((uintptr_t)hi << 32) | lo;
+}
+
+// ---- block sweeps ---------------------------------------------------------------
+//
+// Tile t (rows 16t..16t+16 of the LDS panel) belongs to wave w for the whole
+// sweep, in slot u:
+//     forward:  t = npan - 1 - (w + kWaves u)      backward:  t = w + kWaves u
+// so that the tiles updated at any step are a prefix of every wave's slots
+// (forward steps update the tiles below the current block, backward steps
+// the tiles above it).  A step is straight-line code for a known number of
+// slots (one uniform switch): read two tiles from LDS, run their MFMA chains
+// interleaved, write them back.  The factor tiles (A operands, from HBM) are
+// loaded two steps ahead into two register buffers, the same number of loads
+// every step so that the compiler's waits are exact.
+
+template <typename T, int MAXT>
+struct FBuf {
+  T f[MAXT][4];
+};
+
+// B-operand values of a 16x16 block stored row-major with row stride ld
+template <typename T, typename P>
+__device__ inline void load_b(T (&b)[4], P blk, int ld, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) b[kk] = blk[(4 * lk + kk) * ld + li];
+}
+
+
+struct SweepGeom {
+  int npan, wave, nslots;
+  bool down;
+  __device__ int tile(int u) const { return down ? npan - 1 - (wave + kWaves * u) : wave + kWaves * u; }
+  // slots updated by the step at block I
+  __device__ int active(int I) const {
+    if (down) {
+      const int top = npan - 1 - (I / NB + 1) - wave;   // t >= I/16 + 1
+      return top < 0 ? 0 : min(nslots, top / kWaves + 1);
+    }
+    const int te = I / NB;                             // t < I/16
+    return te <= wave ? 0 : min(nslots, (te - 1 - wave) / kWaves + 1);
+  }
+};
+
+// pan[tile(u)] += F.f[u] b for u < N, two tiles at a time
+template <typename T, int MAXT, int N>
+__device__ inline void apply_n(lptr<T> pan, const SweepGeom& g, const FBuf<T, MAXT>& F, const T (&b)[4], int lane) {
   typedef typename Acc<T>::type A4;
   const int li = lane & 15, lk = lane >> 4;
-  T b[4];
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) b[kk] = pan[(I + 4 * kk + lk) * LDP + li];
-  int t = t_begin + wave;
-  // two tiles per iteration to keep more loads in flight
-  for (; t + kWaves < t_end; t += 2 * kWaves) {
-    const int t2 = t + kWaves;
-    const T* r0 = F + (size_t)perm[16 * t + li] * NB + lk;
-    const T* r1 = F + (size_t)perm[16 * t2 + li] * NB + lk;
-    T a0[4], a1[4];
+  for (int u0 = 0; u0 < N; u0 += 2) {
+    const int nu = (u0 + 1 < N) ? 2 : 1;
+    A4 c[2];
+    int base[2];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) { a0[kk] = -r0[4 * kk]; a1[kk] = -r1[4 * kk]; }
-    A4 c0, c1;
+    for (int v = 0; v < 2; ++v) {
+      if (v < nu) {
+        base[v] = 16 * g.tile(u0 + v) * LDP + li;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      c0[r] = pan[(16 * t + Acc<T>::row(lk, r)) * LDP + li];
-      c1[r] = pan[(16 * t2 + Acc<T>::row(lk, r)) * LDP + li];
+        for (int r = 0; r < 4; ++r) c[v][r] = pan[base[v] + Acc<T>::row(lk, r) * LDP];
+      }
     }
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) { c0 = mfma16(a0[kk], b[kk], c0); c1 = mfma16(a1[kk], b[kk], c1); }
+    for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      pan[(16 * t + Acc<T>::row(lk, r)) * LDP + li] = c0[r];
-      pan[(16 * t2 + Acc<T>::row(lk, r)) * LDP + li] = c1[r];
+      for (int v = 0; v < 2; ++v)
+        if (v < nu) c[v] = mfma16(F.f[u0 + v][kk], b[kk], c[v]);
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      if (v < nu) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pan[base[v] + Acc<T>::row(lk, r) * LDP] = c[v][r];
+      }
     }
   }
-  if (t < t_end) {
-    const T* r0 = F + (size_t)perm[16 * t + li] * NB + lk;
-    T a0[4];
+}
+
+template <typename T, int MAXT>
+__device__ inline void apply_active(lptr<T> pan, const SweepGeom& g, const FBuf<T, MAXT>& F, const T (&b)[4], int na,
+                                    int lane) {
+  switch (na) {
+    case 1: apply_n<T, MAXT, 1>(pan, g, F, b, lane); break;
+    case 2: if constexpr (MAXT >= 2) apply_n<T, MAXT, 2>(pan, g, F, b, lane); break;
+    case 3: if constexpr (MAXT >= 3) apply_n<T, MAXT, 3>(pan, g, F, b, lane); break;
+    case 4: if constexpr (MAXT >= 4) apply_n<T, MAXT, 4>(pan, g, F, b, lane); break;
+    case 5: if constexpr (MAXT >= 5) apply_n<T, MAXT, 5>(pan, g, F, b, lane); break;
+    case 6: if constexpr (MAXT >= 6) apply_n<T, MAXT, 6>(pan, g, F, b, lane); break;
+    case 7: if constexpr (MAXT >= 7) apply_n<T, MAXT, 7>(pan, g, F, b, lane); break;
+    case 8: if constexpr (MAXT >= 8) apply_n<T, MAXT, 8>(pan, g, F, b, lane); break;
+    case 9: if constexpr (MAXT >= 9) apply_n<T, MAXT, 9>(pan, g, F, b, lane); break;
+    case 10: if constexpr (MAXT >= 10) apply_n<T, MAXT, 10>(pan, g, F, b, lane); break;
+    case 11: if constexpr (MAXT >= 11) apply_n<T, MAXT, 11>(pan, g, F, b, lane); break;
+    case 12: if constexpr (MAXT >= 12) apply_n<T, MAXT, 12>(pan, g, F, b, lane); break;
+    case 13: if constexpr (MAXT >= 13) apply_n<T, MAXT, 13>(pan, g, F, b, lane); break;
+    default: break;
+  }
+}
+
+// F.f[u] = factor rows of tile(u) for the first na slots (16-byte loads: lane
+// (i, lk) holds columns 4 lk .. 4 lk + 3 of row i, the k order used by every
+// MFMA in this file)
+template <typename T, int MAXT>
+__device__ inline void load_f(FBuf<T, MAXT>& F, gptr<T> fp, lptr<const int> perm, const SweepGeom& g, int na,
+                              int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  // Every slot is loaded (slots past na repeat slot 0's rows, which are then
+  // in cache) so that each step issues the same number of loads and the
+  // waits before a step's MFMAs cover only that step's tiles.  Row indices
+  // first, then the loads from the uniform base with 32-bit offsets.
+  uint32_t off[MAXT];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) a0[kk] = -r0[4 * kk];
-    A4 c0;
+  for (int u = 0; u < MAXT; ++u) {
+    const int t = min(max(g.tile(u < na ? u : 0), 0), g.npan - 1);
+    off[u] = (uint32_t)((perm[16 * t + li] * NB + 4 * lk) * (int)sizeof(T));
+  }
+  gptr<char> base = reinterpret_cast<gptr<char>>(fp);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) c0[r] = pan[(16 * t + Acc<T>::row(lk, r)) * LDP + li];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) c0 = mfma16(a0[kk], b[kk], c0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pan[(16 * t + Acc<T>::row(lk, r)) * LDP + li] = c0[r];
+  for (int u = 0; u < MAXT; ++u) {
+    if constexpr (sizeof(T) == 8) {
+      typedef double dv2 __attribute__((ext_vector_type(2)));
+      const dv2 v0 = *reinterpret_cast<gptr<dv2>>(base + off[u]);
+      const dv2 v1 = *reinterpret_cast<gptr<dv2>>(base + off[u] + 16);
+      F.f[u][0] = v0[0]; F.f[u][1] = v0[1]; F.f[u][2] = v1[0]; F.f[u][3] = v1[1];
+    } else {
+      typedef float fv4 __attribute__((ext_vector_type(4)));
+      const fv4 v = *reinterpret_cast<gptr<fv4>>(base + off[u]);
+      F.f[u][0] = v[0]; F.f[u][1] = v[1]; F.f[u][2] = v[2]; F.f[u][3] = v[3];
+    }
+  }
+}
+
+// Block sweep over the factor panels, one barrier per step.
+//   down:  steps I = I0, I0+16, ..., < Iend:  rows below I+16 += F_I pan[I]
+//          (F_I = -L[:, I] inv(L_II): forward substitution with the
+//          diagonal-block solves deferred to transform_blocks)
+//   !down: steps I = npad-16, ..., 16:        rows above I   += F_I pan[I]
+//          (F_I = -U[:, I] inv(U_II))
+// All threads call it; it ends on a barrier.  Kept out of line so that its
+// registers do not compete with the values live in the caller.
+template <typename T, int MAXT>
+__device__ __attribute__((noinline)) void sweep(T* pan_g, const T* fac_g, const int* perm_g, int npad, int I0,
+                                                int Iend, bool down, int wave, int lane) {
+  // the arguments are wave-uniform: say so, so that the branches below are
+  // scalar (arguments of an out-of-line function arrive in vector registers)
+  wave = __builtin_amdgcn_readfirstlane(wave);
+  I0 = __builtin_amdgcn_readfirstlane(I0);
+  Iend = __builtin_amdgcn_readfirstlane(Iend);
+  npad = __builtin_amdgcn_readfirstlane(npad);
+  down = __builtin_amdgcn_readfirstlane((int)down) != 0;
+  gptr<T> fac = (gptr<T>)uniform_ptr(reinterpret_cast<uintptr_t>(fac_g));
+  lptr<T> pan = (lptr<T>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<T>)pan_g);
+  lptr<const int> perm =
+      (lptr<const int>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<const int>)perm_g);
+  const int npan = npad / NB;
+  const int nsteps = down ? max(0, min(Iend, npad - NB) - I0 + NB - 1) / NB : npan - 1;
+  if (nsteps <= 0) return;
+  SweepGeom g;
+  g.npan = npan;
+  g.wave = wave;
+  g.down = down;
+  g.nslots = wave < npan ? (npan - 1 - wave) / kWaves + 1 : 0;
+  auto I_of = [&](int s) { return down ? I0 + s * NB : npad - NB - s * NB; };
+  auto F_of = [&](int I) { return fac + (size_t)(I / NB) * npad * NB; };
+  // step index clamped to the last step: past the end the last step's tiles
+  // are loaded again (cache hits), keeping the number of loads per step fixed
+  auto I_cl = [&](int s) { return I_of(min(s, nsteps - 1)); };
+  FBuf<T, MAXT> F0, F1;
+  load_f<T, MAXT>(F0, F_of(I_cl(0)), perm, g, g.active(I_cl(0)), lane);
+  load_f<T, MAXT>(F1, F_of(I_cl(1)), perm, g, g.active(I_cl(1)), lane);
+  auto step = [&](int s, FBuf<T, MAXT>& Fb) {
+    const int I = I_of(s);
+    T b[4];
+    load_b<T>(b, pan + I * LDP, LDP, lane);
+    apply_active<T, MAXT>(pan, g, Fb, b, g.active(I), lane);
+    load_f<T, MAXT>(Fb, F_of(I_cl(s + 2)), perm, g, g.active(I_cl(s + 2)), lane);
+    __syncthreads();
+  };
+  for (int s = 0; s < nsteps; s += 2) {
+    step(s, F0);
+    if (s + 1 < nsteps) step(s + 1, F1);
   }
 }
 
 // pan = U^{-1} L^{-1} pan for a right-hand-side panel already in logical
 // (pivoted) row order; the forward sweep starts at block Istart (rows above
-// it are zero).  All threads of the workgroup call this.
-template <typename T>
+// it are zero).  All threads of the workgroup call this; it ends on a barrier.
+template <typename T, int MAXT>
 __device__ inline void panel_solve(T* pan, const T* fac, const T* inv, const int* perm, int npad, int Istart,
                                    int wave, int lane) {
-  for (int I = Istart; I < npad; I += NB) {
-    if (wave == 0) tri_apply<T>(pan, inv + (size_t)(I / NB) * 2 * NB * NB, I, lane);
-    __syncthreads();
-    if (I + NB < npad) {
-      block_update<T>(pan, fac + (size_t)(I / NB) * npad * NB, perm, I, (I + NB) / 16, npad / 16, wave, lane);
-      __syncthreads();
-    }
-  }
-  for (int I = npad - NB; I >= 0; I -= NB) {
-    if (wave == 0) tri_apply<T>(pan, inv + (size_t)(I / NB) * 2 * NB * NB + NB * NB, I, lane);
-    __syncthreads();
-    if (I > 0) {
-      block_update<T>(pan, fac + (size_t)(I / NB) * npad * NB, perm, I, 0, I / 16, wave, lane);
-      __syncthreads();
-    }
-  }
+  const int npan = npad / NB;
+  sweep<T, MAXT>(pan, fac, perm, npad, Istart, npad, true, wave, lane);
+  transform_blocks<T>(pan, inv, 0, Istart / NB, npan, wave, lane);
+  __syncthreads();
+  sweep<T, MAXT>(pan, fac, perm, npad, 0, 0, false, wave, lane);
+  transform_blocks<T>(pan, inv, 1, 0, npan, wave, lane);
+  __syncthreads();
 }
 
 __device__ inline void argmax_combine(double& v, int& i, double v2, int i2) {
   if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
 }
 
+// LDS bytes before the diagonal-block inverses (panel, permutations,
+// coefficients, reduction scratch), rounded up to 16.
 template <typename T>
+__host__ __device__ inline size_t lds_base_bytes(int npad, int nn) {
+  size_t b = sizeof(T) * (size_t)npad * LDP + 2 * sizeof(int) * (size_t)npad + 2 * sizeof(double) * nn +
+             kWaves * (sizeof(double) + sizeof(int)) + 2 * sizeof(int);
+  return (b + 15) / 16 * 16;
+}
+
+template <typename T, int MAXT>
 __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
+  typedef typename Acc<T>::type A4;
   extern __shared__ __align__(16) unsigned char smem[];
   const DiscDev& dv = a.dv;
   const int npad = a.npad, mpad = a.mpad, n = dv.n, m = dv.m, nn = dv.nn;
@@ -214,15 +377,15 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   double* redv = tau_s + nn;                                             // [kWaves]
   int* redi = reinterpret_cast<int*>(redv + kWaves);                     // [kWaves]
   int* sflag = redi + kWaves;                                            // [2]
+  T* sinv = reinterpret_cast<T*>(smem + lds_base_bytes<T>(npad, nn));    // [2][NB][NB]
   // iterative refinement scratch (only allocated when a.xbuf != null)
-  unsigned long long* colmax = reinterpret_cast<unsigned long long*>(
-      smem + ((sizeof(T) * npad * LDP + 2 * sizeof(int) * npad + 2 * sizeof(double) * nn +
-               kWaves * (sizeof(double) + sizeof(int)) + 2 * sizeof(int) + 15) / 16) * 16);   // [NB]
+  unsigned long long* colmax = reinterpret_cast<unsigned long long*>(sinv + 2 * NB * NB);   // [NB]
   double* xs = reinterpret_cast<double*>(colmax + NB);                    // [npad][8]
-  const bool ir = a.xbuf != nullptr;
+  const bool ir = sizeof(T) == 4 && a.xbuf != nullptr;   // refinement only for the FP32 factorization
   double* xg = ir ? a.xbuf + (size_t)blockIdx.x * npad * NB : nullptr;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   T* fac = a.fac + (size_t)blockIdx.x * npan * npad * NB;
   T* inv = a.inv + (size_t)blockIdx.x * npan * 2 * NB * NB;
 
@@ -255,12 +418,10 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         pan[r * LDP + c] = amat<T>(dv, tau_e, tau_s, perm[r], J + c);
       }
       __syncthreads();
-      for (int I = 0; I < J; I += NB) {
-        if (wave == 0) tri_apply<T>(pan, inv + (size_t)(I / NB) * 2 * NB * NB, I, lane);
-        __syncthreads();
-        block_update<T>(pan, fac + (size_t)(I / NB) * npad * NB, perm, I, (I + NB) / 16, npad / 16, wave, lane);
-        __syncthreads();
-      }
+      // left-looking update by the previous panels (their factors are stored
+      // pre-multiplied: -L[:, I] inv(L_II)), then the U rows of this panel
+      sweep<T, MAXT>(pan, fac, perm, npad, 0, J, true, wave, lane);
+      transform_blocks<T>(pan, inv, 0, 0, J / NB, wave, lane);
       // factor rows [J, npad) of the panel with partial pivoting
       double best = -1.0;
       int bidx = INT_MAX;
@@ -328,7 +489,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
           }
           T* o = inv + (size_t)(J / NB) * 2 * NB * NB;
 #pragma unroll
-          for (int i = 0; i < NB; ++i) o[i * NB + j] = x[i];
+          for (int i = 0; i < NB; ++i) { o[i * NB + j] = x[i]; sinv[i * NB + j] = x[i]; }
         } else {
 #pragma unroll
           for (int ii = NB - 1; ii >= 0; --ii) {
@@ -340,15 +501,30 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
           }
           T* o = inv + (size_t)(J / NB) * 2 * NB * NB + NB * NB;
 #pragma unroll
-          for (int i = 0; i < NB; ++i) o[i * NB + j] = x[i];
+          for (int i = 0; i < NB; ++i) { o[i * NB + j] = x[i]; sinv[NB * NB + i * NB + j] = x[i]; }
         }
       }
-      // store the factored panel at the physical rows
+      __syncthreads();
+      // store the factor panel at the physical rows, pre-multiplied and
+      // negated: rows above the diagonal block -U[r, J] inv(U_JJ), rows below
+      // -L[r, J] inv(L_JJ) (the diagonal block itself is kept as inverses)
       {
         T* F = fac + (size_t)(J / NB) * npad * NB;
-        for (int idx = tid; idx < npad * NB; idx += kThreads) {
-          int r = idx >> 4, c = idx & 15;
-          F[(size_t)perm[r] * NB + c] = pan[r * LDP + c];
+        const int li = lane & 15, lk = lane >> 4;
+        for (int t = wave; t < npan; t += kWaves) {
+          if (t == J / NB) continue;
+          const T* Bi = sinv + (t < J / NB ? NB * NB : 0);
+          T av[4], bv[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            av[kk] = pan[(16 * t + li) * LDP + 4 * lk + kk];
+            bv[kk] = Bi[(4 * lk + kk) * NB + li];
+          }
+          A4 c = {0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) c = mfma16(av[kk], bv[kk], c);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) F[(size_t)perm[16 * t + Acc<T>::row(lk, r)] * NB + li] = -c[r];
         }
       }
       __threadfence_block();
@@ -379,7 +555,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         sflag[1] = (mn / NB) * NB;
       }
       __syncthreads();
-      panel_solve<T>(pan, fac, inv, perm, npad, sflag[1], wave, lane);
+      panel_solve<T, MAXT>(pan, fac, inv, perm, npad, sflag[1], wave, lane);
       if (ir) {
         // FP64 solution panel in HBM, refined with FP64 residuals and FP32 corrections
         for (int idx = tid; idx < npad * NB; idx += kThreads) {
@@ -442,7 +618,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
             elem_res = fmax(elem_res, worst);
             break;
           }
-          panel_solve<T>(pan, fac, inv, perm, npad, 0, wave, lane);
+          panel_solve<T, MAXT>(pan, fac, inv, perm, npad, 0, wave, lane);
           for (int idx = tid; idx < npad * NB; idx += kThreads) {
             int r = idx >> 4, c = idx & 15;
             xg[r * NB + c] += (double)pan[r * LDP + c];
@@ -510,11 +686,9 @@ __global__ void k_fill_int(int* p, int n, int v) {
 
 template <typename T>
 size_t lu_smem_bytes(int npad, int nn, bool ir) {
-  size_t base = sizeof(T) * (size_t)npad * LDP + 2 * sizeof(int) * (size_t)npad + 2 * sizeof(double) * nn +
-                kWaves * (sizeof(double) + sizeof(int)) + 2 * sizeof(int);
-  base = (base + 15) / 16 * 16;
-  if (ir) base += NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * 8;
-  return base + 16;
+  size_t b = lds_base_bytes<T>(npad, nn) + sizeof(T) * 2 * NB * NB;
+  if (ir) b += NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * 8;
+  return b + 16;
 }
 
 }  // namespace
@@ -578,10 +752,30 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   args.ir_steps = 3;
   args.ir_tol = 1e-13;
   args.flags = flags;
-  hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local_lu<T>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  // tiles per wave in a sweep step: ceil(npan / kWaves), rounded up to an
+  // instantiated size
+  const int need = (npan + kWaves - 1) / kWaves;
+  auto pick = [&]() -> void (*)(LuArgs<T>) {
+    if (need <= 1) return k_local_lu<T, 1>;
+    if (need <= 2) return k_local_lu<T, 2>;
+    if (need <= 4) return k_local_lu<T, 4>;
+    if (need <= 7) return k_local_lu<T, 7>;
+    if (need <= 10) return k_local_lu<T, 10>;
+    if constexpr (sizeof(T) == 4) {
+      if (need <= 13) return k_local_lu<T, 13>;
+    }
+    return nullptr;
+  };
+  void (*kern)(LuArgs<T>) = pick();
+  if (!kern) {
+    std::ostringstream os;
+    os << "el_local_solve: n = " << dh.n << " is too large for this precision";
+    return set_error(ctx, EL_ERR_ARG, os.str());
+  }
+  hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)smem);
   if (he != hipSuccess) return hip_check(ctx, he, "hipFuncSetAttribute(k_local_lu)");
-  hipLaunchKernelGGL(k_local_lu<T>, dim3((unsigned)slots), dim3(kThreads), smem, ctx->stream, args);
+  hipLaunchKernelGGL(kern, dim3((unsigned)slots), dim3(kThreads), smem, ctx->stream, args);
   he = hipGetLastError();
   if (he != hipSuccess) return hip_check(ctx, he, "launch k_local_lu");
   int hflags[2];

@@ -1,0 +1,115 @@
+// Device helpers shared by the skeleton kernels: face numbering of a mesh,
+// and the per-element body of the skeleton product (I - P) x
+// (eq. hdg_global_mat): gather the m inflow traces of the element into LDS,
+// reduce each in2out row against them (groups of 8 lanes, 16-byte loads),
+// and write each outflow DOF from its unique upwind element.
+#pragma once
+
+#include "el_internal.h"
+
+namespace el {
+
+constexpr int kMVThreads = 256;
+
+struct MeshDev {
+  int n_x, n_y, n_vf;
+};
+
+__device__ inline int face_of(const MeshDev& ms, int i, int j, int f) {
+  switch (f) {
+    case 0: return j * (ms.n_x + 1) + i;
+    case 1: return j * (ms.n_x + 1) + i + 1;
+    case 2: return ms.n_vf + j * ms.n_x + i;
+    default: return ms.n_vf + (j + 1) * ms.n_x + i;
+  }
+}
+
+__device__ inline bool on_domain_boundary(const MeshDev& ms, int i, int j, int f) {
+  return (f == 0 && i == 0) || (f == 1 && i == ms.n_x - 1) || (f == 2 && j == 0) || (f == 3 && j == ms.n_y - 1);
+}
+
+__device__ inline double bf16_to_double(uint16_t b) {
+  return (double)__uint_as_float(((uint32_t)b) << 16);
+}
+
+// Row dot products of one element operator with the gathered inflow traces.
+// Groups of 8 lanes per row; each lane loads 16 bytes per step.
+template <typename OpT>
+__device__ inline double row_dot(const OpT* __restrict__ row, const double* tin, int m, int gl);
+
+template <>
+__device__ inline double row_dot<double>(const double* __restrict__ row, const double* tin, int m, int gl) {
+  double acc = 0.0;
+  for (int c = 2 * gl; c < m; c += 16) {
+    double2 v = *reinterpret_cast<const double2*>(row + c);
+    acc += v.x * tin[c] + v.y * tin[c + 1];
+  }
+  return acc;
+}
+
+template <>
+__device__ inline double row_dot<float>(const float* __restrict__ row, const double* tin, int m, int gl) {
+  double acc = 0.0;
+  for (int c = 4 * gl; c < m; c += 32) {
+    if (c + 4 <= m) {
+      float4 v = *reinterpret_cast<const float4*>(row + c);
+      acc += (double)v.x * tin[c] + (double)v.y * tin[c + 1] + (double)v.z * tin[c + 2] + (double)v.w * tin[c + 3];
+    } else {
+      for (int cc = c; cc < m; ++cc) acc += (double)row[cc] * tin[cc];
+    }
+  }
+  return acc;
+}
+
+template <>
+__device__ inline double row_dot<uint16_t>(const uint16_t* __restrict__ row, const double* tin, int m, int gl) {
+  double acc = 0.0;
+  for (int c = 8 * gl; c < m; c += 64) {
+    if (c + 8 <= m) {
+      uint4 v = *reinterpret_cast<const uint4*>(row + c);
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc += (double)__uint_as_float(w[u] << 16) * tin[c + 2 * u];
+        acc += (double)__uint_as_float(w[u] & 0xffff0000u) * tin[c + 2 * u + 1];
+      }
+    } else {
+      for (int cc = c; cc < m; ++cc) acc += bf16_to_double(row[cc]) * tin[cc];
+    }
+  }
+  return acc;
+}
+
+// y = x - in2out_e x_in at the outflow DOFs of element e; domain-inflow DOFs
+// of e are copied through (y = x there).  x, y: the mesh's trace vectors;
+// tin: m doubles of LDS.
+template <typename OpT>
+__device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int e, const OpT* __restrict__ op_e,
+                                      const double* __restrict__ x, double* __restrict__ y, double* tin) {
+  const int i = e % ms.n_x, j = e / ms.n_x;
+  const int m = dv.m;
+  for (int t = threadIdx.x; t < m; t += kMVThreads) {
+    const int f = dv.in_f[t];
+    const int F = face_of(ms, i, j, f);
+    const int dof = (F * dv.n_a + dv.in_k[t]) * dv.q + dv.in_j[t];
+    const double v = x[dof];
+    tin[t] = v;
+    if (on_domain_boundary(ms, i, j, f)) y[dof] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 3, gl = lane & 7;
+  for (int o = wave * 8 + g; o < m; o += (kMVThreads / 64) * 8) {
+    double acc = row_dot<OpT>(op_e + (size_t)o * m, tin, m, gl);
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (gl == 0) {
+      const int F = face_of(ms, i, j, dv.out_f[o]);
+      const int dof = (F * dv.n_a + dv.out_k[o]) * dv.q + dv.out_j[o];
+      y[dof] = x[dof] - acc;
+    }
+  }
+}
+
+}  // namespace el

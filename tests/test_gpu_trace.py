@@ -205,3 +205,100 @@ def test_conserve_energy_balance(ctx, dtype):
     keep = np.arange(20) != 5
     assert np.abs(bal[keep]).max() <= tol * np.abs(win).max()
     assert np.abs(bal[5]).max() > 1e-4            # masked element untouched
+
+
+# Batched uneven meshes in one call (sizes in the spirit of the 16^2 ... 128^2
+# batch, scaled so the oracle's direct solves finish in seconds); sharp cloud
+# edge with a seeded random centre per mesh.
+BATCH = [(2, 2), (3, 3), (4, 4), (4, 4), (6, 6), (5, 3), (1, 1), (3, 7)]
+
+
+def _batched_problem(p, n_a):
+    probs = []
+    for i, (nx, ny) in enumerate(BATCH):
+        od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, ny, field="sharp", seed=10 + i)
+        probs.append((od, oms, hh, kap, sig))
+    return probs
+
+
+def _batched_gpu(ctx, p, n_a, probs, graph, tol=1e-12):
+    from paper_2308_02467_amd import el
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    hh = np.concatenate([pr[2] for pr in probs])
+    kap = np.concatenate([pr[3] for pr in probs])
+    sig = np.concatenate([pr[4] for pr in probs])
+    E = hh.size
+    i2o = torch.empty((E, m, m), dtype=torch.float64, device=DEV)
+    print(f"[batched] local solve of {E} elements from {len(probs)} meshes", flush=True)
+    ctx.el_local_solve(d, T(hh), T(kap), T(sig), in2out=i2o)
+    meshes, ops, bs, ts = [], [], [], []
+    e0 = 0
+    gs = inputs.left_inflow(n_a)
+    for od, oms, h, _, _ in probs:
+        ms = el.mesh(oms.n_x, oms.n_y, oms.h)
+        nt = el.trace_size(d, ms)
+        b = torch.empty(nt, dtype=torch.float64, device=DEV)
+        ctx.el_trace_rhs(d, ms, gs, b)
+        meshes.append(ms)
+        ops.append(i2o[e0:e0 + h.size])
+        bs.append(b)
+        ts.append(torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV))
+        e0 += h.size
+    print(f"[batched] el_trace_solve n_mesh={len(meshes)} graph={graph}", flush=True)
+    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=tol, restart=20, max_iter=3000, graph=graph)
+    torch.cuda.synchronize()
+    return st, rep, [t.cpu().numpy() for t in ts]
+
+
+def test_batched_uneven_meshes_parity(ctx):
+    p, n_a = 3, 8
+    probs = _batched_problem(p, n_a)
+    st, rep, ts = _batched_gpu(ctx, p, n_a, probs, graph=True)
+    assert st == 0
+    for (od, oms, hh, kap, sig), r, t in zip(probs, rep, ts):
+        ref = oracle_pipeline(od, oms, hh, kap, sig, inputs.left_inflow(n_a))
+        assert r["converged"] and r["relres"] <= 1e-12, r
+        assert rel_err(t, ref["t"]) <= 1e-10, (oms.n_x, oms.n_y, rel_err(t, ref["t"]))
+
+
+def test_batched_graph_replays_match_eager(ctx):
+    """The captured restart cycle gives bit-identical results to launching the
+    same kernels one by one, on every replay, with other device work and
+    synchronizations between the solves."""
+    p, n_a = 3, 8
+    probs = _batched_problem(p, n_a)
+    _, rep0, ref = _batched_gpu(ctx, p, n_a, probs, graph=False)
+    for it in range(3):
+        junk = torch.randn(1 << 20, dtype=torch.float64, device=DEV)
+        (junk * 2).sum().item()
+        _, rep, ts = _batched_gpu(ctx, p, n_a, probs, graph=True)
+        for a, b, r, r0 in zip(ts, ref, rep, rep0):
+            assert np.array_equal(a, b), it
+            assert r == r0, it
+
+
+def test_batched_single_mesh_converged_and_empty_rhs(ctx):
+    """A mesh with a zero right-hand side returns t = 0 at once while the
+    other meshes of the batch iterate."""
+    from paper_2308_02467_amd import el
+    p, n_a = 2, 4
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, 3, 2, field="gauss")
+    i2o = torch.empty((hh.size, m, m), dtype=torch.float64, device=DEV)
+    ctx.el_local_solve(d, T(hh), T(kap), T(sig), in2out=i2o)
+    ms = el.mesh(3, 2, oms.h)
+    nt = el.trace_size(d, ms)
+    b1 = torch.empty(nt, dtype=torch.float64, device=DEV)
+    ctx.el_trace_rhs(d, ms, inputs.left_inflow(n_a), b1)
+    b0 = torch.zeros(nt, dtype=torch.float64, device=DEV)
+    t0 = torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV)
+    t1 = torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV)
+    print("[batched] zero rhs mesh", flush=True)
+    st, rep = ctx.el_trace_solve(d, [ms, ms], [i2o, i2o], [b0, b1], [t0, t1], tol=1e-12, restart=5)
+    assert st == 0
+    assert rep[0]["iters"] == 0 and rep[0]["converged"] and torch.all(t0 == 0)
+    ref = oracle_pipeline(od, oms, hh, kap, sig, inputs.left_inflow(n_a))
+    assert rel_err(t1.cpu().numpy(), ref["t"]) <= 1e-10
+    assert rep[1]["restarts"] >= 1
