@@ -256,6 +256,14 @@ el_status el_net_fit_normalization(el_ctx* ctx, el_net* net, int64_t N, const fl
 el_status el_net_params(el_ctx* ctx, const el_net* net, int which, float* dst);
 el_status el_net_num_params(const el_net* net, int64_t* n_params);
 
+/* Text report of the block tiles the GEMM autotuner chose so far in this
+ * process, one line per GEMM shape (shape, chosen tile, timing of each
+ * candidate in ms).  The autotuner times each candidate tile once, on the
+ * first call of a shape, on that call's own operands.  Writes at most cap
+ * bytes (NUL-terminated) into host buf (may be NULL); *len (may be NULL)
+ * receives the size needed including the NUL.  Never fails. */
+el_status el_tuning_report(char* buf, size_t cap, size_t* len);
+
 /* Training pairs from the FP64 local solver: y [E][n_out] bfloat16
  * (round to nearest even) = (in2out, in2sol) of each element. */
 el_status el_make_pairs(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa,

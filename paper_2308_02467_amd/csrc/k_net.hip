@@ -6,7 +6,10 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <sstream>
+#include <string>
 #include <vector>
 
 #include "el_internal.h"
@@ -123,15 +126,23 @@ __device__ inline float act_df(int act, float z) {
   return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
+// GEMM epilogues.  The kernel calls col(n) once per output column a lane
+// owns, then (m, n, acc, z, c) for each of that column's rows, so that
+// per-column data (bias, output scaling) is loaded once.
+
 // hidden layer epilogue: z = acc + b; Z (optional) = z; H = bf16(act(z))
 struct EpiHidden {
+  static constexpr const char* kName = "hidden";
+  static constexpr bool kRepeatable = true;   // running it twice gives the same outputs
   const float* bias;
   float* Z;
   uint16_t* H;
   int64_t ld;
   int act;
-  __device__ void operator()(int m, int n, float acc, int) {
-    float z = acc + bias[n];
+  struct Col { float b; };
+  __device__ Col col(int n) const { return Col{bias[n]}; }
+  __device__ void operator()(int m, int n, float acc, int, const Col& c) {
+    const float z = acc + c.b;
     if (Z) Z[(int64_t)m * ld + n] = z;
     H[(int64_t)m * ld + n] = f2bf(act_f(act, z));
   }
@@ -140,39 +151,56 @@ struct EpiHidden {
 
 // output layer, normalized FP32 (testing the forward pass)
 struct EpiOutNorm {
+  static constexpr const char* kName = "out_norm";
+  static constexpr bool kRepeatable = true;
   const float* bias;
   float* Y;
   int64_t ld;
-  __device__ void operator()(int m, int n, float acc, int) { Y[(int64_t)m * ld + n] = acc + bias[n]; }
+  struct Col { float b; };
+  __device__ Col col(int n) const { return Col{bias[n]}; }
+  __device__ void operator()(int m, int n, float acc, int, const Col& c) { Y[(int64_t)m * ld + n] = acc + c.b; }
   __device__ void flush() {}
 };
 
 // output layer, de-normalized operators (bfloat16 or float32): n < mm -> in2out, else in2sol
 template <typename OutT>
 struct EpiOutOps {
+  static constexpr const char* kName = sizeof(OutT) == 2 ? "out_ops_bf16" : "out_ops_f32";
+  static constexpr bool kRepeatable = true;
   const float* bias;
   const float* ymean;
   const float* ystd;
   OutT* i2o;
   OutT* i2s;
   int64_t mm, nm;
+  struct Col {
+    float b, sd, mean;   // y = (acc + b) sd + mean
+    OutT* base;          // column n of element 0, or null
+    int64_t stride;      // per element
+  };
   __device__ static inline OutT cvt(float y) {
     if constexpr (sizeof(OutT) == 2) return f2bf(y);
     else return y;
   }
-  __device__ void operator()(int e, int n, float acc, int) {
-    float y = (acc + bias[n]) * ystd[n] + ymean[n];
-    if (n < mm) {
-      if (i2o) i2o[(int64_t)e * mm + n] = cvt(y);
-    } else if (i2s) {
-      i2s[(int64_t)e * nm + (n - mm)] = cvt(y);
-    }
+  __device__ Col col(int n) const {
+    Col c;
+    c.b = bias[n];
+    c.sd = ystd[n];
+    c.mean = ymean[n];
+    if (n < mm) { c.base = i2o ? i2o + n : nullptr; c.stride = mm; }
+    else { c.base = i2s ? i2s + (n - mm) : nullptr; c.stride = nm; }
+    return c;
+  }
+  __device__ void operator()(int e, int, float acc, int, const Col& c) {
+    if (c.base) c.base[(int64_t)e * c.stride] = cvt((acc + c.b) * c.sd + c.mean);
   }
   __device__ void flush() {}
 };
 
 // output layer in training: MAE against normalized targets; dY = sign(pred - target)
 struct EpiMAE {
+  static constexpr const char* kName = "mae";
+  static constexpr bool kRepeatable = false;   // accumulates the loss
   const float* bias;
   const uint16_t* y;
   const float* ymean;
@@ -181,11 +209,13 @@ struct EpiMAE {
   float* loss;
   int64_t ld;
   float local;
-  __device__ void operator()(int m, int n, float acc, int) {
+  struct Col { float b, mean, sd; };
+  __device__ Col col(int n) const { return Col{bias[n], ymean[n], ystd[n]}; }
+  __device__ void operator()(int m, int n, float acc, int, const Col& c) {
     const int64_t i = (int64_t)m * ld + n;
-    float pred = acc + bias[n];
-    float tgt = (bf2f(y[i]) - ymean[n]) / ystd[n];
-    float d = pred - tgt;
+    const float pred = acc + c.b;
+    const float tgt = (bf2f(y[i]) - c.mean) / c.sd;
+    const float d = pred - tgt;
     local += fabsf(d);
     dY[i] = d > 0.f ? (uint16_t)0x3f80 : (d < 0.f ? (uint16_t)0xbf80 : (uint16_t)0);
   }
@@ -197,83 +227,227 @@ struct EpiMAE {
 };
 
 struct EpiF32 {
+  static constexpr const char* kName = "f32";
+  static constexpr bool kRepeatable = true;
   float* C;
   int64_t ldc, zstride;
-  __device__ void operator()(int m, int n, float acc, int z) { C[z * zstride + (int64_t)m * ldc + n] = acc; }
+  struct Col {};
+  __device__ Col col(int) const { return Col{}; }
+  __device__ void operator()(int m, int n, float acc, int z, const Col&) { C[z * zstride + (int64_t)m * ldc + n] = acc; }
   __device__ void flush() {}
 };
 
-template <bool A_KC, bool B_KC, typename Epi>
-__global__ void __launch_bounds__(gemm::kThreads) k_mm(const uint16_t* __restrict__ A, int64_t lda,
+// at least two workgroups per CU (LDS), so the registers of a wave must fit
+// 2 waves/SIMD
+template <bool A_KC, bool B_KC, int TM, int TN, typename Epi>
+__global__ void __launch_bounds__(gemm::kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_mm(const uint16_t* __restrict__ A, int64_t lda,
                                                         const uint16_t* __restrict__ B, int64_t ldb, int M, int N,
                                                         int K, int k_split, int m_fast, Epi epi) {
   using namespace gemm;
-  __shared__ __align__(16) uint16_t As[2][BM * PITCH];
-  __shared__ __align__(16) uint16_t Bs[2][BN * PITCH];
+  constexpr int BM = 64 * TM, BN = 64 * TN;
+  extern __shared__ __align__(16) uint16_t lds_mm[];
+  uint16_t* As = lds_mm;                    // [2][BM * PITCH]
+  uint16_t* Bs = lds_mm + 2 * BM * PITCH;   // [2][BN * PITCH]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // m_fast: consecutive workgroups walk down M for a fixed N tile, so one
-  // panel of B (the large weight matrix) is read once while the small A
-  // operand stays cache resident
-  const int m0 = (m_fast ? blockIdx.x : blockIdx.y) * BM, n0 = (m_fast ? blockIdx.y : blockIdx.x) * BN;
+  // Tile order, XCD-aware: workgroups are dealt round-robin to the 8 XCDs,
+  // so workgroup b runs on XCD b % 8.  Each XCD gets a contiguous range of
+  // the tile sequence, and the sequence walks groups of 8 M tiles, M fastest
+  // within a group, so that the workgroups resident on one XCD share a few A
+  // and B panels in that XCD's L2.
+  int tile_m, tile_n;
+  {
+    const int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+    const int T = tm * tn;
+    const int b = blockIdx.x;
+    // XCD x holds workgroups b = 8 i + x, i < T/8 (+1 for x < T%8); it gets
+    // the contiguous range starting at x (T/8) + min(x, T%8): a bijection
+    const int xcd = b & 7, loc = b >> 3;
+    const int pid = xcd * (T >> 3) + min(xcd, T & 7) + loc;
+    constexpr int G = 8;
+    const int group = pid / (G * tn), first = group * G;
+    const int gsz = min(tm - first, G);
+    tile_m = first + (pid % (G * tn)) % gsz;
+    tile_n = (pid % (G * tn)) / gsz;
+    (void)m_fast;
+  }
+  const int m0 = tile_m * BM, n0 = tile_n * BN;
   const int kb = blockIdx.z * k_split;
   const int ke = min(K, kb + k_split);
-  f32x4 acc[4][4];
+  f32x16 acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int li = lane & 15, lk = (lane >> 4) * 8;
-  int buf = 0;
-  if (kb < ke) {
-    load_tile<A_KC>(A, lda, M, m0, kb, ke, As[0], tid);
-    load_tile<B_KC>(B, ldb, N, n0, kb, ke, Bs[0], tid);
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  // two register stages: tile s+2 is in flight while tile s is multiplied
+  // and tile s+1 goes from registers to LDS
+  TileLoader<A_KC, BM> la0, la1;
+  TileLoader<B_KC, BN> lb0, lb1;
+  const int nsteps = kb < ke ? (ke - kb + BK - 1) / BK : 0;
+  auto kt = [&](int s) { return kb + min(s, max(nsteps - 1, 0)) * BK; };   // clamped: loads past the end repeat the last tile
+  if (nsteps > 0) {
+    la0.load(A, lda, M, m0, kt(0), ke, tid);
+    lb0.load(B, ldb, N, n0, kt(0), ke, tid);
+    la1.load(A, lda, M, m0, kt(1), ke, tid);
+    lb1.load(B, ldb, N, n0, kt(1), ke, tid);
+    la0.store(As, tid);
+    lb0.store(Bs, tid);
   }
   __syncthreads();
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-    if (k0 + BK < ke) {
-      load_tile<A_KC>(A, lda, M, m0, k0 + BK, ke, As[buf ^ 1], tid);
-      load_tile<B_KC>(B, ldb, N, n0, k0 + BK, ke, Bs[buf ^ 1], tid);
+  const int lr = lane & 31, lq = (lane >> 5) * 8;
+  auto compute = [&](int buf) {
+    const uint16_t* as = As + buf * BM * PITCH + (wm * 32 * TM + lr) * PITCH + lq;
+    const uint16_t* bs = Bs + buf * BN * PITCH + (wn * 32 * TN + lr) * PITCH + lq;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 af[TM], bfr[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = *reinterpret_cast<const bf16x8*>(as + 32 * i * PITCH + ks);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(bs + 32 * j * PITCH + ks);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
-    bf16x8 af[4], bfr[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      af[i] = *reinterpret_cast<const bf16x8*>(As[buf] + (wm * 64 + 16 * i + li) * PITCH + lk);
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      bfr[j] = *reinterpret_cast<const bf16x8*>(Bs[buf] + (wn * 64 + 16 * j + li) * PITCH + lk);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+  };
+  for (int s = 0; s < nsteps; s += 2) {
+    // even step: registers 0 are free (stored), registers 1 hold tile s+1
+    la0.load(A, lda, M, m0, kt(s + 2), ke, tid);
+    lb0.load(B, ldb, N, n0, kt(s + 2), ke, tid);
+    compute(0);
+    if (s + 1 < nsteps) {
+      la1.store(As + BM * PITCH, tid);
+      lb1.store(Bs + BN * PITCH, tid);
+    }
     __syncthreads();
-    buf ^= 1;
+    if (s + 1 >= nsteps) break;
+    // odd step: registers 1 are free, registers 0 hold tile s+2
+    la1.load(A, lda, M, m0, kt(s + 3), ke, tid);
+    lb1.load(B, ldb, N, n0, kt(s + 3), ke, tid);
+    compute(1);
+    if (s + 2 < nsteps) {
+      la0.store(As, tid);
+      lb0.store(Bs, tid);
+    }
+    __syncthreads();
   }
+  // output layout of the 32x32 MFMA (measured on gfx950): register r of lane
+  // l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + wn * 32 * TN + 32 * j + lr;
+    if (n < N) {
+      const auto c = epi.col(n);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + 16 * i + 4 * (lane >> 4) + r;
-        const int n = n0 + wn * 64 + 16 * j + li;
-        if (m < M && n < N) epi(m, n, acc[i][j][r], blockIdx.z);
-      }
+        for (int r = 0; r < 16; ++r) {
+          const int m = m0 + wm * 32 * TM + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          if (m < M) epi(m, n, acc[i][j][r], blockIdx.z, c);
+        }
+    }
+  }
   epi.flush();
+}
+
+template <bool A_KC, bool B_KC, int TM, int TN, typename Epi>
+el_status mm_t(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M, int64_t N,
+               int64_t K, int splits, Epi epi, bool m_fast) {
+  constexpr int BM = 64 * TM, BN = 64 * TN;
+  constexpr size_t smem = 2 * (size_t)(BM + BN) * gemm::PITCH * sizeof(uint16_t);
+  // the tile loaders move whole 16-byte segments along the contiguous
+  // dimension of each operand
+  const int64_t a_cont = A_KC ? K : M, b_cont = B_KC ? K : N;
+  if (a_cont % 8 || b_cont % 8 || lda % 8 || ldb % 8)
+    return set_error(ctx, EL_ERR_ARG, "internal GEMM: contiguous dimensions must be multiples of 8");
+  static bool attr_set = false;   // per instantiation; the attribute is per function
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mm<A_KC, B_KC, TM, TN, Epi>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return hip_check(ctx, e, "hipFuncSetAttribute(k_mm)");
+    attr_set = true;
+  }
+  int64_t ks = (K + splits - 1) / splits;
+  ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
+  const int nz = (int)((K + ks - 1) / ks);
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (tiles > INT_MAX / 2) return set_error(ctx, EL_ERR_ARG, "internal GEMM: too many tiles");
+  dim3 grid((unsigned)tiles, 1, (unsigned)nz);
+  hipLaunchKernelGGL((k_mm<A_KC, B_KC, TM, TN, Epi>), grid, dim3(gemm::kThreads), smem, ctx->stream, A, lda, B, ldb,
+                     (int)M, (int)N, (int)K, (int)ks, (int)m_fast, epi);
+  return hip_check(ctx, hipGetLastError(), "launch k_mm");
+}
+
+// ---- GEMM autotuner --------------------------------------------------------
+// The block tile is chosen per GEMM shape, on first use, by timing the
+// candidates below on the call's own operands (outputs are overwritten by
+// the chosen run); epilogues with side effects other than their outputs
+// (the loss accumulation) use the default.  Choices are kept per process.
+struct TileVariant {
+  int tm, tn;
+};
+constexpr TileVariant kVariants[] = {{2, 2}, {1, 2}, {2, 1}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, std::vector<float>>> g_tune;   // key -> (choice, ms per variant)
+
+template <bool A_KC, bool B_KC, typename Epi>
+el_status mm_variant(el_ctx* ctx, int v, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M,
+                     int64_t N, int64_t K, int splits, const Epi& epi, bool m_fast) {
+  switch (v) {
+    case 1: return mm_t<A_KC, B_KC, 1, 2, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
+    case 2: return mm_t<A_KC, B_KC, 2, 1, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
+    default: return mm_t<A_KC, B_KC, 2, 2, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
+  }
 }
 
 template <bool A_KC, bool B_KC, typename Epi>
 el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M, int64_t N,
              int64_t K, int splits, Epi epi, bool m_fast = false) {
   if (M <= 0 || N <= 0) return EL_OK;
-  int64_t ks = (K + splits - 1) / splits;
-  ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
-  const int nz = (int)((K + ks - 1) / ks);
-  const unsigned tm = (unsigned)((M + gemm::BM - 1) / gemm::BM), tn = (unsigned)((N + gemm::BN - 1) / gemm::BN);
-  dim3 grid(m_fast ? tm : tn, m_fast ? tn : tm, (unsigned)nz);
-  hipLaunchKernelGGL((k_mm<A_KC, B_KC, Epi>), grid, dim3(gemm::kThreads), 0, ctx->stream, A, lda, B, ldb, (int)M,
-                     (int)N, (int)K, (int)ks, (int)m_fast, epi);
-  return hip_check(ctx, hipGetLastError(), "launch k_mm");
+  if constexpr (!Epi::kRepeatable) {
+    return mm_variant<A_KC, B_KC, Epi>(ctx, 0, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
+  } else {
+    std::ostringstream ks;
+    ks << "gemm " << (A_KC ? "A" : "At") << (B_KC ? "B" : "Bt") << ' ' << Epi::kName << " M=" << M << " N=" << N
+       << " K=" << K << " splits=" << splits;
+    const std::string key = ks.str();
+    int choice = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) choice = it->second.first;
+    }
+    if (choice < 0) {
+      std::vector<float> ms(kNumVariants, 0.f);
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return hip_check(ctx, hipGetLastError(), "autotune events");
+      int best = 0;
+      for (int v = 0; v < kNumVariants; ++v) {
+        el_status st = mm_variant<A_KC, B_KC, Epi>(ctx, v, A, lda, B, ldb, M, N, K, splits, epi, m_fast);   // warm-up
+        if (st) return st;
+        hipEventRecord(e0, ctx->stream);
+        st = mm_variant<A_KC, B_KC, Epi>(ctx, v, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
+        if (st) return st;
+        hipEventRecord(e1, ctx->stream);
+        hipError_t he = hipEventSynchronize(e1);
+        if (he != hipSuccess) return hip_check(ctx, he, "autotune");
+        hipEventElapsedTime(&ms[v], e0, e1);
+        if (ms[v] < ms[best]) best = v;
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      choice = best;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = {choice, ms};
+    }
+    return mm_variant<A_KC, B_KC, Epi>(ctx, choice, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
+  }
 }
 
 // out[n] = sum_b X[b][n] (X bfloat16 or float).  256 threads = 16 columns x
@@ -894,6 +1068,27 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
   if (mask_alloc) { hipStreamSynchronize(ctx->stream); hipFree(mask_alloc); }
   if (n_fallback_host) *n_fallback_host = nfb;
   return st;
+}
+
+el_status el_tuning_report(char* buf, size_t cap, size_t* len) {
+  std::ostringstream os;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tune) {
+      const TileVariant v = kVariants[kv.second.first];
+      os << kv.first << " -> tile " << 64 * v.tm << "x" << 64 * v.tn << " (ms:";
+      for (float t : kv.second.second) os << ' ' << t;
+      os << ")\n";
+    }
+  }
+  const std::string s = os.str();
+  if (len) *len = s.size() + 1;
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return EL_OK;
 }
 
 }  // extern "C"

@@ -85,6 +85,7 @@ _SIGS = {
     "el_trace_rhs": [ctypes.c_void_p, el_disc, el_mesh, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
     "el_trace_matvec": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_void_p],
+    "el_tuning_report": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "el_trace_solve": [ctypes.c_void_p, el_disc, ctypes.c_int, ctypes.POINTER(el_mesh),
                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(el_gmres_opts),
@@ -482,3 +483,12 @@ def unpack_net_blob(blob):
     out["y_mean"], out["y_std"] = take(n_out), take(n_out)
     out["theta"], out["adam_m"], out["adam_v"] = take(P), take(P), take(P)
     return out
+
+
+def tuning_report():
+    """The GEMM autotuner's choices so far (el_tuning_report), as text."""
+    n = ctypes.c_size_t()
+    lib().el_tuning_report(None, 0, ctypes.byref(n))
+    buf = ctypes.create_string_buffer(max(n.value, 1))
+    lib().el_tuning_report(buf, n.value, None)
+    return buf.value.decode()
