@@ -187,16 +187,24 @@ el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, i
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean,
                           int op_dtype, const double* trace, double* mean);
 
+/* Forms of the volume operator that goes with in2out: the full in2sol
+ * [n][m], or its ordinate average in2mean [nn][m] (the mean-intensity map,
+ * Sec. 2.4.1: the network may learn it instead of in2sol). */
+#define EL_FORM_IN2SOL 0
+#define EL_FORM_IN2MEAN 1
+
 /* Energy balance of learned operators.  For every element (with mask[e] != 0
  * when mask is given) and every inflow column i, the exact operators satisfy
  *   sum_o w_o in2out[o][i] + sum_(k,nd) W_nd (h kappa_nd / 2) in2sol[(k,nd)][i] = w_i
  * (outflow = inflow - absorption, obtained by testing the local equations
  * with v = 1 and summing over ordinates; w = face quadrature weight times
- * |s.n|).  Each column of in2out is rescaled in place so that this holds.
- * Not part of the paper's method: a post-processing option for the learned
- * operators.  in2out, in2sol in op_dtype (EL_F64, EL_F32, EL_BF16). */
+ * |s.n|); with in2mean the absorption is N_a sum_nd W_nd (h kappa_nd / 2)
+ * in2mean[nd][i].  Each column of in2out is rescaled in place so that this
+ * holds.  Not part of the paper's method: a post-processing option for the
+ * learned operators.  in2vol = in2sol or in2mean (form); in2out and in2vol
+ * in op_dtype (EL_F64, EL_F32, EL_BF16). */
 el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa, void* in2out,
-                      const void* in2sol, int op_dtype, const uint8_t* mask);
+                      const void* in2vol, int form, int op_dtype, const uint8_t* mask);
 
 /* Squared element L2 norms of mean-intensity fields [E][nn] (relative error
  * measure of Sec. 3.2.1): out_host[0] = sum_e (h_e/2)^2 sum W (a - ref)^2,
@@ -209,7 +217,9 @@ el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h,
  * A fully connected network x_i = f_i(A_i x_{i-1} + b_i), f = GELU (exact
  * erf form) or ELU on the hidden layers and the identity on the output layer
  * (Sec. 2.4.1), maps the features of one element to its operators
- * (in2out [m][m] followed by in2sol [n][m], row-major; n_out = m*m + n*m).
+ * (in2out [m][m] followed by in2sol [n][m], row-major; n_out = m*m + n*m;
+ * or, in the in2mean form, in2out followed by in2mean [nn][m]; n_out =
+ * m*m + nn*m).
  * Input of one element (raw): x = (h, kappa[nn], sigma[nn]).  Features:
  * log10 h, log10 max(h kappa/2, 1e-12), log10 max(h sigma/2, 1e-12)
  * (the reference-element coefficients of Sec. 2.4.1), z-scored with
@@ -225,7 +235,7 @@ typedef struct {
   int width;       /* hidden width */
   int depth;       /* hidden layers (>= 1) */
   int act;         /* EL_ACT_GELU or EL_ACT_ELU */
-  int64_t n_out;   /* m*m + n*m */
+  int64_t n_out;   /* m*m + n*m (in2sol form) or m*m + nn*m (in2mean form) */
   uint64_t seed;   /* initialization: W, b ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) */
 } el_net_desc;
 
@@ -264,10 +274,12 @@ el_status el_net_num_params(const el_net* net, int64_t* n_params);
  * receives the size needed including the NUL.  Never fails. */
 el_status el_tuning_report(char* buf, size_t cap, size_t* len);
 
-/* Training pairs from the FP64 local solver: y [E][n_out] bfloat16
- * (round to nearest even) = (in2out, in2sol) of each element. */
+/* Training pairs from the local solver (FP64 LU; FP32 LU with FP64
+ * refinement when the FP64 factorization does not fit one workgroup, as at
+ * n = 1568): y [E][n_out] bfloat16 (round to nearest even) = (in2out,
+ * in2sol) of each element, or (in2out, in2mean) for form EL_FORM_IN2MEAN. */
 el_status el_make_pairs(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa,
-                        const double* sigma, uint16_t* y);
+                        const double* sigma, int form, uint16_t* y);
 
 /* One training step on a batch of B pairs: forward, MAE loss, backward,
  * Adam with learning rate lr.  loss: device float, receives the batch loss
@@ -280,14 +292,16 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
 el_status el_net_forward(el_ctx* ctx, const el_net* net, int64_t B, const float* x, float* y_norm);
 
 /* Learned operators for E elements (inference): in2out [E][m][m] and
- * in2sol [E][n][m] stored as out_dtype (EL_BF16: bfloat16 bits, round to
- * nearest even; EL_F32: float32); either may be NULL.  in_range [E]
+ * in2vol = in2sol [E][n][m] (network in the in2sol form) or in2mean
+ * [E][nn][m] (in2mean form; the form follows from the network's n_out),
+ * stored as out_dtype (EL_BF16: bfloat16 bits, round to nearest even;
+ * EL_F32: float32); either may be NULL.  in_range [E]
  * (1 = every input inside the training box; may be NULL).  fallback = 1:
  * elements outside the box are solved by the plain local solver
  * (precision) and written, rounded to out_dtype, into the same outputs;
  * *n_fallback_host receives their count.  Synchronizes. */
 el_status el_infer(el_ctx* ctx, const el_net* net, el_disc d, int64_t E, const double* h,
-                   const double* kappa, const double* sigma, void* in2out, void* in2sol, int out_dtype,
+                   const double* kappa, const double* sigma, void* in2out, void* in2vol, int out_dtype,
                    uint8_t* in_range, int fallback, int precision, int64_t* n_fallback_host);
 
 #ifdef __cplusplus

@@ -95,6 +95,8 @@ el_status ensure_ws(el_ctx* ctx, Workspace& ws, size_t bytes);
 el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,
                              const double* h, const double* kappa, const double* sigma,
                              double* in2out, double* in2sol, double* in2mean, double* rel_resid);
+// whether the FP64 factorization of this discretization fits one workgroup
+bool local_fp64_fits(el_ctx* ctx, el_ctx::DiscEntry* de);
 el_status launch_trace_rhs(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
                            const double* g_side_host, double* b);
 el_status launch_trace_matvec(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
@@ -110,7 +112,7 @@ el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh
 el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
                               const void* in2mean, int op_dtype, const double* trace, double* mean);
 el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* kappa,
-                          void* in2out, const void* in2sol, int op_dtype, const uint8_t* mask);
+                          void* in2out, const void* in2vol, int form, int op_dtype, const uint8_t* mask);
 el_status launch_mean_l2(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h,
                          const double* a, const double* ref, double* out_host);
 

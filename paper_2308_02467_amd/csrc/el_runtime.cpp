@@ -281,15 +281,16 @@ el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2m
 }
 
 el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa, void* in2out,
-                      const void* in2sol, int op_dtype, const uint8_t* mask) {
+                      const void* in2vol, int form, int op_dtype, const uint8_t* mask) {
   if (!ctx) return EL_ERR_ARG;
-  if (E <= 0 || !h || !kappa || !in2out || !in2sol || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
+  if (E <= 0 || !h || !kappa || !in2out || !in2vol || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32) ||
+      (form != EL_FORM_IN2SOL && form != EL_FORM_IN2MEAN))
     return set_error(ctx, EL_ERR_ARG, "el_conserve: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
-  return launch_conserve(ctx, de, E, h, kappa, in2out, in2sol, op_dtype, mask);
+  return launch_conserve(ctx, de, E, h, kappa, in2out, in2vol, form, op_dtype, mask);
 }
 
 el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* a,

@@ -84,7 +84,10 @@ struct LuArgs {
   uint16_t* b_i2s;        // bfloat16 in2sol [E][n][m]
   float* f_i2o;           // float32 in2out [E][m][m]
   float* f_i2s;           // float32 in2sol [E][n][m]
-  uint16_t* pairs;        // bfloat16 (in2out, in2sol) [E][m*m + n*m]
+  uint16_t* b_i2m;        // bfloat16 in2mean [E][nn][m]
+  float* f_i2m;           // float32 in2mean [E][nn][m]
+  uint16_t* pairs;        // bfloat16 (in2out, in2sol) [E][m*m + n*m] or (in2out, in2mean) [E][m*m + nn*m]
+  int pairs_form;         // EL_FORM_IN2SOL or EL_FORM_IN2MEAN
   const int32_t* emap;    // batch slot -> element index (inputs and outputs), or null
   T* fac;        // [slots][npan][npad][NB]
   T* inv;        // [slots][npan][2][NB][NB]
@@ -94,6 +97,7 @@ struct LuArgs {
   double* rel_resid;  // [E] or null
   int ir_steps;
   double ir_tol;
+  int ir_cols;          // solution columns staged in LDS per residual pass (8, 4 or 2)
 };
 
 // Entry (i, j) of the padded local matrix A (identity outside n x n).
@@ -362,6 +366,64 @@ __host__ __device__ inline size_t lds_base_bytes(int npad, int nn) {
   return (b + 15) / 16 * 16;
 }
 
+// FP64 residual of a solution panel for the refinement: for the rows of the
+// panel (logical order), pan[i][c] = (-B_hat - A x)[perm[i]][c], x the FP64
+// solution panel xg [npad][NB] in HBM, using the structure of A (per-ordinate
+// transport blocks, node-diagonal M and S); colmax[c] = max |residual| of
+// column c.  x is staged through LDS (xs, npad x XC doubles) XC columns at a
+// time.  All threads call it; it ends on a barrier.
+template <typename T, int XC>
+__device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, const double* tau_e,
+                                   const double* tau_s, const double* xg, double* xs, unsigned long long* colmax,
+                                   int npad, int P0, int tid) {
+  const DiscDev& dv = a.dv;
+  const int n = dv.n, m = dv.m, nn = dv.nn;
+  for (int c0 = 0; c0 < NB; c0 += XC) {
+    for (int idx = tid; idx < npad * XC; idx += kThreads) {
+      const int r = idx / XC, c = idx % XC;
+      xs[idx] = xg[r * NB + c0 + c];
+    }
+    __syncthreads();
+    for (int i = tid; i < npad; i += kThreads) {
+      const int q = perm[i];
+      double acc[XC];
+      if (q >= n) {
+#pragma unroll
+        for (int c = 0; c < XC; ++c) acc[c] = -xs[q * XC + c];
+      } else {
+        const int k = q / nn, nd = q - k * nn;
+        const double* Trow = dv.T + ((size_t)k * nn + nd) * nn;
+#pragma unroll
+        for (int c = 0; c < XC; ++c) acc[c] = 0.0;
+        for (int j = 0; j < nn; ++j) {
+          const double t = Trow[j];
+          if (t != 0.0) {
+            const double* xr = xs + (k * nn + j) * XC;
+#pragma unroll
+            for (int c = 0; c < XC; ++c) acc[c] += t * xr[c];
+          }
+        }
+        const double wd = dv.W[nd] * tau_e[nd], ws = dv.W[nd] * tau_s[nd];
+        const double* Qr = dv.Q + k * dv.n_a;
+#pragma unroll
+        for (int c = 0; c < XC; ++c) {
+          double sc = 0.0;
+          for (int kp = 0; kp < dv.n_a; ++kp) sc += Qr[kp] * xs[(kp * nn + nd) * XC + c];
+          const int col = P0 + c0 + c;
+          const double rv = (col < m && q == dv.in_row[col]) ? dv.in_val[col] : 0.0;
+          acc[c] = rv - (acc[c] + wd * xs[q * XC + c] - ws * sc);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < XC; ++c) {
+        pan[i * LDP + c0 + c] = (T)acc[c];
+        atomicMax(&colmax[c0 + c], (unsigned long long)__double_as_longlong(fabs(acc[c])));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int MAXT>
 __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   typedef typename Acc<T>::type A4;
@@ -380,7 +442,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   T* sinv = reinterpret_cast<T*>(smem + lds_base_bytes<T>(npad, nn));    // [2][NB][NB]
   // iterative refinement scratch (only allocated when a.xbuf != null)
   unsigned long long* colmax = reinterpret_cast<unsigned long long*>(sinv + 2 * NB * NB);   // [NB]
-  double* xs = reinterpret_cast<double*>(colmax + NB);                    // [npad][8]
+  double* xs = reinterpret_cast<double*>(colmax + NB);                    // [npad][ir_cols]
   const bool ir = sizeof(T) == 4 && a.xbuf != nullptr;   // refinement only for the FP32 factorization
   double* xg = ir ? a.xbuf + (size_t)blockIdx.x * npad * NB : nullptr;
 
@@ -567,50 +629,9 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         for (int it = 0;; ++it) {
           if (tid < NB) colmax[tid] = 0ull;
           __syncthreads();
-          for (int half = 0; half < 2; ++half) {
-            for (int idx = tid; idx < npad * 8; idx += kThreads) {
-              int r = idx >> 3, c = idx & 7;
-              xs[idx] = xg[r * NB + half * 8 + c];
-            }
-            __syncthreads();
-            for (int i = tid; i < npad; i += kThreads) {
-              const int q = perm[i];
-              double acc[8];
-              if (q >= n) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] = -xs[q * 8 + c];
-              } else {
-                const int k = q / nn, nd = q - k * nn;
-                const double* Trow = dv.T + ((size_t)k * nn + nd) * nn;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-                for (int j = 0; j < nn; ++j) {
-                  const double t = Trow[j];
-                  if (t != 0.0) {
-                    const double* xr = xs + (k * nn + j) * 8;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) acc[c] += t * xr[c];
-                  }
-                }
-                const double wd = dv.W[nd] * tau_e[nd], ws = dv.W[nd] * tau_s[nd];
-                const double* Qr = dv.Q + k * dv.n_a;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                  double sc = 0.0;
-                  for (int kp = 0; kp < dv.n_a; ++kp) sc += Qr[kp] * xs[(kp * nn + nd) * 8 + c];
-                  const int col = P0 + half * 8 + c;
-                  const double rv = (col < m && q == dv.in_row[col]) ? dv.in_val[col] : 0.0;
-                  acc[c] = rv - (acc[c] + wd * xs[q * 8 + c] - ws * sc);
-                }
-              }
-#pragma unroll
-              for (int c = 0; c < 8; ++c) {
-                pan[i * LDP + half * 8 + c] = (T)acc[c];
-                atomicMax(&colmax[half * 8 + c], (unsigned long long)__double_as_longlong(fabs(acc[c])));
-              }
-            }
-            __syncthreads();
-          }
+          if (a.ir_cols == 8) ir_residual<T, 8>(a, pan, perm, tau_e, tau_s, xg, xs, colmax, npad, P0, tid);
+          else if (a.ir_cols == 4) ir_residual<T, 4>(a, pan, perm, tau_e, tau_s, xg, xs, colmax, npad, P0, tid);
+          else ir_residual<T, 2>(a, pan, perm, tau_e, tau_s, xg, xs, colmax, npad, P0, tid);
           double worst = 0.0;
           for (int c = 0; c < NB; ++c)
             if (P0 + c < m) worst = fmax(worst, __longlong_as_double((long long)colmax[c]) / dv.in_val[P0 + c]);
@@ -628,8 +649,10 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         }
       }
       // outputs (pan rows are volume DOFs in natural order)
-      const int64_t n_out = (int64_t)m * m + (int64_t)n * m;
-      if (a.in2sol || a.b_i2s || a.f_i2s || a.pairs) {
+      const bool pairs_sol = a.pairs && a.pairs_form == EL_FORM_IN2SOL;
+      const bool pairs_mean = a.pairs && a.pairs_form == EL_FORM_IN2MEAN;
+      const int64_t n_out = (int64_t)m * m + (int64_t)(pairs_mean ? nn : n) * m;
+      if (a.in2sol || a.b_i2s || a.f_i2s || pairs_sol) {
         for (int idx = tid; idx < n * NB; idx += kThreads) {
           int r = idx >> 4, c = idx & 15;
           if (P0 + c < m) {
@@ -638,7 +661,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
             if (a.in2sol) a.in2sol[o] = v;
             if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
             if (a.f_i2s) a.f_i2s[o] = (float)v;
-            if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+            if (pairs_sol) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
           }
         }
       }
@@ -655,8 +678,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
           }
         }
       }
-      if (a.in2mean) {
-        double* o = a.in2mean + (size_t)e * nn * m;
+      if (a.in2mean || a.b_i2m || a.f_i2m || pairs_mean) {
         const double s = 1.0 / dv.n_a;
         for (int idx = tid; idx < nn * NB; idx += kThreads) {
           int r = idx >> 4, c = idx & 15;
@@ -664,7 +686,12 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
             double acc = 0.0;
             for (int k = 0; k < dv.n_a; ++k)
               acc += ir ? xg[(k * nn + r) * NB + c] : (double)pan[(k * nn + r) * LDP + c];
-            o[(size_t)r * m + P0 + c] = acc * s;
+            const double v = acc * s;
+            const int64_t o = ((int64_t)e * nn + r) * m + P0 + c;
+            if (a.in2mean) a.in2mean[o] = v;
+            if (a.b_i2m) a.b_i2m[o] = gemm::f2bf((float)v);
+            if (a.f_i2m) a.f_i2m[o] = (float)v;
+            if (pairs_mean) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
           }
         }
       }
@@ -685,9 +712,9 @@ __global__ void k_fill_int(int* p, int n, int v) {
 }
 
 template <typename T>
-size_t lu_smem_bytes(int npad, int nn, bool ir) {
+size_t lu_smem_bytes(int npad, int nn, int ir_cols) {
   size_t b = lds_base_bytes<T>(npad, nn) + sizeof(T) * 2 * NB * NB;
-  if (ir) b += NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * 8;
+  if (ir_cols) b += NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * ir_cols;
   return b + 16;
 }
 
@@ -703,7 +730,10 @@ struct LocalOut {
   uint16_t* b_i2s = nullptr;
   float* f_i2o = nullptr;
   float* f_i2s = nullptr;
+  uint16_t* b_i2m = nullptr;
+  float* f_i2m = nullptr;
   uint16_t* pairs = nullptr;
+  int pairs_form = EL_FORM_IN2SOL;
   const int32_t* emap = nullptr;
 };
 
@@ -716,9 +746,16 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   if (rel_resid) {
     hipLaunchKernelGGL(k_fill_double, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, ctx->stream, rel_resid, E, 0.0);
   }
-  size_t smem = lu_smem_bytes<T>(npad, dh.nn, ir);
   int max_smem = 0;
   hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
+  // refinement: stage as many solution columns per residual pass as fit
+  int ir_cols = 0;
+  if (ir) {
+    for (int c : {8, 4, 2})
+      if (lu_smem_bytes<T>(npad, dh.nn, c) <= (size_t)max_smem) { ir_cols = c; break; }
+    if (!ir_cols) ir_cols = 2;
+  }
+  size_t smem = lu_smem_bytes<T>(npad, dh.nn, ir_cols);
   if ((int)smem > max_smem) {
     std::ostringstream os;
     os << "el_local_solve: n = " << dh.n << " needs " << smem << " B of LDS (limit " << max_smem << ")";
@@ -744,6 +781,7 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   args.in2out = out.in2out; args.in2sol = out.in2sol; args.in2mean = out.in2mean;
   args.b_i2o = out.b_i2o; args.b_i2s = out.b_i2s; args.pairs = out.pairs; args.emap = out.emap;
   args.f_i2o = out.f_i2o; args.f_i2s = out.f_i2s;
+  args.b_i2m = out.b_i2m; args.f_i2m = out.f_i2m; args.pairs_form = out.pairs_form;
   char* base = reinterpret_cast<char*>(ctx->ws_local.ptr);
   args.fac = reinterpret_cast<T*>(base);
   args.inv = reinterpret_cast<T*>(base + fac_bytes);
@@ -751,6 +789,7 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   args.rel_resid = rel_resid;
   args.ir_steps = 3;
   args.ir_tol = 1e-13;
+  args.ir_cols = ir_cols;
   args.flags = flags;
   // tiles per wave in a sweep step: ceil(npan / kWaves), rounded up to an
   // instantiated size
@@ -803,6 +842,14 @@ el_status run_local(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E
 
 }  // namespace
 
+bool local_fp64_fits(el_ctx* ctx, el_ctx::DiscEntry* de) {
+  int max_smem = 0;
+  hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
+  const int npad = (de->host.n + NB - 1) / NB * NB;
+  return lu_smem_bytes<double>(npad, de->host.nn, 0) <= (size_t)max_smem &&
+         (npad / NB + kWaves - 1) / kWaves <= 10;
+}
+
 el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,
                              const double* h, const double* kappa, const double* sigma,
                              double* in2out, double* in2sol, double* in2mean, double* rel_resid) {
@@ -812,15 +859,18 @@ el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, 
 }
 
 el_status launch_local_solve_ex(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
-                                const double* kappa, const double* sigma, const int32_t* emap,
-                                void* o_i2o, void* o_i2s, int out_dtype, uint16_t* pairs) {
+                                const double* kappa, const double* sigma, const int32_t* emap, void* o_i2o,
+                                void* o_i2v, int form, int out_dtype, uint16_t* pairs) {
   LocalOut o;
+  const bool mean = form == EL_FORM_IN2MEAN;
   if (out_dtype == EL_F32) {
-    o.f_i2o = reinterpret_cast<float*>(o_i2o); o.f_i2s = reinterpret_cast<float*>(o_i2s);
+    o.f_i2o = reinterpret_cast<float*>(o_i2o);
+    (mean ? o.f_i2m : o.f_i2s) = reinterpret_cast<float*>(o_i2v);
   } else {
-    o.b_i2o = reinterpret_cast<uint16_t*>(o_i2o); o.b_i2s = reinterpret_cast<uint16_t*>(o_i2s);
+    o.b_i2o = reinterpret_cast<uint16_t*>(o_i2o);
+    (mean ? o.b_i2m : o.b_i2s) = reinterpret_cast<uint16_t*>(o_i2v);
   }
-  o.pairs = pairs; o.emap = emap;
+  o.pairs = pairs; o.pairs_form = form; o.emap = emap;
   return run_local(ctx, de, precision, E, h, kappa, sigma, o, nullptr);
 }
 

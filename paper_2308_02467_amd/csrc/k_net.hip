@@ -719,8 +719,8 @@ el_status forward_hidden(el_ctx* ctx, el_net* net, int64_t B, const Scratch& s, 
 }  // namespace
 
 el_status launch_local_solve_ex(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
-                                const double* kappa, const double* sigma, const int32_t* emap,
-                                void* o_i2o, void* o_i2s, int out_dtype, uint16_t* pairs);
+                                const double* kappa, const double* sigma, const int32_t* emap, void* o_i2o,
+                                void* o_i2v, int form, int out_dtype, uint16_t* pairs);
 
 }  // namespace el
 
@@ -895,14 +895,16 @@ el_status el_net_fit_normalization(el_ctx* ctx, el_net* net, int64_t N, const fl
 }
 
 el_status el_make_pairs(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa,
-                        const double* sigma, uint16_t* y) {
+                        const double* sigma, int form, uint16_t* y) {
   if (!ctx) return EL_ERR_ARG;
-  if (E <= 0 || !h || !kappa || !sigma || !y) return set_error(ctx, EL_ERR_ARG, "el_make_pairs: bad argument");
+  if (E <= 0 || !h || !kappa || !sigma || !y || (form != EL_FORM_IN2SOL && form != EL_FORM_IN2MEAN))
+    return set_error(ctx, EL_ERR_ARG, "el_make_pairs: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
-  return launch_local_solve_ex(ctx, de, EL_FP64, E, h, kappa, sigma, nullptr, nullptr, nullptr, EL_BF16, y);
+  const int precision = local_fp64_fits(ctx, de) ? EL_FP64 : EL_FP32_IR;
+  return launch_local_solve_ex(ctx, de, precision, E, h, kappa, sigma, nullptr, nullptr, nullptr, form, EL_BF16, y);
 }
 
 el_status el_net_forward(el_ctx* ctx, const el_net* cnet, int64_t B, const float* x, float* y_norm) {
@@ -990,7 +992,7 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
 }
 
 el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const double* h, const double* kappa,
-                   const double* sigma, void* in2out, void* in2sol, int out_dtype, uint8_t* in_range, int fallback,
+                   const double* sigma, void* in2out, void* in2vol, int out_dtype, uint8_t* in_range, int fallback,
                    int precision, int64_t* n_fallback_host) {
   if (!ctx || !cnet) return EL_ERR_ARG;
   if (E <= 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer: bad argument");
@@ -1002,9 +1004,15 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
   const DiscHost& dh = de->host;
-  const int64_t mm_ = (int64_t)dh.m * dh.m, nm = (int64_t)dh.n * dh.m;
-  if (net->desc.n_out != mm_ + nm || net->desc.n_in != 1 + 2 * dh.nn)
-    return set_error(ctx, EL_ERR_ARG, "el_infer: network sizes do not match the discretization");
+  const int64_t mm_ = (int64_t)dh.m * dh.m;
+  // the network's output size tells its form: (in2out, in2sol) or (in2out, in2mean)
+  int form;
+  if (net->desc.n_out == mm_ + (int64_t)dh.n * dh.m) form = EL_FORM_IN2SOL;
+  else if (net->desc.n_out == mm_ + (int64_t)dh.nn * dh.m) form = EL_FORM_IN2MEAN;
+  else return set_error(ctx, EL_ERR_ARG, "el_infer: network output size does not match the discretization");
+  const int64_t nm = net->desc.n_out - mm_;   // per-element size of in2sol or in2mean
+  if (net->desc.n_in != 1 + 2 * dh.nn)
+    return set_error(ctx, EL_ERR_ARG, "el_infer: network input size does not match the discretization");
   if (!net->fitted) return set_error(ctx, EL_ERR_STATE, "el_infer: network has no training statistics");
   const int D = net->desc.depth;
   const int64_t W = net->desc.width;
@@ -1031,7 +1039,7 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
     st = forward_hidden(ctx, net, B, s, false);
     if (st) break;
     char* po = in2out ? reinterpret_cast<char*>(in2out) + (size_t)e0 * mm_ * osz : nullptr;
-    char* ps = in2sol ? reinterpret_cast<char*>(in2sol) + (size_t)e0 * nm * osz : nullptr;
+    char* ps = in2vol ? reinterpret_cast<char*>(in2vol) + (size_t)e0 * nm * osz : nullptr;
     const uint16_t* Hl = s.H + (size_t)(D - 1) * B * W;
     if (out_dtype == EL_F32) {
       EpiOutOps<float> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<float*>(po),
@@ -1060,7 +1068,7 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
       nfb = hc;
       if (!st && fallback && hc > 0)
         st = launch_local_solve_ex(ctx, de, precision, hc, h, kappa, sigma, reinterpret_cast<int32_t*>(idx), in2out,
-                                   in2sol, out_dtype, nullptr);
+                                   in2vol, form, out_dtype, nullptr);
       hipStreamSynchronize(ctx->stream);
       hipFree(idx);
     }

@@ -172,18 +172,20 @@ template <> __device__ inline void st_op<uint16_t>(uint16_t* p, int64_t i, doubl
 // mask == 0 are left alone).
 template <typename T>
 __global__ void k_conserve(DiscDev dv, int64_t E, const double* __restrict__ h, const double* __restrict__ kappa,
-                           T* __restrict__ i2o, const T* __restrict__ i2s, const uint8_t* __restrict__ mask) {
+                           T* __restrict__ i2o, const T* __restrict__ i2s, int rows, double mult,
+                           const uint8_t* __restrict__ mask) {
   const int64_t e = blockIdx.x;
   if (e >= E || (mask && !mask[e])) return;
   extern __shared__ double wa[];   // [nn] = W_nd h kappa_nd / 2
-  const int nn = dv.nn, m = dv.m, n = dv.n;
+  const int nn = dv.nn, m = dv.m;
   for (int nd = threadIdx.x; nd < nn; nd += blockDim.x) wa[nd] = dv.W[nd] * 0.5 * h[e] * kappa[e * nn + nd];
   __syncthreads();
-  const T* S = i2s + (size_t)e * n * m;
+  const T* S = i2s + (size_t)e * rows * m;
   T* O = i2o + (size_t)e * m * m;
   for (int c = threadIdx.x; c < m; c += blockDim.x) {
     double absorb = 0.0;
-    for (int r = 0; r < n; ++r) absorb += wa[r % nn] * ld_op<T>(S, (int64_t)r * m + c);
+    for (int r = 0; r < rows; ++r) absorb += wa[r % nn] * ld_op<T>(S, (int64_t)r * m + c);
+    absorb *= mult;
     double out = 0.0;
     for (int o = 0; o < m; ++o) out += dv.out_val[o] * ld_op<T>(O, (int64_t)o * m + c);
     const double target = dv.in_val[c] - absorb;
@@ -197,17 +199,23 @@ __global__ void k_conserve(DiscDev dv, int64_t E, const double* __restrict__ h, 
 }  // namespace
 
 el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* kappa,
-                          void* in2out, const void* in2sol, int op_dtype, const uint8_t* mask) {
+                          void* in2out, const void* in2vol, int form, int op_dtype, const uint8_t* mask) {
   const size_t smem = sizeof(double) * de->host.nn;
+  // in2sol: absorption sums all (k, nd) rows; in2mean holds the ordinate
+  // average, so its nn rows are summed and multiplied by N_a
+  const bool mean = form == EL_FORM_IN2MEAN;
+  const int rows = mean ? de->host.nn : de->host.n;
+  const double mult = mean ? (double)de->host.n_a : 1.0;
   if (op_dtype == EL_F64)
     hipLaunchKernelGGL(k_conserve<double>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
-                       reinterpret_cast<double*>(in2out), reinterpret_cast<const double*>(in2sol), mask);
+                       reinterpret_cast<double*>(in2out), reinterpret_cast<const double*>(in2vol), rows, mult, mask);
   else if (op_dtype == EL_F32)
     hipLaunchKernelGGL(k_conserve<float>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
-                       reinterpret_cast<float*>(in2out), reinterpret_cast<const float*>(in2sol), mask);
+                       reinterpret_cast<float*>(in2out), reinterpret_cast<const float*>(in2vol), rows, mult, mask);
   else
     hipLaunchKernelGGL(k_conserve<uint16_t>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
-                       reinterpret_cast<uint16_t*>(in2out), reinterpret_cast<const uint16_t*>(in2sol), mask);
+                       reinterpret_cast<uint16_t*>(in2out), reinterpret_cast<const uint16_t*>(in2vol), rows, mult,
+                       mask);
   return hip_check(ctx, hipGetLastError(), "launch k_conserve");
 }
 

@@ -54,6 +54,7 @@ class el_net_desc(ctypes.Structure):
 
 EL_ACT_GELU = 0
 EL_ACT_ELU = 1
+EL_FORM_IN2SOL, EL_FORM_IN2MEAN = 0, 1
 
 
 class el_gmres_opts(ctypes.Structure):
@@ -97,7 +98,7 @@ _SIGS = {
     "el_mean_l2": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                    ctypes.POINTER(ctypes.c_double)],
     "el_conserve": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
+                    ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
     "el_net_create": [ctypes.c_void_p, ctypes.POINTER(el_net_desc), ctypes.POINTER(ctypes.c_void_p)],
     "el_net_destroy": [ctypes.c_void_p],
     "el_net_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
@@ -107,7 +108,7 @@ _SIGS = {
     "el_net_params": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
     "el_net_num_params": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
     "el_make_pairs": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                      ctypes.c_void_p],
+                      ctypes.c_int, ctypes.c_void_p],
     "el_train_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_float, ctypes.c_void_p],
     "el_net_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
@@ -306,16 +307,20 @@ class Context:
                                                  _ptr(trace, torch.float64, trace_size(d, ms), "trace"),
                                                  _ptr(mean, torch.float64, E * nn, "mean")))
 
-    def el_conserve(self, d, h, kappa, in2out, in2sol, mask=None):
+    def el_conserve(self, d, h, kappa, in2out, in2sol=None, mask=None, in2mean=None):
+        """Energy-balance correction of in2out given in2sol or in2mean."""
         nn, n, m = disc_sizes(d)
         E = h.numel()
+        if (in2sol is None) == (in2mean is None):
+            raise ValueError("give exactly one of in2sol, in2mean")
+        vol, form, rows = (in2sol, EL_FORM_IN2SOL, n) if in2sol is not None else (in2mean, EL_FORM_IN2MEAN, nn)
         dt = _op_dtype(in2out)
-        if _op_dtype(in2sol) != dt:
-            raise ValueError("in2out and in2sol must share one dtype")
+        if _op_dtype(vol) != dt:
+            raise ValueError("in2out and the volume operator must share one dtype")
         return self._check(lib().el_conserve(self.h, d, E, _ptr(h, torch.float64, E, "h"),
                                              _ptr(kappa, torch.float64, E * nn, "kappa"),
                                              _ptr(in2out, numel=E * m * m, name="in2out"),
-                                             _ptr(in2sol, numel=E * n * m, name="in2sol"), dt,
+                                             _ptr(vol, numel=E * rows * m, name="in2vol"), form, dt,
                                              _ptr(mask, torch.uint8, E, "mask")))
 
     def el_mean_l2(self, d, h, a, ref):
@@ -399,34 +404,42 @@ class Net:
                                              _ptr(y_norm, torch.float32, name="y_norm")))
 
     def infer(self, d, h, kappa, sigma, in2out=None, in2sol=None, in_range=None, fallback=True,
-              precision=EL_FP64):
-        """in2out / in2sol: bfloat16 or float32 device tensors (same dtype)."""
+              precision=EL_FP64, in2mean=None):
+        """in2out and in2sol (network in the in2sol form) or in2mean (in2mean
+        form): bfloat16 or float32 device tensors of one dtype."""
         nn, n, m = disc_sizes(d)
         E = h.numel()
-        ref = in2out if in2out is not None else in2sol
+        if in2sol is not None and in2mean is not None:
+            raise ValueError("give in2sol or in2mean, not both")
+        vol = in2sol if in2sol is not None else in2mean
+        rows = n if in2mean is None else nn
+        ref = in2out if in2out is not None else vol
         dt = _op_dtype(ref) if ref is not None else EL_BF16
         if dt not in (EL_BF16, EL_F32):
             raise ValueError("learned operators are stored as bfloat16 or float32")
-        for t, cnt, name in ((in2out, E * m * m, "in2out"), (in2sol, E * n * m, "in2sol")):
+        for t, cnt, name in ((in2out, E * m * m, "in2out"), (vol, E * rows * m, "in2sol/in2mean")):
             if t is not None and (_op_dtype(t) != dt or t.numel() != cnt):
                 raise ValueError(f"{name}: expected {cnt} elements of the common dtype")
         nfb = ctypes.c_int64()
         self.ctx._check(lib().el_infer(self.ctx.h, self.h, d, E, _ptr(h, torch.float64, E, "h"),
                                        _ptr(kappa, torch.float64, E * nn, "kappa"),
                                        _ptr(sigma, torch.float64, E * nn, "sigma"),
-                                       _ptr(in2out, name="in2out"), _ptr(in2sol, name="in2sol"), int(dt),
+                                       _ptr(in2out, name="in2out"), _ptr(vol, name="in2vol"), int(dt),
                                        _ptr(in_range, torch.uint8, E, "in_range"), int(bool(fallback)),
                                        int(precision), ctypes.byref(nfb)))
         return nfb.value
 
 
-def el_make_pairs(ctx, d, h, kappa, sigma, y):
+def el_make_pairs(ctx, d, h, kappa, sigma, y, form=None):
+    """bfloat16 targets (in2out, in2sol) or, with form EL_FORM_IN2MEAN, (in2out, in2mean)."""
     nn, n, m = disc_sizes(d)
     E = h.numel()
+    form = EL_FORM_IN2SOL if form is None else form
+    rows = n if form == EL_FORM_IN2SOL else nn
     ctx._check(lib().el_make_pairs(ctx.h, d, E, _ptr(h, torch.float64, E, "h"),
                                    _ptr(kappa, torch.float64, E * nn, "kappa"),
-                                   _ptr(sigma, torch.float64, E * nn, "sigma"),
-                                   _bf16_ptr(y, E * (m * m + n * m), "y")))
+                                   _ptr(sigma, torch.float64, E * nn, "sigma"), int(form),
+                                   _bf16_ptr(y, E * (m * m + rows * m), "y")))
 
 
 # ---- network state blob (format documented in include/el.h) -------------------

@@ -20,12 +20,14 @@ import torch
 from . import el, inputs
 
 
-def training_set(ctx, d, N, seed=1234, chunk=8192, log=True):
-    """(x [N, 1+2nn] float32 raw inputs, y [N, n_out] bfloat16 targets), on the device."""
+def training_set(ctx, d, N, seed=1234, chunk=8192, log=True, form=el.EL_FORM_IN2SOL, draws=None):
+    """(x [N, 1+2nn] float32 raw inputs, y [N, n_out] bfloat16 targets), on the device.
+    form: targets (in2out, in2sol) or (in2out, in2mean).  draws: optional
+    (h, kappa, sigma) arrays replacing the default training distribution."""
     nn, n, m = el.disc_sizes(d)
-    n_out = m * m + n * m
+    n_out = m * m + (n if form == el.EL_FORM_IN2SOL else nn) * m
     xi, _ = el.lgl(d.p)
-    h, kap, sig = inputs.training_draws(N, xi, seed=seed)
+    h, kap, sig = inputs.training_draws(N, xi, seed=seed) if draws is None else draws
     dev = torch.device(f"cuda:{ctx.device}")
     x = torch.as_tensor(np.concatenate([h[:, None], kap, sig], axis=1), dtype=torch.float32, device=dev)
     y = torch.empty((N, n_out), dtype=torch.bfloat16, device=dev)
@@ -34,7 +36,7 @@ def training_set(ctx, d, N, seed=1234, chunk=8192, log=True):
     S = torch.as_tensor(sig, dtype=torch.float64, device=dev)
     for c0 in range(0, N, chunk):
         c1 = min(N, c0 + chunk)
-        el.el_make_pairs(ctx, d, H[c0:c1], K[c0:c1], S[c0:c1], y[c0:c1])
+        el.el_make_pairs(ctx, d, H[c0:c1], K[c0:c1], S[c0:c1], y[c0:c1], form=form)
         if log:
             print(f"[learned] training pairs {c1}/{N}", file=sys.stderr, flush=True)
     return x, y

@@ -135,3 +135,22 @@ def test_fp32_ir_parity(ctx, p, n_a, g, E):
     print(f"[fp32_ir] max rel residual {res[0].max():.2e}", flush=True)
     assert np.all(res[0] <= 1e-13), res[0].max()
     _check(p, n_a, g, h, kap, sig, gpu, tol=1e-9)
+
+
+def test_fp32_ir_na32_hg_paper_cloud_size(ctx):
+    """The n = 1568 discretization of the realistic-cloud workload (p = 6,
+    N_a = 32, Henyey-Greenstein g = 0.85): FP32 LU + FP64 refinement against
+    the FP64 oracle element by element.  The FP64 factorization of this size
+    does not fit one workgroup and is refused with a clear error."""
+    from paper_2308_02467_amd import el
+    p, n_a, g, E = 6, 32, 0.85, 5
+    o = LocalDisc(p, n_a, g)
+    h, kap, sig = inputs.training_draws(E, o.xi, seed=77)
+    res = []
+    gpu = _gpu_local(ctx, p, n_a, g, h, kap, sig, precision=1, resid=res)
+    print(f"[fp32_ir n=1568] max rel residual {res[0].max():.2e}", flush=True)
+    assert np.all(res[0] <= 1e-13), res[0].max()
+    _check(p, n_a, g, h, kap, sig, gpu, tol=1e-9)
+    with pytest.raises(el.ElError) as exc:
+        _gpu_local(ctx, p, n_a, g, h[:1], kap[:1], sig[:1], outputs=("in2out",), precision=0)
+    assert "LDS" in str(exc.value) or "too large" in str(exc.value)

@@ -253,3 +253,67 @@ def test_training_learns_the_operator(ctx):
     print(f"[train] untrained {e0:.3e}, mean operator {emean:.3e}, trained {e1:.3e}", flush=True)
     assert e1 < 0.2 * emean and e1 < 0.1 * e0
     net.close()
+
+
+def test_make_pairs_in2mean_form(ctx):
+    """Targets (in2out, in2mean): the oracle's in2mean rounded to bfloat16."""
+    from paper_2308_02467_amd import el
+    p, n_a = 3, 8
+    o = LocalDisc(p, n_a)
+    h, kap, sig = inputs.training_draws(24, o.xi, seed=19)
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    y = torch.empty((24, m * m + nn * m), dtype=torch.bfloat16, device=DEV)
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
+    print("[el_make_pairs] in2mean form", flush=True)
+    el.el_make_pairs(ctx, d, T(h), T(kap), T(sig), y, form=el.EL_FORM_IN2MEAN)
+    i2o, _, i2m = local_solve_batch(o, h, kap, sig)
+    ref = np.concatenate([i2o.reshape(24, -1), i2m.reshape(24, -1)], axis=1)
+    got = y.to(torch.float64).cpu().numpy()
+    assert np.all(np.abs(got - bf16_round(ref)) <= 2.0 ** -7 * np.abs(ref) + 1e-30)
+    assert np.mean(got == bf16_round(ref)) > 0.99
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_infer_in2mean_form_with_fallback(ctx, dtype):
+    """A network in the in2mean form writes (in2out, in2mean); elements
+    outside the training box get the plain solver's in2out and in2mean."""
+    from paper_2308_02467_amd import el
+    p, n_a = 2, 4
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    n_in, n_out = 1 + 2 * nn, m * m + nn * m
+    rng = np.random.default_rng(23)
+    hn = _host_net(rng, n_in, 64, 2, n_out)
+    box = (0.01, 0.05, 0.02, 2.0, 0.1, 20.0)
+    net = _load(ctx, hn, n_in, 64, 2, n_out, box=box)
+    E = 30
+    o = LocalDisc(p, n_a)
+    hh = rng.uniform(0.012, 0.048, E)
+    kap = rng.uniform(0.03, 1.9, (E, nn))
+    sig = rng.uniform(0.2, 19, (E, nn))
+    out_idx = [4, 22]
+    sig[4, 1] = 40.0
+    hh[22] = 0.3
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
+    i2o = torch.empty((E, m, m), dtype=dtype, device=DEV)
+    i2m = torch.empty((E, nn, m), dtype=dtype, device=DEV)
+    print(f"[el_infer] in2mean form {dtype}", flush=True)
+    nfb = net.infer(d, T(hh), T(kap), T(sig), i2o, in2mean=i2m, fallback=True)
+    assert nfb == 2
+    r_o, _, r_m = local_solve_batch(o, hh[out_idx], kap[out_idx], sig[out_idx])
+    tol = 2.0 ** -7 if dtype == torch.bfloat16 else 1e-6
+    got_m = i2m.to(torch.float64).cpu().numpy()[out_idx]
+    got_o = i2o.to(torch.float64).cpu().numpy()[out_idx]
+    assert np.all(np.abs(got_m - r_m) <= tol * np.abs(r_m) + 1e-30)
+    assert np.all(np.abs(got_o - r_o) <= tol * np.abs(r_o) + 1e-30)
+    x = np.concatenate([hh[:, None], kap, sig], axis=1)
+    X0 = features(x, hn["fm"].astype(np.float64), hn["fs"].astype(np.float64), hn["k0"])
+    yn, _ = hn["oracle"].forward(X0, bf16=True)
+    yv = yn * hn["ys"].astype(np.float64) + hn["ym"].astype(np.float64)
+    keep = np.ones(E, bool)
+    keep[out_idx] = False
+    got = np.concatenate([i2o.to(torch.float64).cpu().numpy().reshape(E, -1),
+                          i2m.to(torch.float64).cpu().numpy().reshape(E, -1)], axis=1)
+    assert rel_err(got[keep], yv[keep]) <= 1e-2
+    net.close()

@@ -302,3 +302,30 @@ def test_batched_single_mesh_converged_and_empty_rhs(ctx):
     ref = oracle_pipeline(od, oms, hh, kap, sig, inputs.left_inflow(n_a))
     assert rel_err(t1.cpu().numpy(), ref["t"]) <= 1e-10
     assert rep[1]["restarts"] >= 1
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_conserve_in2mean_form(ctx, dtype):
+    """The balance with the ordinate-averaged operator: exact (in2out, in2mean)
+    pairs are left unchanged and perturbed ones are restored."""
+    from paper_2308_02467_amd import el
+    p, n_a = 3, 8
+    o = LocalDisc(p, n_a)
+    h, kap, sig = inputs.training_draws(12, o.xi, seed=6)
+    i2o, _, i2m = local_solve_batch(o, h, kap, sig)
+    d = el.disc(p, n_a)
+    wout = np.array([o.omega[j] * o.sn[k, f] for (f, k, j, nd, r) in o.out_tab])
+    win = np.array([-o.omega[j] * o.sn[k, f] for (f, k, j, nd, r) in o.in_tab])
+    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    O = T(i2o).to(dtype)
+    Mn = T(i2m).to(dtype)
+    print(f"[el_conserve] in2mean {dtype}", flush=True)
+    ctx.el_conserve(d, T(h), T(kap), O, in2mean=Mn)
+    assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= (1e-13 if dtype == torch.float64 else 1e-6)
+    rng = np.random.default_rng(2)
+    Op = T(i2o * (1 + 0.02 * rng.standard_normal(i2o.shape))).to(dtype)
+    ctx.el_conserve(d, T(h), T(kap), Op, in2mean=Mn)
+    got = Op.to(torch.float64).cpu().numpy()
+    ab = n_a * np.einsum("n,enm->em", o.W, (0.5 * h[:, None, None] * kap[:, :, None]) * Mn.to(torch.float64).cpu().numpy())
+    bal = np.einsum("o,eom->em", wout, got) + ab - win[None, :]
+    assert np.abs(bal).max() <= tol * np.abs(win).max()
