@@ -59,6 +59,14 @@ def parse():
     ap.add_argument("--no-conserve", action="store_true", help="skip the energy-balance correction")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-meshes leg (8 meshes of 16^2 .. 128^2 elements in one solve)")
+    ap.add_argument("--cloud", action="store_true",
+                    help="run only the realistic-cloud leg (256^2 elements, p=6, N_a=32, HG g=0.85, "
+                         "log-normal sigma, learned in2mean form + FP32-refinement fallback)")
+    ap.add_argument("--cloud-n", type=int, default=256)
+    ap.add_argument("--cloud-train-samples", type=int, default=65536)
+    ap.add_argument("--cloud-epochs", type=int, default=60)
     return ap.parse_args()
 
 
@@ -73,6 +81,10 @@ def main():
         sys.exit(2)
     import torch
     from paper_2308_02467_amd import el, inputs
+
+    if args.cloud:
+        print(json.dumps(cloud_main(args)))
+        return
 
     dev = torch.device("cuda:0")
     p, n_a, nx = 6, 16, args.n
@@ -169,9 +181,16 @@ def main():
         log("accuracy diagnostics")
         acc = accuracy(ctx, d, ms, hh, i2o, i2s, b, mean, args.restart)
 
+    batched = None
+    if not args.no_batched:
+        del i2s, u
+        torch.cuda.empty_cache()
+        batched = batched_leg(args, ctx, el, inputs, stream)
+        i2s = u = None
+
     learned = None
     if not args.no_learned:
-        del i2s, i2m, u
+        i2s = i2m = u = None
         torch.cuda.empty_cache()
         learned = learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o, mean, stream, E, nn, n, m)
 
@@ -207,10 +226,247 @@ def main():
         "learned": learned,
         "speedup_learned_vs_plain": (plain_ms / learned["ms_per_step"]) if learned else None,
         "fp32_ir": fp32_ir,
+        "batched_meshes": batched,
+        "gemm_tiles": el.tuning_report().strip().split("\n") if el.tuning_report().strip() else [],
         "accuracy": acc,
     }
     print(json.dumps(out))
     ctx.close()
+
+
+BATCH_SIDES = (16, 32, 48, 64, 64, 96, 128, 128)
+
+
+def batched_leg(args, ctx, el, inputs, stream):
+    """Eight independent solves of 16^2 .. 128^2 elements (p = 6, N_a = 16,
+    sharp cloud edge with a seeded random centre per mesh) in one pass: one
+    local solve over all 53,760 elements, one GMRES over all eight skeleton
+    systems (captured restart cycle), recovery of the mean intensity."""
+    import torch
+    dev = torch.device("cuda:0")
+    p, n_a = 6, 16
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    xi, _ = el.lgl(p)
+    g_side = inputs.left_inflow(n_a)
+    hs, ks, ss, meshes = [], [], [], []
+    for i, s_ in enumerate(BATCH_SIDES):
+        h = 1.0 / s_
+        X, Y = inputs.element_node_coords(s_, s_, h, xi)
+        kap, sig = inputs.sharp_cloud(X, Y, seed=100 + i)
+        hs.append(np.full(s_ * s_, h)); ks.append(kap); ss.append(sig)
+        meshes.append(el.mesh(s_, s_, h))
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    H, K, S = T(np.concatenate(hs)), T(np.concatenate(ks)), T(np.concatenate(ss))
+    E = H.numel()
+    i2o = torch.empty((E, m, m), dtype=torch.float64, device=dev)
+    i2m = torch.empty((E, nn, m), dtype=torch.float64, device=dev)
+    offs = np.cumsum([0] + [s_ * s_ for s_ in BATCH_SIDES])
+    bs = [torch.empty(el.trace_size(d, ms), dtype=torch.float64, device=dev) for ms in meshes]
+    ts = [torch.empty_like(b) for b in bs]
+    means = [torch.empty((s_ * s_, nn), dtype=torch.float64, device=dev) for s_ in BATCH_SIDES]
+    ops = [i2o[offs[i]:offs[i + 1]] for i in range(len(meshes))]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    rec = []
+
+    def step(record, graph=True):
+        e = [ev() for _ in range(4)]
+        e[0].record(stream)
+        ctx.el_local_solve(d, H, K, S, in2out=i2o, in2mean=i2m)
+        e[1].record(stream)
+        for ms, b in zip(meshes, bs):
+            ctx.el_trace_rhs(d, ms, g_side, b)
+        st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=args.tol, restart=args.restart, max_iter=20000,
+                                     graph=graph)
+        e[2].record(stream)
+        for i, ms in enumerate(meshes):
+            ctx.el_recover_mean(d, ms, i2m[offs[i]:offs[i + 1]], ts[i], means[i])
+        e[3].record(stream)
+        if record:
+            rec.append((e, rep))
+
+    log(f"batched meshes {BATCH_SIDES}: {E} elements")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - w0) * 1e3 / args.steps
+    ph = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(3)] for r in rec])
+    # the same eight skeleton solves one mesh at a time, for comparison
+    t_seq = ev(), ev()
+    t_seq[0].record(stream)
+    seq_iters = []
+    for i, ms in enumerate(meshes):
+        st, rp = ctx.el_trace_solve(d, [ms], [ops[i]], [bs[i]], [ts[i]], tol=args.tol, restart=args.restart,
+                                    max_iter=20000)
+        seq_iters.append(rp[0]["iters"])
+    t_seq[1].record(stream)
+    torch.cuda.synchronize()
+    reps = rec[-1][1]
+    out = {
+        "workload": f"{len(BATCH_SIDES)} meshes of {'/'.join(f'{s_}^2' for s_ in BATCH_SIDES)} elements, p=6, "
+                    "N_a=16, sharp cloud edge (seeded random centres), plain FP64, one GMRES over all meshes",
+        "elements": int(E), "ms_per_step": ms_step, "value": E / (ms_step * 1e-3),
+        "unit": "element solves/s (whole batched step)",
+        "phases_ms": {"local_solve": float(np.median(ph[:, 0])), "rhs_and_gmres": float(np.median(ph[:, 1])),
+                      "recover_mean": float(np.median(ph[:, 2]))},
+        "gmres_per_mesh": [{"side": s_, "iters": r["iters"], "relres": r["relres"], "converged": r["converged"]}
+                           for s_, r in zip(BATCH_SIDES, reps)],
+        "gmres_one_mesh_at_a_time_ms": t_seq[0].elapsed_time(t_seq[1]),
+        "gmres_one_mesh_at_a_time_iters": seq_iters,
+    }
+    del i2o, i2m
+    torch.cuda.empty_cache()
+    return out
+
+
+def cloud_main(args):
+    """Realistic synthetic cloud: 256^2 elements, p = 6, N_a = 32, Henyey-
+    Greenstein g = 0.85, sigma a seeded log-normal field with a k^(-5/3)
+    spectrum (mean 10, log-std 1) set to zero where the field is negative,
+    kappa = 0.05 sigma + 0.01, radiance 1 entering through the left side.
+    The network (in2mean form) is trained on elements drawn from
+    independently seeded fields of the same statistics; elements outside its
+    training box go to the FP32 + refinement local solver.  Reference: the
+    FP32 + refinement local solve of every element (operators stored as
+    float32) and GMRES to 1e-8."""
+    import torch
+    from paper_2308_02467_amd import el, inputs, learned
+    dev = torch.device("cuda:0")
+    ctx = el.Context(0)
+    stream = torch.cuda.current_stream()
+    p, n_a, g, nx = 6, 32, 0.85, args.cloud_n
+    h = 1.0 / nx
+    d = el.disc(p, n_a, g)
+    ms = el.mesh(nx, nx, h)
+    nn, n, m = el.disc_sizes(d)
+    E = nx * nx
+    xi, _ = el.lgl(p)
+    X, Y = inputs.element_node_coords(nx, nx, h, xi)
+    kap_np, sig_np = inputs.lognormal_cloud(X, Y, seed=2024)
+    g_side = inputs.left_inflow(n_a)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    hh, kap, sig = T(np.full(E, h)), T(kap_np), T(sig_np)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    n_out = m * m + nn * m
+
+    # training elements: random elements of independently seeded fields
+    rng = np.random.default_rng(7)
+    per = max(1, args.cloud_train_samples // 4)
+    hs, ks, ss = [], [], []
+    for f in range(4):
+        kf, sf = inputs.lognormal_cloud(X, Y, seed=3000 + f)
+        sel = rng.choice(E, size=per, replace=False)
+        hs.append(np.full(per, h)); ks.append(kf[sel]); ss.append(sf[sel])
+    draws = (np.concatenate(hs), np.concatenate(ks), np.concatenate(ss))
+    N = draws[0].size
+    log(f"cloud: {N} training pairs (in2mean form, n = {n})")
+    t0 = time.perf_counter()
+    x, y = learned.training_set(ctx, d, N, form=el.EL_FORM_IN2MEAN, draws=draws)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    net = el.Net.create(ctx, 1 + 2 * nn, args.width, args.depth, n_out, seed=0)
+    net.fit_normalization(x, y)
+    t0 = time.perf_counter()
+    hist = learned.train(net, x, y, args.cloud_epochs, batch=4096, lr=1e-3, time_limit=args.train_time_limit,
+                         decay_at=args.lr_decay)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, y
+    torch.cuda.empty_cache()
+
+    nt = el.trace_size(d, ms)
+    b = torch.empty(nt, dtype=torch.float64, device=dev)
+    ctx.el_trace_rhs(d, ms, g_side, b)
+
+    # reference: FP32 + refinement for every element, GMRES to 1e-8
+    log("cloud: reference local solve (FP32 + refinement, all elements)")
+    ro = torch.empty((E, m, m), dtype=torch.float32, device=dev)
+    rmn = torch.empty((E, nn, m), dtype=torch.float64, device=dev)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    chunk = 16384
+    for c0 in range(0, E, chunk):
+        c1 = min(E, c0 + chunk)
+        tmp_o = torch.empty((c1 - c0, m, m), dtype=torch.float64, device=dev)
+        ctx.el_local_solve(d, hh[c0:c1], kap[c0:c1], sig[c0:c1], precision=el.EL_FP32_IR, in2out=tmp_o,
+                           in2mean=rmn[c0:c1])
+        ro[c0:c1] = tmp_o.to(torch.float32)
+        del tmp_o
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ref_local_ms = e0.elapsed_time(e1)
+    t_ref = torch.empty_like(b)
+    log("cloud: reference GMRES")
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    st, rep_ref = ctx.el_trace_solve(d, [ms], [ro], [b], [t_ref], tol=1e-8, restart=args.restart, max_iter=40000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ref_gmres_ms = e0.elapsed_time(e1)
+    mean_ref = torch.empty((E, nn), dtype=torch.float64, device=dev)
+    ctx.el_recover_mean(d, ms, rmn, t_ref, mean_ref)
+    del rmn
+
+    lo = torch.empty((E, m, m), dtype=torch.float32, device=dev)
+    lm = torch.empty((E, nn, m), dtype=torch.float32, device=dev)
+    mask = torch.empty(E, dtype=torch.uint8, device=dev)
+    t = torch.empty_like(b)
+    mean = torch.empty_like(mean_ref)
+    rec = []
+
+    def step(record):
+        e = [ev() for _ in range(4)]
+        e[0].record(stream)
+        nfb = net.infer(d, hh, kap, sig, lo, in2mean=lm, in_range=mask, fallback=True, precision=el.EL_FP32_IR)
+        ctx.el_conserve(d, hh, kap, lo, in2mean=lm, mask=mask)
+        e[1].record(stream)
+        ctx.el_trace_rhs(d, ms, g_side, b)
+        st, rep = ctx.el_trace_solve(d, [ms], [lo], [b], [t], tol=args.tol, restart=args.restart, max_iter=40000)
+        e[2].record(stream)
+        ctx.el_recover_mean(d, ms, lm, t, mean)
+        e[3].record(stream)
+        if record:
+            rec.append((e, rep[0], nfb))
+
+    log("cloud: learned solve")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - w0) * 1e3 / args.steps
+    ph = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(3)] for r in rec])
+    d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_ref)
+    out = {
+        "metric": "element solves/s + full solve time at 1e-3 rel L2, learned vs plain (p=6)",
+        "value": E / (ms_step * 1e-3), "unit": "element solves/s (whole learned step)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"realistic cloud: {nx}x{nx} elements, p=6, N_a=32, HG g=0.85, log-normal sigma "
+                               "(k^-5/3, mean 10, log-std 1, zero below threshold), kappa=0.05 sigma+0.01, "
+                               "learned in2mean form + FP32-refinement fallback, FP64 GMRES",
+                   "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol, "gmres_restart": args.restart},
+        "network": f"{1 + 2 * nn}-{args.width}x{args.depth}-{n_out} GELU (in2out + in2mean)",
+        "train_samples": N, "epochs_run": len(hist), "final_train_loss": hist[-1] if hist else None,
+        "pair_generation_s": t_gen, "training_s": t_train,
+        "phases_ms": {"infer_fallback_and_correction": float(np.median(ph[:, 0])),
+                      "rhs_and_gmres": float(np.median(ph[:, 1])), "recover_mean": float(np.median(ph[:, 2]))},
+        "fallback_elements": rec[-1][2], "gmres": rec[-1][1],
+        "mean_intensity_rel_l2_vs_reference": (d2 / r2) ** 0.5,
+        "reference": {"local_solve_ms": ref_local_ms, "local_solve_el_per_s": E / (ref_local_ms * 1e-3),
+                      "gmres_ms": ref_gmres_ms, "gmres": rep_ref[0], "operator_storage": "float32"},
+        "reference_step_ms": ref_local_ms + ref_gmres_ms,
+    }
+    net.close()
+    ctx.close()
+    return out
 
 
 def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_plain, stream, E, nn, n, m):
