@@ -104,6 +104,7 @@ typedef struct {
   int restarts;
   double relres;  /* true relative residual at exit */
   int converged;
+  int reorth_passes;  /* Arnoldi steps that needed the second Gram-Schmidt pass */
 } el_gmres_report;
 
 /* ---- context -------------------------------------------------------------- */
@@ -160,9 +161,10 @@ el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2o
                           int op_dtype, const double* x, double* y);
 
 /* Solve (I - P) t = b for n_mesh independent meshes of any sizes together
- * with restarted GMRES (Sec. 2.3): x0 = 0, classical Gram-Schmidt with DGKS
- * reorthogonalization (second pass when the norm drops below 1/sqrt(2)),
- * Givens rotations, FP64 vectors and reductions.  All meshes share every
+ * with restarted GMRES (Sec. 2.3): x0 = 0, Arnoldi on P (the Krylov space
+ * of I - P is the same; the Hessenberg matrix of I - P follows exactly),
+ * classical Gram-Schmidt with DGKS reorthogonalization (second pass when the
+ * norm drops below 1/sqrt(2)), Givens rotations, FP64 vectors and reductions.  All meshes share every
  * launch; the Arnoldi scalars stay on the device and the host synchronizes
  * once per restart cycle.  A mesh stops when its true relative residual
  * <= opts->tol (checked at each cycle start) or after max_iter steps.

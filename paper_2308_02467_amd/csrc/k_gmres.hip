@@ -10,10 +10,15 @@
 // converged or stopped simply makes the later launches skip its blocks.
 //
 // Per Arnoldi step (the same for every mesh):
-//   w = (I - P) v_j;  h = V^T w and |w|^2 (one pass);  w -= V h and |w|^2;
+//   w = P v_j;  h = V^T w and |w|^2 (one pass);  w -= V h and |w|^2;
 //   when |w| < |w_before| / sqrt(2) (DGKS test, decided on the device) a
-//   second classical Gram-Schmidt pass;  Givens update of the least-squares
-//   problem and the stopping test on the device;  v_{j+1} = w / |w|.
+//   second classical Gram-Schmidt pass;  v_{j+1} = w / |w|.
+// The Krylov spaces of P and I - P are the same, and (I - P) V_j =
+// V_{j+1} (I~ - H_P), so the least-squares problem of I - P is updated with
+// the column e_j - h (and -|w| below the diagonal) by Givens rotations on
+// the device, with the stopping test.  Arnoldi on P instead of I - P avoids
+// projecting out the large v_j component of (I - P) v_j, so the second
+// Gram-Schmidt pass is needed less often.
 // One restart cycle (restart steps) is captured once as a HIP graph and
 // replayed; the host synchronizes once per cycle, after the true residual
 // b - (I - P) x of every mesh has been formed and tested.  x0 = 0; all
@@ -55,6 +60,7 @@ struct BState {
   int kused;           // Arnoldi steps taken in the current cycle
   int iters, restarts;
   int done, conv, bad;
+  int reorths;         // second Gram-Schmidt passes taken
 };
 
 // Per-mesh array of S doubles: Hessenberg matrix (column-major, R+1 rows),
@@ -118,7 +124,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---- products -----------------------------------------------------------------
-template <typename OpT>
+template <typename OpT, bool IMP>
 __global__ void __launch_bounds__(kMVThreads) k_bmatvec(DiscDev dv, const BMesh* __restrict__ ms, int n_mesh,
                                                          const BState* __restrict__ st, int pred,
                                                          const double* __restrict__ x, double* __restrict__ y) {
@@ -128,8 +134,8 @@ __global__ void __launch_bounds__(kMVThreads) k_bmatvec(DiscDev dv, const BMesh*
   const BMesh M = ms[mi];
   const int e = (int)((int64_t)blockIdx.x - M.e0);
   const MeshDev md{M.n_x, M.n_y, M.n_vf};
-  matvec_element<OpT>(dv, md, e, reinterpret_cast<const OpT*>(M.op) + (size_t)e * dv.m * dv.m, x + M.d0,
-                      y + M.d0, tin);
+  matvec_element<OpT, IMP>(dv, md, e, reinterpret_cast<const OpT*>(M.op) + (size_t)e * dv.m * dv.m, x + M.d0,
+                           y + M.d0, tin);
 }
 
 // ---- vector kernels (one block = kChunk DOFs of one mesh) ---------------------
@@ -395,9 +401,12 @@ __global__ void k_bgivens(int j, int n_mesh, double* __restrict__ hs, BLay lay, 
   double* cs = B + lay.cs;
   double* sn = B + lay.sn;
   double* g = B + lay.g;
-  for (int i = 0; i <= j; ++i) col[i] = s.reorth ? h1[i] + h2[i] : h1[i];
+  // Arnoldi on P: P v_j = V h + |w| v_{j+1}, so column j of the Hessenberg
+  // matrix of I - P is e_j - h with -|w| below the diagonal
+  for (int i = 0; i <= j; ++i) col[i] = (i == j ? 1.0 : 0.0) - (s.reorth ? h1[i] + h2[i] : h1[i]);
   const double hn = sqrt(fmax(s.reorth ? B[lay.sc + 3] : B[lay.sc + 2], 0.0));
-  col[j + 1] = hn;
+  s.reorths += s.reorth;
+  col[j + 1] = -hn;
   for (int i = 0; i < j; ++i) {
     const double a0 = col[i], a1 = col[i + 1];
     col[i] = cs[i] * a0 + sn[i] * a1;
@@ -460,17 +469,23 @@ struct Batch {
   BState* st;        // [n_mesh]
   BMesh* ms;         // [n_mesh]
 
-  void matvec(hipStream_t s, int pred, const double* x, double* y) const {
+  // imp: y = (I - P) x (true residuals); otherwise y = P x (Arnoldi)
+  template <bool IMP>
+  void matvec_t(hipStream_t s, int pred, const double* x, double* y) const {
     const size_t smem = sizeof(double) * m;
     if (op_dtype == EL_F64)
-      hipLaunchKernelGGL(k_bmatvec<double>, dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st, pred,
-                         x, y);
-    else if (op_dtype == EL_F32)
-      hipLaunchKernelGGL(k_bmatvec<float>, dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st, pred,
-                         x, y);
-    else
-      hipLaunchKernelGGL(k_bmatvec<uint16_t>, dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
+      hipLaunchKernelGGL((k_bmatvec<double, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
                          pred, x, y);
+    else if (op_dtype == EL_F32)
+      hipLaunchKernelGGL((k_bmatvec<float, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
+                         pred, x, y);
+    else
+      hipLaunchKernelGGL((k_bmatvec<uint16_t, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh,
+                         st, pred, x, y);
+  }
+  void matvec(hipStream_t s, int pred, const double* x, double* y, bool imp) const {
+    if (imp) matvec_t<true>(s, pred, x, y);
+    else matvec_t<false>(s, pred, x, y);
   }
   void dot(hipStream_t s, int pred, int cnt, const double* w, int self, int dst, int decide = -1) const {
     const int outc = cnt + (self ? 1 : 0);
@@ -491,7 +506,7 @@ struct Batch {
   void step(hipStream_t s, int j) const {
     const int cnt = j + 1;
     double* w = V + (size_t)(j + 1) * Np;
-    matvec(s, P_ACTIVE, V + (size_t)j * Np, w);
+    matvec(s, P_ACTIVE, V + (size_t)j * Np, w, false);
     dot(s, P_ACTIVE, cnt, w, 1, lay.h1);
     update(s, P_ACTIVE, cnt, lay.h1, w, 1.0, lay.sc + 2, cnt);
     dot(s, P_REORTH, cnt, w, 0, lay.h2);
@@ -607,7 +622,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   std::vector<BState> hst(n_mesh);
   for (;;) {
     // true residual r = b - (I - P) x into V[0], its norm, test, v0 = r / |r|
-    bt.matvec(s, P_NOT_DONE, bt.xcat, bt.tmp);
+    bt.matvec(s, P_NOT_DONE, bt.xcat, bt.tmp, true);
     hipLaunchKernelGGL(k_bsub, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.bcat, bt.tmp, bt.V, bt.ms, n_mesh, bt.st,
                        P_NOT_DONE);
     hipLaunchKernelGGL(k_bdot, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.V, (int64_t)0, 0, bt.V, 1, bt.ms, n_mesh,
@@ -650,6 +665,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
     rep[i].restarts = hst[i].restarts;
     rep[i].relres = hst[i].bn == 0.0 ? 0.0 : hst[i].relres;
     rep[i].converged = hst[i].conv;
+    rep[i].reorth_passes = hst[i].reorths;
     if (!hst[i].conv) all_conv = false;
   }
   if (!all_conv) {

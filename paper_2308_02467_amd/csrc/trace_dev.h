@@ -80,10 +80,11 @@ __device__ inline double row_dot<uint16_t>(const uint16_t* __restrict__ row, con
   return acc;
 }
 
-// y = x - in2out_e x_in at the outflow DOFs of element e; domain-inflow DOFs
-// of e are copied through (y = x there).  x, y: the mesh's trace vectors;
-// tin: m doubles of LDS.
-template <typename OpT>
+// IMP: y = x - in2out_e x_in at the outflow DOFs of element e and y = x on
+// the domain-inflow DOFs it sees, i.e. y = (I - P) x; !IMP: y = in2out_e x_in
+// and 0 on the domain-inflow DOFs, i.e. y = P x.  x, y: the mesh's trace
+// vectors; tin: m doubles of LDS.
+template <typename OpT, bool IMP = true>
 __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int e, const OpT* __restrict__ op_e,
                                       const double* __restrict__ x, double* __restrict__ y, double* tin) {
   const int i = e % ms.n_x, j = e / ms.n_x;
@@ -94,22 +95,31 @@ __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int 
     const int dof = (F * dv.n_a + dv.in_k[t]) * dv.q + dv.in_j[t];
     const double v = x[dof];
     tin[t] = v;
-    if (on_domain_boundary(ms, i, j, f)) y[dof] = v;
+    if (on_domain_boundary(ms, i, j, f)) y[dof] = IMP ? v : 0.0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 3, gl = lane & 7;
-  for (int o = wave * 8 + g; o < m; o += (kMVThreads / 64) * 8) {
-    double acc = row_dot<OpT>(op_e + (size_t)o * m, tin, m, gl);
+  constexpr int kRowStep = (kMVThreads / 64) * 8;   // rows per pass of the block
+  auto finish = [&](int o, double acc) {
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
     acc += __shfl_xor(acc, 4);
     if (gl == 0) {
       const int F = face_of(ms, i, j, dv.out_f[o]);
       const int dof = (F * dv.n_a + dv.out_k[o]) * dv.q + dv.out_j[o];
-      y[dof] = x[dof] - acc;
+      y[dof] = IMP ? x[dof] - acc : acc;
     }
+  };
+  // two rows per group at a time: twice the loads in flight
+  int o = wave * 8 + g;
+  for (; o + kRowStep < m; o += 2 * kRowStep) {
+    const double a0 = row_dot<OpT>(op_e + (size_t)o * m, tin, m, gl);
+    const double a1 = row_dot<OpT>(op_e + (size_t)(o + kRowStep) * m, tin, m, gl);
+    finish(o, a0);
+    finish(o + kRowStep, a1);
   }
+  if (o < m) finish(o, row_dot<OpT>(op_e + (size_t)o * m, tin, m, gl));
 }
 
 }  // namespace el

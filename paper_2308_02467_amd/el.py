@@ -64,7 +64,7 @@ class el_gmres_opts(ctypes.Structure):
 
 class el_gmres_report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("relres", ctypes.c_double),
-                ("converged", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("reorth_passes", ctypes.c_int)]
 
 
 _lib = None
@@ -288,8 +288,8 @@ class Context:
         rep = (el_gmres_report * k)()
         st = lib().el_trace_solve(self.h, d, k, M, ops, dt.pop(), B, X, ctypes.byref(opts), rep)
         self._check(st, allow_warn=True)
-        return st, [dict(iters=r.iters, restarts=r.restarts, relres=r.relres, converged=bool(r.converged))
-                    for r in rep]
+        return st, [dict(iters=r.iters, restarts=r.restarts, relres=r.relres, converged=bool(r.converged),
+                         reorth_passes=r.reorth_passes) for r in rep]
 
     # -- recovery ------------------------------------------------------------------
     def el_recover(self, d, ms, in2sol, trace, u=None, mean=None):
