@@ -20,8 +20,10 @@ the learned mean intensity against the plain FP64 solve and the CPU oracle
 timed on a bounded sample are reported beside it.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -72,6 +74,31 @@ def parse():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+MATVEC_SOURCES = ("paper_2308_02467_amd/csrc/trace_dev.h", "paper_2308_02467_amd/csrc/k_trace.hip")
+TRAFFIC_SUMMARY = "profiles/k_matvec_float_128x128_p6_na16_hbm_traffic.md"
+
+
+def matvec_source_hash():
+    h = hashlib.sha256()
+    for f in MATVEC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch of k_matvec<float> from the committed rocprofv3
+    counter summary, or None when the kernel's source changed since."""
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_SUMMARY)).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch k_matvec<float> = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
+    if not m or m.group(2) != matvec_source_hash():
+        return None
+    return float(m.group(1))
 
 
 def main():
@@ -565,9 +592,11 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
         "without_correction": {"mean_intensity_rel_l2_vs_plain": err_raw,
                                "in2out_rel_err_median": float(np.median(op_raw))},
         "operator_storage": "float32",
-        "roofline_matvec": {"bound": "hbm", "kernel": "k_matvec<float>", "achieved": mv_gbs, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS, "bytes_per_launch": mv_bytes,
-                            "avg_launch_ms": mv_ms},
+        "roofline_matvec": {"bound": "hbm",
+                            "kernel": "k_matvec<float> (element body shared with the GMRES product k_bmatvec<float>)",
+                            "achieved": mv_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(),
+                            "bytes_per_launch": mv_bytes, "avg_launch_ms": mv_ms},
     }
     net.close()
     return out
