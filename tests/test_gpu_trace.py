@@ -329,3 +329,54 @@ def test_conserve_in2mean_form(ctx, dtype):
     ab = n_a * np.einsum("n,enm->em", o.W, (0.5 * h[:, None, None] * kap[:, :, None]) * Mn.to(torch.float64).cpu().numpy())
     bal = np.einsum("o,eom->em", wout, got) + ab - win[None, :]
     assert np.abs(bal).max() <= tol * np.abs(win).max()
+
+
+def test_batched_full_size_sampled_and_energy(ctx):
+    """The batched workload at its real sizes (meshes of 16^2 ... 128^2
+    elements, p = 6, N_a = 16, sharp cloud edge): one local solve over all
+    53,760 elements and one GMRES over the eight skeleton systems.  Checked
+    by sampled element operators against the oracle, the true residual of
+    every mesh, and every mesh's global energy balance (incoming = outgoing
+    + absorbed, the absorption from the mean intensity)."""
+    from paper_2308_02467_amd import el
+    p, n_a = 6, 16
+    sides = (16, 32, 48, 64, 64, 96, 128, 128)
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    o = LocalDisc(p, n_a)
+    probs = []
+    for i, s_ in enumerate(sides):
+        od, oms, hh, kap, sig = mesh_problem(p, n_a, s_, s_, field="sharp", seed=100 + i)
+        probs.append((oms, hh, kap, sig))
+    H = T(np.concatenate([pr[1] for pr in probs]))
+    K = T(np.concatenate([pr[2] for pr in probs]))
+    S = T(np.concatenate([pr[3] for pr in probs]))
+    E = H.numel()
+    i2o = torch.empty((E, m, m), dtype=torch.float64, device=DEV)
+    i2m = torch.empty((E, nn, m), dtype=torch.float64, device=DEV)
+    print(f"[batched full] local solve of {E} elements", flush=True)
+    ctx.el_local_solve(d, H, K, S, in2out=i2o, in2mean=i2m)
+    offs = np.cumsum([0] + [s_ * s_ for s_ in sides])
+    gs = inputs.left_inflow(n_a)
+    meshes, bs, ts = [], [], []
+    for (oms, hh, _, _) in probs:
+        ms = el.mesh(oms.n_x, oms.n_y, oms.h)
+        b = torch.empty(el.trace_size(d, ms), dtype=torch.float64, device=DEV)
+        ctx.el_trace_rhs(d, ms, gs, b)
+        meshes.append(ms); bs.append(b); ts.append(torch.empty_like(b))
+    ops = [i2o[offs[i]:offs[i + 1]] for i in range(len(sides))]
+    print("[batched full] one GMRES over 8 meshes", flush=True)
+    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=1e-11, restart=50, max_iter=20000)
+    assert st == 0 and all(r["converged"] and r["relres"] <= 1e-11 for r in rep), rep
+    rng = np.random.default_rng(5)
+    sel = np.sort(rng.choice(E, 6, replace=False))
+    ro, _, rm = local_solve_batch(o, H.cpu().numpy()[sel], K.cpu().numpy()[sel], S.cpu().numpy()[sel])
+    assert per_element_rel(i2o[sel].cpu().numpy(), ro) <= 1e-10
+    assert per_element_rel(i2m[sel].cpu().numpy(), rm) <= 1e-10
+    for i, ((oms, hh, kap, _), ms) in enumerate(zip(probs, meshes)):
+        mean = torch.empty((hh.size, nn), dtype=torch.float64, device=DEV)
+        ctx.el_recover_mean(d, ms, i2m[offs[i]:offs[i + 1]], ts[i], mean)
+        inc, outg = orecover.boundary_fluxes(o, oms, ts[i].cpu().numpy(), oms.inflow_mask(o))
+        mn = mean.cpu().numpy()
+        ab = float(np.sum((0.5 * hh)[:, None] ** 2 * o.w_ang.sum() * o.W[None, :] * kap * mn))
+        assert abs(inc - outg - ab) <= 1e-9 * inc, (sides[i], inc, outg, ab)
