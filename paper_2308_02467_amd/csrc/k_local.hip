@@ -93,7 +93,8 @@ struct LuArgs {
   T* inv;        // [slots][npan][2][NB][NB]
   int* flags;    // [0] first singular element, [1] first bad-input element
   // iterative refinement (T = float): FP64 solution panel per slot, report
-  double* xbuf;       // [slots][npad][NB] or null
+  double* xbuf;       // [slots][npad][NB]: paired panel during the LU, FP64 solution during refinement
+  int refine;         // FP32 factorization with FP64 refinement
   double* rel_resid;  // [E] or null
   int ir_steps;
   double ir_tol;
@@ -119,7 +120,7 @@ __device__ inline T amat(const DiscDev& dv, const double* tau_e, const double* t
 // pan[I..I+16) = Tinv * pan[I..I+16), Tinv a 16x16 block (row-major).
 // Executed by one wave.
 template <typename T>
-__device__ inline void tri_apply(T* pan, const T* tinv, int I, int lane) {
+__device__ inline void tri_apply(T* pan, const T* tinv, int I, int lane, int ld = LDP) {
   typedef typename Acc<T>::type A4;
   A4 c = {0, 0, 0, 0};
   const int li = lane & 15, lk = lane >> 4;
@@ -127,20 +128,22 @@ __device__ inline void tri_apply(T* pan, const T* tinv, int I, int lane) {
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     a[kk] = tinv[li * NB + 4 * lk + kk];
-    b[kk] = pan[(I + 4 * lk + kk) * LDP + li];
+    b[kk] = pan[(I + 4 * lk + kk) * ld + li];
   }
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) c = mfma16(a[kk], b[kk], c);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) pan[(I + Acc<T>::row(lk, r)) * LDP + li] = c[r];
+  for (int r = 0; r < 4; ++r) pan[(I + Acc<T>::row(lk, r)) * ld + li] = c[r];
 }
 
 // pan[I] = inv_I pan[I] for the 16-row blocks I in [tb, te), spread over the
 // waves (the blocks are independent).  which = 0: unit-lower inverse,
 // 1: upper inverse.
 template <typename T>
-__device__ inline void transform_blocks(T* pan, const T* inv, int which, int tb, int te, int wave, int lane) {
-  for (int t = tb + wave; t < te; t += kWaves) tri_apply<T>(pan, inv + (size_t)t * 2 * NB * NB + which * NB * NB, 16 * t, lane);
+__device__ inline void transform_blocks(T* pan, const T* inv, int which, int tb, int te, int wave, int lane,
+                                        int ld = LDP) {
+  for (int t = tb + wave; t < te; t += kWaves)
+    tri_apply<T>(pan, inv + (size_t)t * 2 * NB * NB + which * NB * NB, 16 * t, lane, ld);
 }
 
 // Address-space-qualified pointers for the out-of-line sweep: without them
@@ -148,6 +151,8 @@ __device__ inline void transform_blocks(T* pan, const T* inv, int which, int tb,
 // instruction, whose completion the LDS wait counter also tracks.
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+using gmut = __attribute__((address_space(1))) T*;
 template <typename T>
 using lptr = __attribute__((address_space(3))) T*;
 
@@ -256,9 +261,9 @@ __device__ inline void apply_active(lptr<T> pan, const SweepGeom& g, const FBuf<
 // F.f[u] = factor rows of tile(u) for the first na slots (16-byte loads: lane
 // (i, lk) holds columns 4 lk .. 4 lk + 3 of row i, the k order used by every
 // MFMA in this file)
-template <typename T, int MAXT>
-__device__ inline void load_f(FBuf<T, MAXT>& F, gptr<T> fp, lptr<const int> perm, const SweepGeom& g, int na,
-                              int lane) {
+template <typename T, int MAXT, int LO, int HI>
+__device__ inline void load_f_part(FBuf<T, MAXT>& F, gptr<T> fp, lptr<const int> perm, const SweepGeom& g, int na,
+                                   int lane) {
   const int li = lane & 15, lk = lane >> 4;
   // Every slot is loaded (slots past na repeat slot 0's rows, which are then
   // in cache) so that each step issues the same number of loads and the
@@ -266,13 +271,13 @@ __device__ inline void load_f(FBuf<T, MAXT>& F, gptr<T> fp, lptr<const int> perm
   // first, then the loads from the uniform base with 32-bit offsets.
   uint32_t off[MAXT];
 #pragma unroll
-  for (int u = 0; u < MAXT; ++u) {
+  for (int u = LO; u < HI; ++u) {
     const int t = min(max(g.tile(u < na ? u : 0), 0), g.npan - 1);
     off[u] = (uint32_t)((perm[16 * t + li] * NB + 4 * lk) * (int)sizeof(T));
   }
   gptr<char> base = reinterpret_cast<gptr<char>>(fp);
 #pragma unroll
-  for (int u = 0; u < MAXT; ++u) {
+  for (int u = LO; u < HI; ++u) {
     if constexpr (sizeof(T) == 8) {
       typedef double dv2 __attribute__((ext_vector_type(2)));
       const dv2 v0 = *reinterpret_cast<gptr<dv2>>(base + off[u]);
@@ -284,6 +289,12 @@ __device__ inline void load_f(FBuf<T, MAXT>& F, gptr<T> fp, lptr<const int> perm
       F.f[u][0] = v[0]; F.f[u][1] = v[1]; F.f[u][2] = v[2]; F.f[u][3] = v[3];
     }
   }
+}
+
+template <typename T, int MAXT>
+__device__ inline void load_f(FBuf<T, MAXT>& F, gptr<T> fp, lptr<const int> perm, const SweepGeom& g, int na,
+                              int lane) {
+  load_f_part<T, MAXT, 0, MAXT>(F, fp, perm, g, na, lane);
 }
 
 // Block sweep over the factor panels, one barrier per step.
@@ -338,6 +349,152 @@ __device__ __attribute__((noinline)) void sweep(T* pan_g, const T* fac_g, const 
   }
 }
 
+// The sweep of sweep() applied to two panels with one pass over the factor
+// panels: the left panel in LDS as in sweep(), the right panel in MFMA
+// accumulators, loaded from and stored back to the global scratch rs
+// [npad][16] (logical row order).  Each factor tile read from HBM feeds both
+// panels, halving the factor traffic (two consecutive panels of the
+// left-looking factorization, or two right-hand-side panels).  The right
+// panel's block row of each step (its B operand) is published through the
+// LDS buffer bbuf [2][16][16] by the wave that owns it.  All threads call
+// it; it ends on a barrier.
+template <typename T, int MAXT, int LO, int N>
+__device__ inline void apply2_n(lptr<T> pan, const SweepGeom& g, const FBuf<T, MAXT>& F, const T (&b)[4],
+                                const T (&b2)[4], typename Acc<T>::type (&acc)[MAXT], int lane) {
+  typedef typename Acc<T>::type A4;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int u0 = LO; u0 < LO + N; u0 += 2) {
+    const int nu = (u0 + 1 < LO + N) ? 2 : 1;
+    A4 c[2];
+    int base[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      if (v < nu) {
+        base[v] = 16 * g.tile(u0 + v) * LDP + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[v][r] = pan[base[v] + Acc<T>::row(lk, r) * LDP];
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+        if (v < nu) {
+          c[v] = mfma16(F.f[u0 + v][kk], b[kk], c[v]);
+          acc[u0 + v] = mfma16(F.f[u0 + v][kk], b2[kk], acc[u0 + v]);
+        }
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      if (v < nu) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pan[base[v] + Acc<T>::row(lk, r) * LDP] = c[v][r];
+      }
+    }
+  }
+}
+
+// slots [LO, LO + cnt) with 0 <= cnt <= N, dispatched to straight-line code
+template <typename T, int MAXT, int LO, int N>
+__device__ inline void apply2_part(lptr<T> pan, const SweepGeom& g, const FBuf<T, MAXT>& F, const T (&b)[4],
+                                   const T (&b2)[4], typename Acc<T>::type (&acc)[MAXT], int cnt, int lane) {
+  if constexpr (N > 0) {
+    if (cnt == N) apply2_n<T, MAXT, LO, N>(pan, g, F, b, b2, acc, lane);
+    else apply2_part<T, MAXT, LO, N - 1>(pan, g, F, b, b2, acc, cnt, lane);
+  }
+}
+
+template <typename T, int MAXT>
+__device__ __attribute__((noinline)) void sweep2(T* pan_g, T* rs_g, T* bbuf_g, const T* fac_g, const int* perm_g,
+                                                 int npad, int I0, int Iend, bool down, int wave, int lane) {
+  typedef typename Acc<T>::type A4;
+  // The right panel's accumulators take the registers of the second factor
+  // buffer that sweep() uses, so the factor tiles of a step are split into
+  // two halves, slots [0, H) and [H, MAXT): each half is reloaded for the
+  // next step as soon as its MFMAs of this step are issued.
+  constexpr int H = (MAXT + 1) / 2;
+  wave = __builtin_amdgcn_readfirstlane(wave);
+  I0 = __builtin_amdgcn_readfirstlane(I0);
+  Iend = __builtin_amdgcn_readfirstlane(Iend);
+  npad = __builtin_amdgcn_readfirstlane(npad);
+  down = __builtin_amdgcn_readfirstlane((int)down) != 0;
+  gptr<T> fac = (gptr<T>)uniform_ptr(reinterpret_cast<uintptr_t>(fac_g));
+  gmut<T> rs = (gmut<T>)uniform_ptr(reinterpret_cast<uintptr_t>(rs_g));
+  lptr<T> pan = (lptr<T>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<T>)pan_g);
+  lptr<T> bbuf = (lptr<T>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<T>)bbuf_g);
+  lptr<const int> perm =
+      (lptr<const int>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<const int>)perm_g);
+  const int npan = npad / NB;
+  const int nsteps = down ? max(0, min(Iend, npad - NB) - I0 + NB - 1) / NB : npan - 1;
+  const int li = lane & 15, lk = lane >> 4;
+  SweepGeom g;
+  g.npan = npan;
+  g.wave = wave;
+  g.down = down;
+  g.nslots = wave < npan ? (npan - 1 - wave) / kWaves + 1 : 0;
+  A4 acc[MAXT];
+#pragma unroll
+  for (int u = 0; u < MAXT; ++u) {
+    if (u < g.nslots) {
+      const int t = g.tile(u);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[u][r] = rs[(16 * t + Acc<T>::row(lk, r)) * NB + li];
+    } else {
+      acc[u] = A4{0, 0, 0, 0};
+    }
+  }
+  auto I_of = [&](int s) { return down ? I0 + s * NB : npad - NB - s * NB; };
+  // the wave owning the right panel's block row of step s publishes it to
+  // bbuf[s & 1]
+  auto publish = [&](int s) {
+    const int t = I_of(s) / NB;
+    const int d = down ? npan - 1 - t - wave : t - wave;
+    if (d >= 0 && d % kWaves == 0) {
+      const int un = d / kWaves;
+      lptr<T> o = bbuf + (s & 1) * NB * NB;
+#pragma unroll
+      for (int u = 0; u < MAXT; ++u)
+        if (u == un) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[Acc<T>::row(lk, r) * NB + li] = acc[u][r];
+        }
+    }
+  };
+  if (nsteps > 0) {
+    auto F_of = [&](int s) { return fac + (size_t)(I_of(min(s, nsteps - 1)) / NB) * npad * NB; };
+    auto na_of = [&](int s) { return g.active(I_of(min(s, nsteps - 1))); };
+    FBuf<T, MAXT> F;
+    load_f_part<T, MAXT, 0, H>(F, F_of(0), perm, g, na_of(0), lane);
+    load_f_part<T, MAXT, H, MAXT>(F, F_of(0), perm, g, na_of(0), lane);
+    publish(0);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+      const int I = I_of(s);
+      const int na = g.active(I);
+      T b[4], b2[4];
+      load_b<T>(b, pan + I * LDP, LDP, lane);
+      load_b<T>(b2, bbuf + (s & 1) * NB * NB, NB, lane);
+      apply2_part<T, MAXT, 0, H>(pan, g, F, b, b2, acc, min(na, H), lane);
+      load_f_part<T, MAXT, 0, H>(F, F_of(s + 1), perm, g, na_of(s + 1), lane);
+      apply2_part<T, MAXT, H, MAXT - H>(pan, g, F, b, b2, acc, max(na - H, 0), lane);
+      load_f_part<T, MAXT, H, MAXT>(F, F_of(s + 1), perm, g, na_of(s + 1), lane);
+      // the next step's block row of the right panel is complete now
+      if (s + 1 < nsteps) publish(s + 1);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < MAXT; ++u) {
+    if (u < g.nslots) {
+      const int t = g.tile(u);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rs[(16 * t + Acc<T>::row(lk, r)) * NB + li] = acc[u][r];
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
 // pan = U^{-1} L^{-1} pan for a right-hand-side panel already in logical
 // (pivoted) row order; the forward sweep starts at block Istart (rows above
 // it are zero).  All threads of the workgroup call this; it ends on a barrier.
@@ -350,6 +507,25 @@ __device__ inline void panel_solve(T* pan, const T* fac, const T* inv, const int
   __syncthreads();
   sweep<T, MAXT>(pan, fac, perm, npad, 0, 0, false, wave, lane);
   transform_blocks<T>(pan, inv, 1, 0, npan, wave, lane);
+  __syncthreads();
+}
+
+// panel_solve() for two right-hand-side panels at once: pan (LDS) and rs
+// (global scratch [npad][NB], logical row order), both zero above block
+// Istart.  All threads call it; it ends on a barrier.
+template <typename T, int MAXT>
+__device__ inline void panel_solve2(T* pan, T* rs, T* bbuf, const T* fac, const T* inv, const int* perm, int npad,
+                                    int Istart, int wave, int lane) {
+  const int npan = npad / NB;
+  sweep2<T, MAXT>(pan, rs, bbuf, fac, perm, npad, Istart, npad, true, wave, lane);
+  transform_blocks<T>(pan, inv, 0, Istart / NB, npan, wave, lane);
+  transform_blocks<T>(rs, inv, 0, Istart / NB, npan, wave, lane, NB);
+  __threadfence_block();
+  __syncthreads();
+  sweep2<T, MAXT>(pan, rs, bbuf, fac, perm, npad, 0, 0, false, wave, lane);
+  transform_blocks<T>(pan, inv, 1, 0, npan, wave, lane);
+  transform_blocks<T>(rs, inv, 1, 0, npan, wave, lane, NB);
+  __threadfence_block();
   __syncthreads();
 }
 
@@ -440,11 +616,16 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   int* redi = reinterpret_cast<int*>(redv + kWaves);                     // [kWaves]
   int* sflag = redi + kWaves;                                            // [2]
   T* sinv = reinterpret_cast<T*>(smem + lds_base_bytes<T>(npad, nn));    // [2][NB][NB]
+  T* bbuf = sinv + 2 * NB * NB;                                          // [2][NB][NB]
+  int* perm_old = reinterpret_cast<int*>(bbuf + 2 * NB * NB);             // [npad]
   // iterative refinement scratch (only allocated when a.xbuf != null)
-  unsigned long long* colmax = reinterpret_cast<unsigned long long*>(sinv + 2 * NB * NB);   // [NB]
+  unsigned long long* colmax = reinterpret_cast<unsigned long long*>(
+      reinterpret_cast<unsigned char*>(perm_old) + ((sizeof(int) * npad + 15) / 16) * 16);   // [NB]
   double* xs = reinterpret_cast<double*>(colmax + NB);                    // [npad][ir_cols]
-  const bool ir = sizeof(T) == 4 && a.xbuf != nullptr;   // refinement only for the FP32 factorization
+  const bool ir = sizeof(T) == 4 && a.refine;   // refinement only for the FP32 factorization
   double* xg = ir ? a.xbuf + (size_t)blockIdx.x * npad * NB : nullptr;
+  T* rs = reinterpret_cast<T*>(a.xbuf + (size_t)blockIdx.x * npad * NB);   // second panel of a pair (the
+                                                                           // refinement reuses it later)
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -472,17 +653,48 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
       continue;
     }
 
-    // ---- LU panels
+    // ---- LU panels, in pairs: the second panel of a pair rides along in
+    // registers through the sweep of the first (sweep2), waits in the
+    // scratch rs while the first is factored, and then only needs the update
+    // by the first
+    bool pending = false;   // panel J is the second of a pair, waiting in rs
     for (int J = 0; J < npad; J += NB) {
-      // generate the panel of A, rows in current logical order
-      for (int idx = tid; idx < npad * NB; idx += kThreads) {
-        int r = idx >> 4, c = idx & 15;
-        pan[r * LDP + c] = amat<T>(dv, tau_e, tau_s, perm[r], J + c);
+      if (!pending) {
+        // generate the panel of A, rows in current logical order
+        for (int idx = tid; idx < npad * NB; idx += kThreads) {
+          int r = idx >> 4, c = idx & 15;
+          pan[r * LDP + c] = amat<T>(dv, tau_e, tau_s, perm[r], J + c);
+        }
+        const bool pair = J + NB < npad;
+        if (pair) {
+          for (int idx = tid; idx < npad * NB; idx += kThreads) {
+            int r = idx >> 4, c = idx & 15;
+            rs[r * NB + c] = amat<T>(dv, tau_e, tau_s, perm[r], J + NB + c);
+          }
+          for (int r = tid; r < npad; r += kThreads) perm_old[r] = perm[r];
+          __threadfence_block();
+        }
+        __syncthreads();
+        // left-looking update by the previous panels (their factors are stored
+        // pre-multiplied: -L[:, I] inv(L_II)), then the U rows of this panel
+        if (pair) sweep2<T, MAXT>(pan, rs, bbuf, fac, perm, npad, 0, J, true, wave, lane);
+        else sweep<T, MAXT>(pan, fac, perm, npad, 0, J, true, wave, lane);
+        pending = pair;
+      } else {
+        // second panel of the pair: rows of rs are in the logical order of
+        // before the first panel's interchanges; physical row perm[r] sat at
+        // logical row pinv_old[perm[r]] then
+        for (int r = tid; r < npad; r += kThreads) pinv[perm_old[r]] = r;
+        __syncthreads();
+        for (int idx = tid; idx < npad * NB; idx += kThreads) {
+          int r = idx >> 4, c = idx & 15;
+          pan[r * LDP + c] = rs[pinv[perm[r]] * NB + c];
+        }
+        __syncthreads();
+        // the remaining update: by the first panel of the pair
+        sweep<T, MAXT>(pan, fac, perm, npad, J - NB, J, true, wave, lane);
+        pending = false;
       }
-      __syncthreads();
-      // left-looking update by the previous panels (their factors are stored
-      // pre-multiplied: -L[:, I] inv(L_II)), then the U rows of this panel
-      sweep<T, MAXT>(pan, fac, perm, npad, 0, J, true, wave, lane);
       transform_blocks<T>(pan, inv, 0, 0, J / NB, wave, lane);
       // factor rows [J, npad) of the panel with partial pivoting
       double best = -1.0;
@@ -599,25 +811,35 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     for (int r = tid; r < npad; r += kThreads) pinv[perm[r]] = r;
     __syncthreads();
 
-    // ---- right-hand side panels: X = U^{-1} L^{-1} P (-B_hat)
+    // ---- right-hand side panels: X = U^{-1} L^{-1} P (-B_hat), two at a
+    // time (the second in rs) when no refinement follows
     double elem_res = 0.0;
-    for (int P0 = 0; P0 < mpad; P0 += NB) {
+    for (int P0 = 0; P0 < mpad;) {
+      const bool two = !ir && P0 + NB < mpad;
       for (int idx = tid; idx < npad * NB; idx += kThreads) {
         int r = idx >> 4, c = idx & 15;
         int col = P0 + c;
         T v = T(0);
         if (col < m && perm[r] == dv.in_row[col]) v = (T)dv.in_val[col];
         pan[r * LDP + c] = v;
+        if (two) {
+          col += NB;
+          v = T(0);
+          if (col < m && perm[r] == dv.in_row[col]) v = (T)dv.in_val[col];
+          rs[r * NB + c] = v;
+        }
       }
-      // first nonzero logical row of the panel
+      // first nonzero logical row of the panel(s)
       if (tid == 0) {
         int mn = npad;
-        for (int c = 0; c < NB; ++c)
+        for (int c = 0; c < (two ? 2 * NB : NB); ++c)
           if (P0 + c < m) mn = min(mn, pinv[dv.in_row[P0 + c]]);
         sflag[1] = (mn / NB) * NB;
       }
+      __threadfence_block();
       __syncthreads();
-      panel_solve<T, MAXT>(pan, fac, inv, perm, npad, sflag[1], wave, lane);
+      if (two) panel_solve2<T, MAXT>(pan, rs, bbuf, fac, inv, perm, npad, sflag[1], wave, lane);
+      else panel_solve<T, MAXT>(pan, fac, inv, perm, npad, sflag[1], wave, lane);
       if (ir) {
         // FP64 solution panel in HBM, refined with FP64 residuals and FP32 corrections
         for (int idx = tid; idx < npad * NB; idx += kThreads) {
@@ -649,53 +871,63 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         }
       }
       // outputs (pan rows are volume DOFs in natural order)
-      const bool pairs_sol = a.pairs && a.pairs_form == EL_FORM_IN2SOL;
-      const bool pairs_mean = a.pairs && a.pairs_form == EL_FORM_IN2MEAN;
-      const int64_t n_out = (int64_t)m * m + (int64_t)(pairs_mean ? nn : n) * m;
-      if (a.in2sol || a.b_i2s || a.f_i2s || pairs_sol) {
-        for (int idx = tid; idx < n * NB; idx += kThreads) {
-          int r = idx >> 4, c = idx & 15;
-          if (P0 + c < m) {
-            const double v = ir ? xg[r * NB + c] : (double)pan[r * LDP + c];
-            const int64_t o = ((int64_t)e * n + r) * m + P0 + c;
-            if (a.in2sol) a.in2sol[o] = v;
-            if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
-            if (a.f_i2s) a.f_i2s[o] = (float)v;
-            if (pairs_sol) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+      for (int half = 0; half < (two ? 2 : 1); ++half) {
+        if (half == 1) {
+          // the second panel's solution: rs -> pan
+          __syncthreads();
+          for (int idx = tid; idx < npad * NB; idx += kThreads) pan[(idx >> 4) * LDP + (idx & 15)] = rs[idx];
+          __syncthreads();
+          P0 += NB;
+        }
+        const bool pairs_sol = a.pairs && a.pairs_form == EL_FORM_IN2SOL;
+        const bool pairs_mean = a.pairs && a.pairs_form == EL_FORM_IN2MEAN;
+        const int64_t n_out = (int64_t)m * m + (int64_t)(pairs_mean ? nn : n) * m;
+        if (a.in2sol || a.b_i2s || a.f_i2s || pairs_sol) {
+          for (int idx = tid; idx < n * NB; idx += kThreads) {
+            int r = idx >> 4, c = idx & 15;
+            if (P0 + c < m) {
+              const double v = ir ? xg[r * NB + c] : (double)pan[r * LDP + c];
+              const int64_t o = ((int64_t)e * n + r) * m + P0 + c;
+              if (a.in2sol) a.in2sol[o] = v;
+              if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
+              if (a.f_i2s) a.f_i2s[o] = (float)v;
+              if (pairs_sol) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+            }
           }
         }
-      }
-      if (a.in2out || a.b_i2o || a.f_i2o || a.pairs) {
-        for (int idx = tid; idx < m * NB; idx += kThreads) {
-          int r = idx >> 4, c = idx & 15;
-          if (P0 + c < m) {
-            const double v = ir ? xg[dv.out_row[r] * NB + c] : (double)pan[dv.out_row[r] * LDP + c];
-            const int64_t o = ((int64_t)e * m + r) * m + P0 + c;
-            if (a.in2out) a.in2out[o] = v;
-            if (a.b_i2o) a.b_i2o[o] = gemm::f2bf((float)v);
-            if (a.f_i2o) a.f_i2o[o] = (float)v;
-            if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+        if (a.in2out || a.b_i2o || a.f_i2o || a.pairs) {
+          for (int idx = tid; idx < m * NB; idx += kThreads) {
+            int r = idx >> 4, c = idx & 15;
+            if (P0 + c < m) {
+              const double v = ir ? xg[dv.out_row[r] * NB + c] : (double)pan[dv.out_row[r] * LDP + c];
+              const int64_t o = ((int64_t)e * m + r) * m + P0 + c;
+              if (a.in2out) a.in2out[o] = v;
+              if (a.b_i2o) a.b_i2o[o] = gemm::f2bf((float)v);
+              if (a.f_i2o) a.f_i2o[o] = (float)v;
+              if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+            }
           }
         }
-      }
-      if (a.in2mean || a.b_i2m || a.f_i2m || pairs_mean) {
-        const double s = 1.0 / dv.n_a;
-        for (int idx = tid; idx < nn * NB; idx += kThreads) {
-          int r = idx >> 4, c = idx & 15;
-          if (P0 + c < m) {
-            double acc = 0.0;
-            for (int k = 0; k < dv.n_a; ++k)
-              acc += ir ? xg[(k * nn + r) * NB + c] : (double)pan[(k * nn + r) * LDP + c];
-            const double v = acc * s;
-            const int64_t o = ((int64_t)e * nn + r) * m + P0 + c;
-            if (a.in2mean) a.in2mean[o] = v;
-            if (a.b_i2m) a.b_i2m[o] = gemm::f2bf((float)v);
-            if (a.f_i2m) a.f_i2m[o] = (float)v;
-            if (pairs_mean) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+        if (a.in2mean || a.b_i2m || a.f_i2m || pairs_mean) {
+          const double s = 1.0 / dv.n_a;
+          for (int idx = tid; idx < nn * NB; idx += kThreads) {
+            int r = idx >> 4, c = idx & 15;
+            if (P0 + c < m) {
+              double acc = 0.0;
+              for (int k = 0; k < dv.n_a; ++k)
+                acc += ir ? xg[(k * nn + r) * NB + c] : (double)pan[(k * nn + r) * LDP + c];
+              const double v = acc * s;
+              const int64_t o = ((int64_t)e * nn + r) * m + P0 + c;
+              if (a.in2mean) a.in2mean[o] = v;
+              if (a.b_i2m) a.b_i2m[o] = gemm::f2bf((float)v);
+              if (a.f_i2m) a.f_i2m[o] = (float)v;
+              if (pairs_mean) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+            }
           }
         }
       }
       __syncthreads();
+      P0 += NB;
     }
     if (ir && tid == 0 && a.rel_resid) a.rel_resid[e] = elem_res;
   }
@@ -713,7 +945,7 @@ __global__ void k_fill_int(int* p, int n, int v) {
 
 template <typename T>
 size_t lu_smem_bytes(int npad, int nn, int ir_cols) {
-  size_t b = lds_base_bytes<T>(npad, nn) + sizeof(T) * 2 * NB * NB;
+  size_t b = lds_base_bytes<T>(npad, nn) + sizeof(T) * 4 * NB * NB + ((sizeof(int) * (size_t)npad + 15) / 16) * 16;
   if (ir_cols) b += NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * ir_cols;
   return b + 16;
 }
@@ -765,7 +997,7 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   const int64_t slots = std::min<int64_t>(E, (int64_t)ctx->num_cus * 2);
   size_t fac_bytes = sizeof(T) * (size_t)slots * npan * npad * NB;
   size_t inv_bytes = sizeof(T) * (size_t)slots * npan * 2 * NB * NB;
-  size_t x_bytes = ir ? sizeof(double) * (size_t)slots * npad * NB : 0;
+  size_t x_bytes = sizeof(double) * (size_t)slots * npad * NB;
   el_status st = ensure_ws(ctx, ctx->ws_local, fac_bytes + inv_bytes + x_bytes + 256);
   if (st) return st;
   st = ensure_ws(ctx, ctx->ws_small, 8192);
@@ -785,7 +1017,8 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   char* base = reinterpret_cast<char*>(ctx->ws_local.ptr);
   args.fac = reinterpret_cast<T*>(base);
   args.inv = reinterpret_cast<T*>(base + fac_bytes);
-  args.xbuf = ir ? reinterpret_cast<double*>(base + ((fac_bytes + inv_bytes + 255) / 256) * 256) : nullptr;
+  args.xbuf = reinterpret_cast<double*>(base + ((fac_bytes + inv_bytes + 255) / 256) * 256);
+  args.refine = ir ? 1 : 0;
   args.rel_resid = rel_resid;
   args.ir_steps = 3;
   args.ir_tol = 1e-13;
