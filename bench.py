@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--width", type=int, default=1024)
     ap.add_argument("--depth", type=int, default=4)
     ap.add_argument("--no-conserve", action="store_true", help="skip the energy-balance correction")
+    ap.add_argument("--op-dtype", choices=("float16", "float32"), default="float16",
+                    help="storage of the learned operators (in2out and in2sol)")
+    ap.add_argument("--storage-study", action="store_true",
+                    help="learned-solve error for several operator storages")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--no-batched", action="store_true",
@@ -77,7 +81,9 @@ def log(msg):
 
 
 MATVEC_SOURCES = ("paper_2308_02467_amd/csrc/trace_dev.h", "paper_2308_02467_amd/csrc/k_trace.hip")
-TRAFFIC_SUMMARY = "profiles/k_matvec_float_128x128_p6_na16_hbm_traffic.md"
+TRAFFIC_SUMMARY = {"float32": "profiles/k_matvec_float_128x128_p6_na16_hbm_traffic.md",
+                   "float16": "profiles/k_matvec_f16_128x128_p6_na16_hbm_traffic.md"}
+MATVEC_KERNEL = {"float32": "k_matvec<float>", "float16": "k_matvec<_Float16>"}
 
 
 def matvec_source_hash():
@@ -88,14 +94,16 @@ def matvec_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per launch of k_matvec<float> from the committed rocprofv3
-    counter summary, or None when the kernel's source changed since."""
+def recorded_traffic(op_dtype):
+    """HBM bytes per launch of the skeleton product with operators stored as
+    op_dtype, from the committed rocprofv3 counter summary, or None when the
+    kernel's source changed since."""
     try:
-        text = open(os.path.join(ROOT, TRAFFIC_SUMMARY)).read()
-    except OSError:
+        text = open(os.path.join(ROOT, TRAFFIC_SUMMARY[op_dtype])).read()
+    except (OSError, KeyError):
         return None
-    m = re.search(r"traffic_bytes_per_launch k_matvec<float> = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
+    kern = re.escape(MATVEC_KERNEL[op_dtype])
+    m = re.search(r"traffic_bytes_per_launch " + kern + r" = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
     if not m or m.group(2) != matvec_source_hash():
         return None
     return float(m.group(1))
@@ -229,7 +237,7 @@ def main():
     if learned is not None:
         head_ms, head_value, unit = learned["ms_per_step"], learned["value"], "element solves/s (whole learned step)"
         roof = learned.pop("roofline_matvec")
-        dtype = "bf16+f32+f64"
+        dtype = "bf16+" + {"float16": "f16", "float32": "f32"}[args.op_dtype] + "+f64"
         workload = (f"learned HDG (element network + GMRES), {nx}x{nx} elements, p=6, N_a=16, Gaussian cloud, "
                     f"left inflow; mean-intensity rel L2 vs plain FP64 {learned['mean_intensity_rel_l2_vs_plain']:.2e}")
     else:
@@ -449,8 +457,10 @@ def cloud_main(args):
     d2p, r2p = ctx.el_mean_l2(d, hh, mean_pl, mean_ref)
     del rmn, t_pl, mean_pl
 
-    lo = torch.empty((E, m, m), dtype=torch.float32, device=dev)
+    lo32 = torch.empty((E, m, m), dtype=torch.float32, device=dev)
     lm = torch.empty((E, nn, m), dtype=torch.float32, device=dev)
+    op_t = getattr(torch, args.op_dtype)
+    lo = lo32 if op_t == torch.float32 else torch.empty((E, m, m), dtype=op_t, device=dev)
     mask = torch.empty(E, dtype=torch.uint8, device=dev)
     t = torch.empty_like(b)
     mean = torch.empty_like(mean_ref)
@@ -459,8 +469,8 @@ def cloud_main(args):
     def step(record):
         e = [ev() for _ in range(4)]
         e[0].record(stream)
-        nfb = net.infer(d, hh, kap, sig, lo, in2mean=lm, in_range=mask, fallback=True, precision=el.EL_FP32_IR)
-        ctx.el_conserve(d, hh, kap, lo, in2mean=lm, mask=mask)
+        nfb = net.infer(d, hh, kap, sig, lo32, in2mean=lm, in_range=mask, fallback=True, precision=el.EL_FP32_IR)
+        ctx.el_conserve(d, hh, kap, lo32, in2mean=lm, mask=mask, out=None if lo is lo32 else lo)
         e[1].record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
         st, rep = ctx.el_trace_solve(d, [ms], [lo], [b], [t], tol=args.tol, restart=args.restart, max_iter=40000)
@@ -485,8 +495,8 @@ def cloud_main(args):
         "metric": "element solves/s + full solve time at 1e-3 rel L2, learned vs plain (p=6)",
         "value": E / (ms_step * 1e-3), "unit": "element solves/s (whole learned step)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64",
-        "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+" + {"float16": "f16", "float32": "f32"}[args.op_dtype] + "+f64", "data": "synthetic",
         "config": {"workload": f"realistic cloud: {nx}x{nx} elements, p=6, N_a=32, HG g=0.85, log-normal sigma "
                                "(k^-5/3, mean 10, log-std 1, zero below threshold), kappa=0.05 sigma+0.01, "
                                "learned in2mean form + FP32-refinement fallback, FP64 GMRES",
@@ -497,7 +507,7 @@ def cloud_main(args):
         "phases_ms": {"infer_fallback_and_correction": float(np.median(ph[:, 0])),
                       "rhs_and_gmres": float(np.median(ph[:, 1])), "recover_mean": float(np.median(ph[:, 2]))},
         "fallback_elements": rec[-1][2], "gmres": rec[-1][1],
-        "mean_intensity_rel_l2_vs_reference": (d2 / r2) ** 0.5,
+        "mean_intensity_rel_l2_vs_reference": (d2 / r2) ** 0.5, "learned_in2out_storage": args.op_dtype,
         "reference": {"local_solve_ms": ref_local_ms, "local_solve_el_per_s": E / (ref_local_ms * 1e-3),
                       "gmres_ms": ref_gmres_ms, "gmres": rep_ref[0], "operator_storage": "float32"},
         "plain_step_ms": ref_local_ms + plain_gmres_ms,
@@ -534,8 +544,13 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     t_train = time.perf_counter() - t0
     del x, y
     torch.cuda.empty_cache()
-    lo = torch.empty((E, m, m), dtype=torch.float32, device=dev)
+    # the network writes FP32 operators; the energy-balance correction reads
+    # them and writes the in2out that GMRES sweeps, rounded once to op_dtype
+    op_t = getattr(torch, args.op_dtype)
+    esz = torch.empty(0, dtype=op_t).element_size()
+    lo32 = torch.empty((E, m, m), dtype=torch.float32, device=dev)
     ls = torch.empty((E, n, m), dtype=torch.float32, device=dev)
+    lo = lo32 if op_t == torch.float32 else torch.empty((E, m, m), dtype=op_t, device=dev)
     mask = torch.empty(E, dtype=torch.uint8, device=dev)
     t = torch.empty_like(b)
     mean = torch.empty_like(mean_plain)
@@ -544,12 +559,13 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     def step(record, conserve=not args.no_conserve):
         e = [ev() for _ in range(4)]
         e[0].record(stream)
-        nfb = net.infer(d, hh, kap, sig, lo, ls, mask, fallback=True)
+        nfb = net.infer(d, hh, kap, sig, lo32, ls, mask, fallback=True)
         if conserve:
-            ctx.el_conserve(d, hh, kap, lo, ls, mask)
+            ctx.el_conserve(d, hh, kap, lo32, ls, mask, out=None if lo is lo32 else lo)
+        op = lo if conserve else lo32
         e[1].record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
-        st, rep = ctx.el_trace_solve(d, [ms], [lo], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
+        st, rep = ctx.el_trace_solve(d, [ms], [op], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
         e[2].record(stream)
         ctx.el_recover(d, ms, ls, t, None, mean)
         e[3].record(stream)
@@ -560,7 +576,7 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     step(False, conserve=False)
     d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_plain)
     err_raw = (d2 / r2) ** 0.5
-    op_raw = ((lo.double() - i2o_plain).flatten(1).norm(dim=1) / i2o_plain.flatten(1).norm(dim=1)).cpu().numpy()
+    op_raw = ((lo32.double() - i2o_plain).flatten(1).norm(dim=1) / i2o_plain.flatten(1).norm(dim=1)).cpu().numpy()
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -573,7 +589,7 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_plain)
     op_err = ((lo.double() - i2o_plain).flatten(1).norm(dim=1) / i2o_plain.flatten(1).norm(dim=1)).cpu().numpy()
 
-    # dominant kernel of the learned step: the FP32 in2out sweep (k_matvec<float>), HBM-bound
+    # dominant kernel of the learned step: the in2out sweep (k_matvec<op type>), HBM-bound
     xv = torch.rand_like(b)
     yv = torch.empty_like(b)
     reps = 20
@@ -585,8 +601,11 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     e1.record(stream)
     torch.cuda.synchronize()
     mv_ms = e0.elapsed_time(e1) / reps
-    mv_bytes = E * m * (m * 4 + 3 * 8)          # operator + gathered inflow + outflow read/write
+    mv_bytes = E * m * (m * esz + 3 * 8)        # operator + gathered inflow + outflow read/write
     mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+
+    study = storage_study(args, ctx, net, d, ms, hh, kap, sig, g_side, b, mean_plain, E, n, m) \
+        if args.storage_study else None
 
     n_in = 1 + 2 * nn
     flop_el = 2.0 * (n_in * args.width + (args.depth - 1) * args.width ** 2 + args.width * (m * m + n * m))
@@ -607,15 +626,51 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
         "in2out_rel_err_median": float(np.median(op_err)), "in2out_rel_err_max": float(op_err.max()),
         "without_correction": {"mean_intensity_rel_l2_vs_plain": err_raw,
                                "in2out_rel_err_median": float(np.median(op_raw))},
-        "operator_storage": "float32",
+        "operator_storage": args.op_dtype,
+        "storage_study": study,
         "roofline_matvec": {"bound": "hbm",
-                            "kernel": "k_matvec<float> (element body shared with the GMRES product k_bmatvec<float>)",
+                            "kernel": f"{MATVEC_KERNEL[args.op_dtype]} (element body shared with the GMRES product)",
                             "achieved": mv_gbs, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(),
+                            "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(args.op_dtype),
                             "bytes_per_launch": mv_bytes, "avg_launch_ms": mv_ms},
     }
     net.close()
     return out
+
+
+def storage_study(args, ctx, net, d, ms, hh, kap, sig, g_side, b, mean_plain, E, n, m):
+    """Mean-intensity error of the learned solve for three storages of the
+    learned in2out: float32; float16 rounded once after the float32
+    energy-balance correction (the timed path); float16 written by the
+    network and corrected afterwards (corrections below half a float16 unit
+    are lost)."""
+    import torch
+    dev = hh.device
+    res = {}
+    lo32 = torch.empty((E, m, m), dtype=torch.float32, device=dev)
+    ls32 = torch.empty((E, n, m), dtype=torch.float32, device=dev)
+    lo16 = torch.empty((E, m, m), dtype=torch.float16, device=dev)
+    mask = torch.empty(E, dtype=torch.uint8, device=dev)
+    t = torch.empty_like(b)
+    mean = torch.empty_like(mean_plain)
+
+    def err(op_o, op_s):
+        ctx.el_trace_solve(d, [ms], [op_o], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
+        ctx.el_recover(d, ms, op_s, t, None, mean)
+        d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_plain)
+        return (d2 / r2) ** 0.5
+
+    net.infer(d, hh, kap, sig, lo32, ls32, mask, fallback=True)
+    ctx.el_conserve(d, hh, kap, lo32, ls32, mask, out=lo16)
+    res["float16_in2out_rounded_after_float32_correction"] = err(lo16, ls32)
+    ctx.el_conserve(d, hh, kap, lo32, ls32, mask)
+    res["float32_in2out"] = err(lo32, ls32)
+    del lo32, ls32
+    ls16 = torch.empty((E, n, m), dtype=torch.float16, device=dev)
+    net.infer(d, hh, kap, sig, lo16, ls16, mask, fallback=True)
+    ctx.el_conserve(d, hh, kap, lo16, ls16, mask)
+    res["float16_network_output_corrected_in_float16"] = err(lo16, ls16)
+    return res
 
 
 def accuracy(ctx, d, ms, hh, i2o, i2s, b, mean_timed, restart):
@@ -645,6 +700,8 @@ def accuracy(ctx, d, ms, hh, i2o, i2s, b, mean_timed, restart):
     del o16
     o32 = i2o.to(torch.float32)
     out["f32_in2out_bf16_in2sol_rel_l2"] = solve_with(o32, s16)[0]
+    o16h = i2o.to(torch.float16).to(torch.float32)       # FP16 rounding of the operator
+    out["f16_in2out_f64_in2sol_rel_l2"] = solve_with(o16h, i2s)[0]
     return out
 
 

@@ -70,8 +70,9 @@ typedef int el_status;
 
 /* operator storage types for the trace sweep and recovery */
 #define EL_F64 0
-#define EL_BF16 1
+#define EL_BF16 1  /* bfloat16 bit patterns in uint16_t */
 #define EL_F32 2
+#define EL_F16 3   /* IEEE binary16 */
 
 typedef struct el_ctx el_ctx;
 
@@ -156,7 +157,8 @@ el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_sid
 
 /* y = (I - P) x on one mesh: (P x)[out dofs of e] = in2out_e x[in dofs of e],
  * P = 0 on domain-inflow rows.  in2out is [E][m][m] FP64 (op_dtype EL_F64),
- * FP32 (EL_F32) or bfloat16 bit patterns (EL_BF16); accumulation is FP64. */
+ * FP32 (EL_F32), FP16 (EL_F16) or bfloat16 bit patterns (EL_BF16);
+ * accumulation is FP64. */
 el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out,
                           int op_dtype, const double* x, double* y);
 
@@ -181,11 +183,11 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
 
 /* ---- recovery (Alg. 1 step 4, eq. hdg_local_mat_sol, eq. ang_ave) ----------
  * u [E][n] = in2sol_e t[in dofs of e] (NULL = skip) and the mean intensity
- * mean [E][nn] = (1/N_a) sum_k u (NULL = skip).  in2sol is [E][n][m] FP64,
- * FP32 or bfloat16 bits (op_dtype). */
+ * mean [E][nn] = (1/N_a) sum_k u (NULL = skip).  in2sol is [E][n][m] in
+ * op_dtype (EL_F64, EL_F32, EL_F16, EL_BF16). */
 el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
                      const double* trace, double* u, double* mean);
-/* Mean intensity directly from in2mean [E][nn][m] (FP64, FP32 or bfloat16 bits). */
+/* Mean intensity directly from in2mean [E][nn][m] in op_dtype. */
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean,
                           int op_dtype, const double* trace, double* mean);
 
@@ -201,12 +203,17 @@ el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2m
  * (outflow = inflow - absorption, obtained by testing the local equations
  * with v = 1 and summing over ordinates; w = face quadrature weight times
  * |s.n|); with in2mean the absorption is N_a sum_nd W_nd (h kappa_nd / 2)
- * in2mean[nd][i].  Each column of in2out is rescaled in place so that this
- * holds.  Not part of the paper's method: a post-processing option for the
+ * in2mean[nd][i].  Each column of in2out is rescaled so that this holds.  Not part of the paper's method: a post-processing option for the
  * learned operators.  in2vol = in2sol or in2mean (form); in2out and in2vol
- * in op_dtype (EL_F64, EL_F32, EL_BF16). */
+ * in op_dtype (EL_F64, EL_F32, EL_F16, EL_BF16).  The corrected in2out goes
+ * to out in out_dtype: out = NULL or out = in2out corrects in place (out_dtype
+ * = op_dtype); a separate out must not overlap in2out and may round FP32
+ * operators to EL_F16 or EL_BF16 once, after the correction (correcting
+ * values that are already rounded to 16 bits loses the correction whenever
+ * it is below half a unit).  Elements with mask[e] == 0 are copied to out
+ * unchanged. */
 el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa, void* in2out,
-                      const void* in2vol, int form, int op_dtype, const uint8_t* mask);
+                      const void* in2vol, int form, int op_dtype, const uint8_t* mask, void* out, int out_dtype);
 
 /* Squared element L2 norms of mean-intensity fields [E][nn] (relative error
  * measure of Sec. 3.2.1): out_host[0] = sum_e (h_e/2)^2 sum W (a - ref)^2,
@@ -296,8 +303,8 @@ el_status el_net_forward(el_ctx* ctx, const el_net* net, int64_t B, const float*
 /* Learned operators for E elements (inference): in2out [E][m][m] and
  * in2vol = in2sol [E][n][m] (network in the in2sol form) or in2mean
  * [E][nn][m] (in2mean form; the form follows from the network's n_out),
- * stored as out_dtype (EL_BF16: bfloat16 bits, round to nearest even;
- * EL_F32: float32); either may be NULL.  in_range [E]
+ * stored as out_dtype (EL_BF16: bfloat16 bits, EL_F16: binary16, both
+ * rounded to nearest even from FP32; EL_F32: float32); either may be NULL.  in_range [E]
  * (1 = every input inside the training box; may be NULL).  fallback = 1:
  * elements outside the box are solved by the plain local solver
  * (precision) and written, rounded to out_dtype, into the same outputs;

@@ -112,7 +112,8 @@ el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh
 el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
                               const void* in2mean, int op_dtype, const double* trace, double* mean);
 el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* kappa,
-                          void* in2out, const void* in2vol, int form, int op_dtype, const uint8_t* mask);
+                          const void* in2out, const void* in2vol, int form, int op_dtype, const uint8_t* mask,
+                          void* out, int out_dtype);
 el_status launch_mean_l2(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h,
                          const double* a, const double* ref, double* out_host);
 

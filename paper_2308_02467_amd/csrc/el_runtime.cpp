@@ -94,6 +94,8 @@ el_status ensure_ws(el_ctx* ctx, Workspace& ws, size_t bytes) {
   return EL_OK;
 }
 
+static bool op_dtype_ok(int t) { return t == EL_F64 || t == EL_F32 || t == EL_F16 || t == EL_BF16; }
+
 static bool mesh_ok(const el_mesh& m) {
   return m.n_x > 0 && m.n_y > 0 && std::isfinite(m.h) && m.h > 0 && std::isfinite(m.x0) && std::isfinite(m.y0);
 }
@@ -221,7 +223,7 @@ el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_sid
 el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out, int op_dtype,
                           const double* x, double* y) {
   if (!ctx) return EL_ERR_ARG;
-  if (!mesh_ok(mesh) || !in2out || !x || !y || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
+  if (!mesh_ok(mesh) || !in2out || !x || !y || !op_dtype_ok(op_dtype))
     return set_error(ctx, EL_ERR_ARG, "el_trace_matvec: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
@@ -236,7 +238,7 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
   if (!ctx) return EL_ERR_ARG;
   if (n_mesh <= 0 || !meshes_host || !in2out || !b || !trace || !opts_host || !rep_host)
     return set_error(ctx, EL_ERR_ARG, "el_trace_solve: bad argument");
-  if (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32)
+  if (!op_dtype_ok(op_dtype))
     return set_error(ctx, EL_ERR_ARG, "el_trace_solve: op_dtype");
   const el_gmres_opts& o = *opts_host;
   if (!(o.tol > 0) || o.restart < 1 || o.restart > 256 || o.max_iter < 1)
@@ -258,7 +260,7 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
 el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
                      const double* trace, double* u, double* mean) {
   if (!ctx) return EL_ERR_ARG;
-  if (!mesh_ok(mesh) || !in2sol || !trace || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
+  if (!mesh_ok(mesh) || !in2sol || !trace || !op_dtype_ok(op_dtype))
     return set_error(ctx, EL_ERR_ARG, "el_recover: bad argument");
   if (!u && !mean) return EL_OK;
   hipSetDevice(ctx->device);
@@ -271,7 +273,7 @@ el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, i
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean, int op_dtype,
                           const double* trace, double* mean) {
   if (!ctx) return EL_ERR_ARG;
-  if (!mesh_ok(mesh) || !in2mean || !trace || !mean || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32))
+  if (!mesh_ok(mesh) || !in2mean || !trace || !mean || !op_dtype_ok(op_dtype))
     return set_error(ctx, EL_ERR_ARG, "el_recover_mean: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
@@ -281,16 +283,24 @@ el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2m
 }
 
 el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa, void* in2out,
-                      const void* in2vol, int form, int op_dtype, const uint8_t* mask) {
+                      const void* in2vol, int form, int op_dtype, const uint8_t* mask, void* out, int out_dtype) {
   if (!ctx) return EL_ERR_ARG;
-  if (E <= 0 || !h || !kappa || !in2out || !in2vol || (op_dtype != EL_F64 && op_dtype != EL_BF16 && op_dtype != EL_F32) ||
+  if (!out) { out = in2out; out_dtype = op_dtype; }
+  if (E <= 0 || !h || !kappa || !in2out || !in2vol || !op_dtype_ok(op_dtype) || !op_dtype_ok(out_dtype) ||
       (form != EL_FORM_IN2SOL && form != EL_FORM_IN2MEAN))
     return set_error(ctx, EL_ERR_ARG, "el_conserve: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
-  return launch_conserve(ctx, de, E, h, kappa, in2out, in2vol, form, op_dtype, mask);
+  // out is in2out itself (same type) or a separate buffer that does not overlap it
+  auto esz = [](int t) -> size_t { return t == EL_F64 ? 8 : t == EL_F32 ? 4 : 2; };
+  const size_t per = (size_t)de->host.m * de->host.m;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(in2out), a1 = a0 + (size_t)E * per * esz(op_dtype);
+  const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + (size_t)E * per * esz(out_dtype);
+  if (out == in2out ? out_dtype != op_dtype : (b0 < a1 && a0 < b1))
+    return set_error(ctx, EL_ERR_ARG, "el_conserve: out must be in2out itself or not overlap it");
+  return launch_conserve(ctx, de, E, h, kappa, in2out, in2vol, form, op_dtype, mask, out, out_dtype);
 }
 
 el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* a,

@@ -473,15 +473,11 @@ struct Batch {
   template <bool IMP>
   void matvec_t(hipStream_t s, int pred, const double* x, double* y) const {
     const size_t smem = sizeof(double) * m;
-    if (op_dtype == EL_F64)
-      hipLaunchKernelGGL((k_bmatvec<double, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
-                         pred, x, y);
-    else if (op_dtype == EL_F32)
-      hipLaunchKernelGGL((k_bmatvec<float, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
-                         pred, x, y);
-    else
-      hipLaunchKernelGGL((k_bmatvec<uint16_t, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh,
-                         st, pred, x, y);
+    with_op_type(op_dtype, [&](auto tag) {
+      using T = decltype(tag);
+      hipLaunchKernelGGL((k_bmatvec<T, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st, pred,
+                         x, y);
+    });
   }
   void matvec(hipStream_t s, int pred, const double* x, double* y, bool imp) const {
     if (imp) matvec_t<true>(s, pred, x, y);

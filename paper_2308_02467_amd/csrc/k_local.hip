@@ -86,6 +86,9 @@ struct LuArgs {
   float* f_i2s;           // float32 in2sol [E][n][m]
   uint16_t* b_i2m;        // bfloat16 in2mean [E][nn][m]
   float* f_i2m;           // float32 in2mean [E][nn][m]
+  _Float16* h_i2o;        // float16 in2out [E][m][m]
+  _Float16* h_i2s;        // float16 in2sol [E][n][m]
+  _Float16* h_i2m;        // float16 in2mean [E][nn][m]
   uint16_t* pairs;        // bfloat16 (in2out, in2sol) [E][m*m + n*m] or (in2out, in2mean) [E][m*m + nn*m]
   int pairs_form;         // EL_FORM_IN2SOL or EL_FORM_IN2MEAN
   const int32_t* emap;    // batch slot -> element index (inputs and outputs), or null
@@ -882,7 +885,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         const bool pairs_sol = a.pairs && a.pairs_form == EL_FORM_IN2SOL;
         const bool pairs_mean = a.pairs && a.pairs_form == EL_FORM_IN2MEAN;
         const int64_t n_out = (int64_t)m * m + (int64_t)(pairs_mean ? nn : n) * m;
-        if (a.in2sol || a.b_i2s || a.f_i2s || pairs_sol) {
+        if (a.in2sol || a.b_i2s || a.f_i2s || a.h_i2s || pairs_sol) {
           for (int idx = tid; idx < n * NB; idx += kThreads) {
             int r = idx >> 4, c = idx & 15;
             if (P0 + c < m) {
@@ -891,11 +894,12 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
               if (a.in2sol) a.in2sol[o] = v;
               if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
               if (a.f_i2s) a.f_i2s[o] = (float)v;
+              if (a.h_i2s) a.h_i2s[o] = (_Float16)(float)v;
               if (pairs_sol) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
             }
           }
         }
-        if (a.in2out || a.b_i2o || a.f_i2o || a.pairs) {
+        if (a.in2out || a.b_i2o || a.f_i2o || a.h_i2o || a.pairs) {
           for (int idx = tid; idx < m * NB; idx += kThreads) {
             int r = idx >> 4, c = idx & 15;
             if (P0 + c < m) {
@@ -904,11 +908,12 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
               if (a.in2out) a.in2out[o] = v;
               if (a.b_i2o) a.b_i2o[o] = gemm::f2bf((float)v);
               if (a.f_i2o) a.f_i2o[o] = (float)v;
+              if (a.h_i2o) a.h_i2o[o] = (_Float16)(float)v;
               if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
             }
           }
         }
-        if (a.in2mean || a.b_i2m || a.f_i2m || pairs_mean) {
+        if (a.in2mean || a.b_i2m || a.f_i2m || a.h_i2m || pairs_mean) {
           const double s = 1.0 / dv.n_a;
           for (int idx = tid; idx < nn * NB; idx += kThreads) {
             int r = idx >> 4, c = idx & 15;
@@ -921,6 +926,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
               if (a.in2mean) a.in2mean[o] = v;
               if (a.b_i2m) a.b_i2m[o] = gemm::f2bf((float)v);
               if (a.f_i2m) a.f_i2m[o] = (float)v;
+              if (a.h_i2m) a.h_i2m[o] = (_Float16)(float)v;
               if (pairs_mean) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
             }
           }
@@ -964,6 +970,9 @@ struct LocalOut {
   float* f_i2s = nullptr;
   uint16_t* b_i2m = nullptr;
   float* f_i2m = nullptr;
+  _Float16* h_i2o = nullptr;
+  _Float16* h_i2s = nullptr;
+  _Float16* h_i2m = nullptr;
   uint16_t* pairs = nullptr;
   int pairs_form = EL_FORM_IN2SOL;
   const int32_t* emap = nullptr;
@@ -1014,6 +1023,7 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   args.b_i2o = out.b_i2o; args.b_i2s = out.b_i2s; args.pairs = out.pairs; args.emap = out.emap;
   args.f_i2o = out.f_i2o; args.f_i2s = out.f_i2s;
   args.b_i2m = out.b_i2m; args.f_i2m = out.f_i2m; args.pairs_form = out.pairs_form;
+  args.h_i2o = out.h_i2o; args.h_i2s = out.h_i2s; args.h_i2m = out.h_i2m;
   char* base = reinterpret_cast<char*>(ctx->ws_local.ptr);
   args.fac = reinterpret_cast<T*>(base);
   args.inv = reinterpret_cast<T*>(base + fac_bytes);
@@ -1099,6 +1109,9 @@ el_status launch_local_solve_ex(el_ctx* ctx, el_ctx::DiscEntry* de, int precisio
   if (out_dtype == EL_F32) {
     o.f_i2o = reinterpret_cast<float*>(o_i2o);
     (mean ? o.f_i2m : o.f_i2s) = reinterpret_cast<float*>(o_i2v);
+  } else if (out_dtype == EL_F16) {
+    o.h_i2o = reinterpret_cast<_Float16*>(o_i2o);
+    (mean ? o.h_i2m : o.h_i2s) = reinterpret_cast<_Float16*>(o_i2v);
   } else {
     o.b_i2o = reinterpret_cast<uint16_t*>(o_i2o);
     (mean ? o.b_i2m : o.b_i2s) = reinterpret_cast<uint16_t*>(o_i2v);

@@ -5,6 +5,7 @@
 // state are FP32.
 #include <climits>
 #include <cmath>
+#include <type_traits>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -165,7 +166,8 @@ struct EpiOutNorm {
 // output layer, de-normalized operators (bfloat16 or float32): n < mm -> in2out, else in2sol
 template <typename OutT>
 struct EpiOutOps {
-  static constexpr const char* kName = sizeof(OutT) == 2 ? "out_ops_bf16" : "out_ops_f32";
+  static constexpr const char* kName = std::is_same<OutT, _Float16>::value ? "out_ops_f16"
+                                       : sizeof(OutT) == 2 ? "out_ops_bf16" : "out_ops_f32";
   static constexpr bool kRepeatable = true;
   const float* bias;
   const float* ymean;
@@ -179,7 +181,8 @@ struct EpiOutOps {
     int64_t stride;      // per element
   };
   __device__ static inline OutT cvt(float y) {
-    if constexpr (sizeof(OutT) == 2) return f2bf(y);
+    if constexpr (std::is_same<OutT, _Float16>::value) return (_Float16)y;
+    else if constexpr (sizeof(OutT) == 2) return f2bf(y);
     else return y;
   }
   __device__ Col col(int n) const {
@@ -996,7 +999,8 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
                    int precision, int64_t* n_fallback_host) {
   if (!ctx || !cnet) return EL_ERR_ARG;
   if (E <= 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer: bad argument");
-  if (out_dtype != EL_BF16 && out_dtype != EL_F32) return set_error(ctx, EL_ERR_ARG, "el_infer: out_dtype");
+  if (out_dtype != EL_BF16 && out_dtype != EL_F32 && out_dtype != EL_F16)
+    return set_error(ctx, EL_ERR_ARG, "el_infer: out_dtype");
   const size_t osz = out_dtype == EL_F32 ? 4 : 2;
   el_net* net = const_cast<el_net*>(cnet);
   hipSetDevice(ctx->device);
@@ -1044,6 +1048,10 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
     if (out_dtype == EL_F32) {
       EpiOutOps<float> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<float*>(po),
                            reinterpret_cast<float*>(ps), mm_, nm};
+      st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi, true);
+    } else if (out_dtype == EL_F16) {
+      EpiOutOps<_Float16> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<_Float16*>(po),
+                              reinterpret_cast<_Float16*>(ps), mm_, nm};
       st = mm<true, true>(ctx, Hl, W, net->wbf + net->w_off[D], W, B, net->desc.n_out, W, 1, epi, true);
     } else {
       EpiOutOps<uint16_t> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<uint16_t*>(po),

@@ -2,7 +2,7 @@
 // intensity (eq. ang_ave), plus the element L2 norms used for the relative
 // error of Sec. 3.2.1.
 //
-// k_recover streams in2sol [E][n][m] (FP64 or bfloat16) once: one workgroup
+// k_recover streams in2sol [E][n][m] (FP64, FP32, FP16 or bfloat16) once: one workgroup
 // per element gathers the m inflow traces into LDS, groups of 8 lanes reduce
 // one operator row each, u is staged in LDS and the ordinate average is taken
 // there.  HBM-bound: n*m operator entries per element.
@@ -10,70 +10,12 @@
 #include <sstream>
 
 #include "el_internal.h"
+#include "trace_dev.h"
 
 namespace el {
 namespace {
 
 constexpr int kThreads = 256;
-
-struct MeshDev {
-  int n_x, n_y, n_vf;
-};
-
-__device__ inline int face_of(const MeshDev& ms, int i, int j, int f) {
-  switch (f) {
-    case 0: return j * (ms.n_x + 1) + i;
-    case 1: return j * (ms.n_x + 1) + i + 1;
-    case 2: return ms.n_vf + j * ms.n_x + i;
-    default: return ms.n_vf + (j + 1) * ms.n_x + i;
-  }
-}
-
-template <typename OpT>
-__device__ inline double row_dot(const OpT* __restrict__ row, const double* tin, int m, int gl);
-
-template <>
-__device__ inline double row_dot<double>(const double* __restrict__ row, const double* tin, int m, int gl) {
-  double acc = 0.0;
-  for (int c = 2 * gl; c < m; c += 16) {
-    double2 v = *reinterpret_cast<const double2*>(row + c);
-    acc += v.x * tin[c] + v.y * tin[c + 1];
-  }
-  return acc;
-}
-
-template <>
-__device__ inline double row_dot<float>(const float* __restrict__ row, const double* tin, int m, int gl) {
-  double acc = 0.0;
-  for (int c = 4 * gl; c < m; c += 32) {
-    if (c + 4 <= m) {
-      float4 v = *reinterpret_cast<const float4*>(row + c);
-      acc += (double)v.x * tin[c] + (double)v.y * tin[c + 1] + (double)v.z * tin[c + 2] + (double)v.w * tin[c + 3];
-    } else {
-      for (int cc = c; cc < m; ++cc) acc += (double)row[cc] * tin[cc];
-    }
-  }
-  return acc;
-}
-
-template <>
-__device__ inline double row_dot<uint16_t>(const uint16_t* __restrict__ row, const double* tin, int m, int gl) {
-  double acc = 0.0;
-  for (int c = 8 * gl; c < m; c += 64) {
-    if (c + 8 <= m) {
-      uint4 v = *reinterpret_cast<const uint4*>(row + c);
-      uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        acc += (double)__uint_as_float(w[u] << 16) * tin[c + 2 * u];
-        acc += (double)__uint_as_float(w[u] & 0xffff0000u) * tin[c + 2 * u + 1];
-      }
-    } else {
-      for (int cc = c; cc < m; ++cc) acc += (double)__uint_as_float(((uint32_t)row[cc]) << 16) * tin[cc];
-    }
-  }
-  return acc;
-}
 
 // rows = number of operator rows (n for in2sol, nn for in2mean);
 // mode 0: u (and optional mean over ordinates) from in2sol;
@@ -151,71 +93,65 @@ __global__ void k_l2_partial(const double* __restrict__ W, int nn, int64_t E, co
   }
 }
 
-template <typename T> __device__ inline double ld_op(const T* p, int64_t i);
-template <> __device__ inline double ld_op<double>(const double* p, int64_t i) { return p[i]; }
-template <> __device__ inline double ld_op<float>(const float* p, int64_t i) { return (double)p[i]; }
-template <> __device__ inline double ld_op<uint16_t>(const uint16_t* p, int64_t i) {
-  return (double)__uint_as_float(((uint32_t)p[i]) << 16);
-}
-template <typename T> __device__ inline void st_op(T* p, int64_t i, double v);
-template <> __device__ inline void st_op<double>(double* p, int64_t i, double v) { p[i] = v; }
-template <> __device__ inline void st_op<float>(float* p, int64_t i, double v) { p[i] = (float)v; }
-template <> __device__ inline void st_op<uint16_t>(uint16_t* p, int64_t i, double v) {
-  uint32_t u = __float_as_uint((float)v);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  p[i] = (uint16_t)(u >> 16);
-}
-
 // Energy balance of one element, column by column: sum_o w_o in2out[o][i] +
 // sum_(k,nd) W_nd (h kappa_nd / 2) in2sol[(k,nd)][i] = w_i.  Each column of
-// in2out is rescaled so that the balance holds exactly (elements with
-// mask == 0 are left alone).
-template <typename T>
+// in2out is rescaled so that the balance holds exactly; the scale is taken in
+// FP64 from the stored values and the result is rounded once to the output
+// type TW (out may be i2o itself when TW == T).  Elements with mask == 0 are
+// copied unchanged (converted to TW); in place they are skipped.
+template <typename T, typename TW>
 __global__ void k_conserve(DiscDev dv, int64_t E, const double* __restrict__ h, const double* __restrict__ kappa,
-                           T* __restrict__ i2o, const T* __restrict__ i2s, int rows, double mult,
+                           const T* i2o, const T* __restrict__ i2s, TW* out, int rows, double mult,
                            const uint8_t* __restrict__ mask) {
   const int64_t e = blockIdx.x;
-  if (e >= E || (mask && !mask[e])) return;
+  if (e >= E) return;
+  const bool keep = mask && !mask[e];
+  const bool in_place = reinterpret_cast<const void*>(out) == reinterpret_cast<const void*>(i2o);
+  if (keep && in_place) return;
   extern __shared__ double wa[];   // [nn] = W_nd h kappa_nd / 2
   const int nn = dv.nn, m = dv.m;
   for (int nd = threadIdx.x; nd < nn; nd += blockDim.x) wa[nd] = dv.W[nd] * 0.5 * h[e] * kappa[e * nn + nd];
   __syncthreads();
   const T* S = i2s + (size_t)e * rows * m;
-  T* O = i2o + (size_t)e * m * m;
+  const T* O = i2o + (size_t)e * m * m;
+  TW* W = out + (size_t)e * m * m;
   for (int c = threadIdx.x; c < m; c += blockDim.x) {
-    double absorb = 0.0;
-    for (int r = 0; r < rows; ++r) absorb += wa[r % nn] * ld_op<T>(S, (int64_t)r * m + c);
-    absorb *= mult;
-    double out = 0.0;
-    for (int o = 0; o < m; ++o) out += dv.out_val[o] * ld_op<T>(O, (int64_t)o * m + c);
-    const double target = dv.in_val[c] - absorb;
-    if (out > 0.0 && target > 0.0) {
-      const double s = target / out;
-      for (int o = 0; o < m; ++o) st_op<T>(O, (int64_t)o * m + c, s * ld_op<T>(O, (int64_t)o * m + c));
+    double s = 1.0;
+    if (!keep) {
+      double absorb = 0.0;
+      for (int r = 0; r < rows; ++r) absorb += wa[r % nn] * op_to_double(S[(int64_t)r * m + c]);
+      absorb *= mult;
+      double sum = 0.0;
+      for (int o = 0; o < m; ++o) sum += dv.out_val[o] * op_to_double(O[(int64_t)o * m + c]);
+      const double target = dv.in_val[c] - absorb;
+      if (sum > 0.0 && target > 0.0) s = target / sum;
     }
+    for (int o = 0; o < m; ++o) W[(int64_t)o * m + c] = op_from_double<TW>(s * op_to_double(O[(int64_t)o * m + c]));
   }
 }
 
 }  // namespace
 
 el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* kappa,
-                          void* in2out, const void* in2vol, int form, int op_dtype, const uint8_t* mask) {
+                          const void* in2out, const void* in2vol, int form, int op_dtype, const uint8_t* mask,
+                          void* out, int out_dtype) {
   const size_t smem = sizeof(double) * de->host.nn;
   // in2sol: absorption sums all (k, nd) rows; in2mean holds the ordinate
   // average, so its nn rows are summed and multiplied by N_a
   const bool mean = form == EL_FORM_IN2MEAN;
   const int rows = mean ? de->host.nn : de->host.n;
   const double mult = mean ? (double)de->host.n_a : 1.0;
-  if (op_dtype == EL_F64)
-    hipLaunchKernelGGL(k_conserve<double>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
-                       reinterpret_cast<double*>(in2out), reinterpret_cast<const double*>(in2vol), rows, mult, mask);
-  else if (op_dtype == EL_F32)
-    hipLaunchKernelGGL(k_conserve<float>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
-                       reinterpret_cast<float*>(in2out), reinterpret_cast<const float*>(in2vol), rows, mult, mask);
-  else
-    hipLaunchKernelGGL(k_conserve<uint16_t>, dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
-                       reinterpret_cast<uint16_t*>(in2out), reinterpret_cast<const uint16_t*>(in2vol), rows, mult,
-                       mask);
+  auto run = [&](auto in_tag, auto out_tag) {
+    using T = decltype(in_tag);
+    using TW = decltype(out_tag);
+    hipLaunchKernelGGL((k_conserve<T, TW>), dim3((unsigned)E), dim3(256), smem, ctx->stream, de->view, E, h, kappa,
+                       reinterpret_cast<const T*>(in2out), reinterpret_cast<const T*>(in2vol),
+                       reinterpret_cast<TW*>(out), rows, mult, mask);
+  };
+  if (out_dtype == op_dtype) with_op_type(op_dtype, [&](auto tag) { run(tag, tag); });
+  else if (op_dtype == EL_F32 && out_dtype == EL_F16) run(float{}, _Float16{});
+  else if (op_dtype == EL_F32 && out_dtype == EL_BF16) run(float{}, uint16_t{});
+  else return set_error(ctx, EL_ERR_ARG, "el_conserve: output type must be the input type, or FP16/BF16 from FP32");
   return hip_check(ctx, hipGetLastError(), "launch k_conserve");
 }
 
@@ -225,15 +161,11 @@ el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh
   const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
   const DiscHost& dh = de->host;
   const size_t smem = sizeof(double) * (dh.m + dh.n);
-  if (op_dtype == EL_F64)
-    hipLaunchKernelGGL(k_recover<double>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const double*>(in2sol), dh.n, 0, trace, u, mean);
-  else if (op_dtype == EL_F32)
-    hipLaunchKernelGGL(k_recover<float>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const float*>(in2sol), dh.n, 0, trace, u, mean);
-  else
-    hipLaunchKernelGGL(k_recover<uint16_t>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const uint16_t*>(in2sol), dh.n, 0, trace, u, mean);
+  with_op_type(op_dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL(k_recover<T>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const T*>(in2sol), dh.n, 0, trace, u, mean);
+  });
   return hip_check(ctx, hipGetLastError(), "launch k_recover");
 }
 
@@ -243,15 +175,11 @@ el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh&
   const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
   const DiscHost& dh = de->host;
   const size_t smem = sizeof(double) * (dh.m + dh.nn);
-  if (op_dtype == EL_F64)
-    hipLaunchKernelGGL(k_recover<double>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const double*>(in2mean), dh.nn, 1, trace, nullptr, mean);
-  else if (op_dtype == EL_F32)
-    hipLaunchKernelGGL(k_recover<float>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const float*>(in2mean), dh.nn, 1, trace, nullptr, mean);
-  else
-    hipLaunchKernelGGL(k_recover<uint16_t>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const uint16_t*>(in2mean), dh.nn, 1, trace, nullptr, mean);
+  with_op_type(op_dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL(k_recover<T>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const T*>(in2mean), dh.nn, 1, trace, nullptr, mean);
+  });
   return hip_check(ctx, hipGetLastError(), "launch k_recover(mean)");
 }
 

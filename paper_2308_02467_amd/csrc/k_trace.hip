@@ -106,15 +106,11 @@ el_status launch_trace_matvec(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh&
   MeshDev ms{mesh.n_x, mesh.n_y, (mesh.n_x + 1) * mesh.n_y};
   const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
   const size_t smem = sizeof(double) * de->host.m;
-  if (op_dtype == EL_F64)
-    hipLaunchKernelGGL(k_matvec<double>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const double*>(in2out), x, y);
-  else if (op_dtype == EL_F32)
-    hipLaunchKernelGGL(k_matvec<float>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const float*>(in2out), x, y);
-  else
-    hipLaunchKernelGGL(k_matvec<uint16_t>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const uint16_t*>(in2out), x, y);
+  with_op_type(op_dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL(k_matvec<T>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,
+                       reinterpret_cast<const T*>(in2out), x, y);
+  });
   return hip_check(ctx, hipGetLastError(), "launch k_matvec");
 }
 

@@ -32,6 +32,37 @@ __device__ inline double bf16_to_double(uint16_t b) {
   return (double)__uint_as_float(((uint32_t)b) << 16);
 }
 
+// Storage types of the element operators (in2out, in2sol, in2mean): double
+// (EL_F64), float (EL_F32), _Float16 (EL_F16) and bfloat16 bit patterns held
+// in uint16_t (EL_BF16).  with_op_type calls f with a value of the type that
+// op_dtype names.
+template <typename F>
+inline void with_op_type(int op_dtype, F&& f) {
+  switch (op_dtype) {
+    case EL_F64: f(double{}); break;
+    case EL_F32: f(float{}); break;
+    case EL_F16: f(_Float16{}); break;
+    default: f(uint16_t{}); break;
+  }
+}
+
+__device__ inline double op_to_double(double v) { return v; }
+__device__ inline double op_to_double(float v) { return (double)v; }
+__device__ inline double op_to_double(_Float16 v) { return (double)(float)v; }
+__device__ inline double op_to_double(uint16_t v) { return bf16_to_double(v); }
+
+// rounding to the storage type (round to nearest even; FP64 -> FP32 first)
+template <typename T> __device__ inline T op_from_double(double v);
+template <> __device__ inline double op_from_double<double>(double v) { return v; }
+template <> __device__ inline float op_from_double<float>(double v) { return (float)v; }
+template <> __device__ inline _Float16 op_from_double<_Float16>(double v) { return (_Float16)(float)v; }
+template <> __device__ inline uint16_t op_from_double<uint16_t>(double v) {
+  uint32_t u = __float_as_uint((float)v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 // Row dot products of one element operator with the gathered inflow traces.
 // Groups of 8 lanes per row; each lane loads 16 bytes per step.
 template <typename OpT>
@@ -75,6 +106,22 @@ __device__ inline double row_dot<uint16_t>(const uint16_t* __restrict__ row, con
       }
     } else {
       for (int cc = c; cc < m; ++cc) acc += bf16_to_double(row[cc]) * tin[cc];
+    }
+  }
+  return acc;
+}
+
+template <>
+__device__ inline double row_dot<_Float16>(const _Float16* __restrict__ row, const double* tin, int m, int gl) {
+  typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+  double acc = 0.0;
+  for (int c = 8 * gl; c < m; c += 64) {
+    if (c + 8 <= m) {
+      const h8 v = *reinterpret_cast<const h8*>(row + c);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += (double)(float)v[u] * tin[c + u];
+    } else {
+      for (int cc = c; cc < m; ++cc) acc += (double)(float)row[cc] * tin[cc];
     }
   }
   return acc;

@@ -27,6 +27,7 @@ EL_FP32_IR = 1
 EL_F64 = 0
 EL_BF16 = 1
 EL_F32 = 2
+EL_F16 = 3
 
 _ERRNAMES = {EL_ERR_ARG: "EL_ERR_ARG", EL_ERR_HIP: "EL_ERR_HIP", EL_ERR_SINGULAR: "EL_ERR_SINGULAR",
              EL_ERR_NONFINITE: "EL_ERR_NONFINITE", EL_ERR_NOMEM: "EL_ERR_NOMEM"}
@@ -98,7 +99,7 @@ _SIGS = {
     "el_mean_l2": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                    ctypes.POINTER(ctypes.c_double)],
     "el_conserve": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                    ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
+                    ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "el_net_create": [ctypes.c_void_p, ctypes.POINTER(el_net_desc), ctypes.POINTER(ctypes.c_void_p)],
     "el_net_destroy": [ctypes.c_void_p],
     "el_net_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
@@ -201,9 +202,11 @@ def _op_dtype(t):
         return EL_F64
     if t.dtype == torch.float32:
         return EL_F32
+    if t.dtype == torch.float16:
+        return EL_F16
     if t.dtype in (torch.bfloat16, torch.int16, torch.uint16):
         return EL_BF16
-    raise ValueError(f"operator dtype {t.dtype} not supported (float64, float32 or bfloat16)")
+    raise ValueError(f"operator dtype {t.dtype} not supported (float64, float32, float16 or bfloat16)")
 
 
 class Context:
@@ -307,8 +310,10 @@ class Context:
                                                  _ptr(trace, torch.float64, trace_size(d, ms), "trace"),
                                                  _ptr(mean, torch.float64, E * nn, "mean")))
 
-    def el_conserve(self, d, h, kappa, in2out, in2sol=None, mask=None, in2mean=None):
-        """Energy-balance correction of in2out given in2sol or in2mean."""
+    def el_conserve(self, d, h, kappa, in2out, in2sol=None, mask=None, in2mean=None, out=None):
+        """Energy-balance correction of in2out given in2sol or in2mean, in place
+        or (out given) into out, which may be float16 or bfloat16 when the
+        operators are float32 (rounded once, after the correction)."""
         nn, n, m = disc_sizes(d)
         E = h.numel()
         if (in2sol is None) == (in2mean is None):
@@ -317,11 +322,13 @@ class Context:
         dt = _op_dtype(in2out)
         if _op_dtype(vol) != dt:
             raise ValueError("in2out and the volume operator must share one dtype")
+        odt = _op_dtype(out) if out is not None else dt
         return self._check(lib().el_conserve(self.h, d, E, _ptr(h, torch.float64, E, "h"),
                                              _ptr(kappa, torch.float64, E * nn, "kappa"),
                                              _ptr(in2out, numel=E * m * m, name="in2out"),
                                              _ptr(vol, numel=E * rows * m, name="in2vol"), form, dt,
-                                             _ptr(mask, torch.uint8, E, "mask")))
+                                             _ptr(mask, torch.uint8, E, "mask"),
+                                             _ptr(out, numel=E * m * m, name="out"), odt))
 
     def el_mean_l2(self, d, h, a, ref):
         nn, _, _ = disc_sizes(d)
@@ -406,7 +413,7 @@ class Net:
     def infer(self, d, h, kappa, sigma, in2out=None, in2sol=None, in_range=None, fallback=True,
               precision=EL_FP64, in2mean=None):
         """in2out and in2sol (network in the in2sol form) or in2mean (in2mean
-        form): bfloat16 or float32 device tensors of one dtype."""
+        form): bfloat16, float16 or float32 device tensors of one dtype."""
         nn, n, m = disc_sizes(d)
         E = h.numel()
         if in2sol is not None and in2mean is not None:
@@ -415,8 +422,8 @@ class Net:
         rows = n if in2mean is None else nn
         ref = in2out if in2out is not None else vol
         dt = _op_dtype(ref) if ref is not None else EL_BF16
-        if dt not in (EL_BF16, EL_F32):
-            raise ValueError("learned operators are stored as bfloat16 or float32")
+        if dt not in (EL_BF16, EL_F32, EL_F16):
+            raise ValueError("learned operators are stored as bfloat16, float16 or float32")
         for t, cnt, name in ((in2out, E * m * m, "in2out"), (vol, E * rows * m, "in2sol/in2mean")):
             if t is not None and (_op_dtype(t) != dt or t.numel() != cnt):
                 raise ValueError(f"{name}: expected {cnt} elements of the common dtype")

@@ -164,7 +164,15 @@ def test_make_pairs_match_oracle(ctx):
     assert np.mean(got == bf16_round(ref)) > 0.99
 
 
-@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+# rounding of the stored operators: relative bound and the smallest spacing
+# (binary16 subnormals)
+ROUND = {torch.bfloat16: (2.0 ** -7, 1e-30), torch.float16: (2.0 ** -10, 2.0 ** -24), torch.float32: (1e-6, 1e-30)}
+NP_ROUND = {torch.bfloat16: bf16_round,
+            torch.float16: lambda a: a.astype(np.float16).astype(np.float64),
+            torch.float32: lambda a: a.astype(np.float32).astype(np.float64)}
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, torch.float16])
 def test_infer_range_mask_and_fallback(ctx, dtype):
     from paper_2308_02467_amd import el
     p, n_a = 2, 4
@@ -188,17 +196,19 @@ def test_infer_range_mask_and_fallback(ctx, dtype):
     i2o = torch.empty((E, m, m), dtype=dtype, device=DEV)
     i2s = torch.empty((E, n, m), dtype=dtype, device=DEV)
     mask = torch.empty(E, dtype=torch.uint8, device=DEV)
-    rnd = bf16_round if dtype == torch.bfloat16 else (lambda a: a.astype(np.float32).astype(np.float64))
-    print("[el_infer] with fallback", flush=True)
+    rnd = NP_ROUND[dtype]
+    print(f"[el_infer] with fallback {dtype}", flush=True)
     nfb = net.infer(d, T(hh), T(kap), T(sig), i2o, i2s, mask, fallback=True)
     assert nfb == 3
     exp_mask = np.ones(E, np.uint8)
     exp_mask[out_idx] = 0
     assert np.array_equal(mask.cpu().numpy(), exp_mask)
-    # fallback elements: plain FP64 local solve rounded to bfloat16
+    # fallback elements: plain FP64 local solve rounded to the storage type
+    # (the kernel rounds through FP32: at most one unit apart)
     r_o, r_s, _ = local_solve_batch(o, hh[out_idx], kap[out_idx], sig[out_idx])
     got_o = i2o.to(torch.float64).cpu().numpy()[out_idx]
-    assert np.all(np.abs(got_o - rnd(r_o)) <= 2.0 ** -7 * np.abs(r_o) + 1e-30)
+    rel, tiny = ROUND[dtype]
+    assert np.all(np.abs(got_o - rnd(r_o)) <= rel * np.abs(r_o) + tiny)
     if dtype == torch.float32:
         assert rel_err(got_o, r_o) <= 1e-6
     # in-range elements: de-normalized network output rounded to bfloat16
@@ -274,7 +284,42 @@ def test_make_pairs_in2mean_form(ctx):
     assert np.mean(got == bf16_round(ref)) > 0.99
 
 
-@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_infer_storage_types_are_the_rounded_float32_outputs(ctx):
+    """The float16 and bfloat16 outputs of el_infer are its float32 outputs
+    rounded to nearest: one GEMM, rounded in the epilogue."""
+    from paper_2308_02467_amd import el
+    p, n_a = 2, 4
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    n_in, n_out = 1 + 2 * nn, m * m + n * m
+    rng = np.random.default_rng(29)
+    hn = _host_net(rng, n_in, 64, 2, n_out)
+    net = _load(ctx, hn, n_in, 64, 2, n_out)
+    E = 37
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
+    hh = T(rng.uniform(0.012, 0.048, E))
+    kap = T(rng.uniform(0.03, 1.9, (E, nn)))
+    sig = T(rng.uniform(0.2, 19, (E, nn)))
+    outs = {}
+    for dt in (torch.float32, torch.float16, torch.bfloat16):
+        i2o = torch.empty((E, m, m), dtype=dt, device=DEV)
+        i2s = torch.empty((E, n, m), dtype=dt, device=DEV)
+        print(f"[el_infer] {dt}", flush=True)
+        net.infer(d, hh, kap, sig, i2o, i2s, None, fallback=False)
+        outs[dt] = (i2o, i2s)
+    for dt in (torch.float16, torch.bfloat16):
+        for got, f32 in zip(outs[dt], outs[torch.float32]):
+            # equal, except where the float32 output is a tie between two
+            # 16-bit neighbours (the epilogue's value may differ from it in
+            # the last float32 bit: its multiply-add is fused differently)
+            ref = f32.to(dt)
+            bad = got != ref
+            assert torch.all(got[bad].double() + ref[bad].double() == 2 * f32[bad].double())
+            assert int(bad.sum()) <= 1e-3 * bad.numel()
+    net.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, torch.float16])
 def test_infer_in2mean_form_with_fallback(ctx, dtype):
     """A network in the in2mean form writes (in2out, in2mean); elements
     outside the training box get the plain solver's in2out and in2mean."""
@@ -302,11 +347,11 @@ def test_infer_in2mean_form_with_fallback(ctx, dtype):
     nfb = net.infer(d, T(hh), T(kap), T(sig), i2o, in2mean=i2m, fallback=True)
     assert nfb == 2
     r_o, _, r_m = local_solve_batch(o, hh[out_idx], kap[out_idx], sig[out_idx])
-    tol = 2.0 ** -7 if dtype == torch.bfloat16 else 1e-6
+    tol, tiny = ROUND[dtype]
     got_m = i2m.to(torch.float64).cpu().numpy()[out_idx]
     got_o = i2o.to(torch.float64).cpu().numpy()[out_idx]
-    assert np.all(np.abs(got_m - r_m) <= tol * np.abs(r_m) + 1e-30)
-    assert np.all(np.abs(got_o - r_o) <= tol * np.abs(r_o) + 1e-30)
+    assert np.all(np.abs(got_m - r_m) <= tol * np.abs(r_m) + tiny)
+    assert np.all(np.abs(got_o - r_o) <= tol * np.abs(r_o) + tiny)
     x = np.concatenate([hh[:, None], kap, sig], axis=1)
     X0 = features(x, hn["fm"].astype(np.float64), hn["fs"].astype(np.float64), hn["k0"])
     yn, _ = hn["oracle"].forward(X0, bf16=True)

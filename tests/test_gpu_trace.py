@@ -2,8 +2,11 @@
 
 * element DOF maps and the boundary right-hand side: bit-exact (integers /
   copies of the boundary data);
-* (I - P) x with FP64 operators: <= 1e-13 relative; with bfloat16 operators
-  against the oracle product with the same bfloat16-rounded operator: <= 1e-13;
+* (I - P) x with FP64 operators: <= 1e-13 relative; with FP32, FP16 and
+  bfloat16 operators against the oracle product with the same rounded
+  operator: <= 1e-13 (the products accumulate in FP64);
+* recovery from FP32, FP16 and bfloat16 in2sol / in2mean against the oracle
+  with the same rounded operators: <= 1e-13;
 * trace solution (GMRES at 1e-12 vs the oracle's sparse direct solve) and the
   recovered intensity / mean intensity: <= 1e-10 relative;
 * at 32 x 32 (p = 6, N_a = 16) where the oracle cannot run whole: sampled
@@ -89,6 +92,41 @@ def test_matvec_f64_and_bf16(ctx, p, n_a, nx, ny):
     ctx.el_trace_matvec(d, ms, op32, T(x), y)
     ref32 = otrace.matvec(op32.to(torch.float64).cpu().numpy(), ind, outd, x)
     assert rel_err(y.cpu().numpy(), ref32) <= 1e-13
+    # IEEE binary16 operator
+    oph = T(i2o).to(torch.float16)
+    print(f"[el_trace_matvec] p={p} n_a={n_a} {nx}x{ny} f16", flush=True)
+    ctx.el_trace_matvec(d, ms, oph, T(x), y)
+    refh = otrace.matvec(oph.to(torch.float64).cpu().numpy(), ind, outd, x)
+    assert rel_err(y.cpu().numpy(), refh) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.bfloat16])
+def test_recover_operator_dtypes(ctx, dtype):
+    """u = in2sol t_in and the mean intensity (from in2sol and from in2mean)
+    with rounded operators, against the oracle with the same rounding."""
+    from paper_2308_02467_amd import el
+    p, n_a, nx, ny = 3, 8, 3, 4
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, ny)
+    _, i2s, i2m = local_solve_batch(od, hh, kap, sig)
+    ind, _ = oms.element_dofs(od)
+    d, ms = el.disc(p, n_a), el.mesh(nx, ny, oms.h)
+    nn, n, m = el.disc_sizes(d)
+    E = nx * ny
+    t = np.random.default_rng(3).standard_normal(el.trace_size(d, ms))
+    S = T(i2s).to(dtype)
+    Mn = T(i2m).to(dtype)
+    u = torch.full((E, n), float("nan"), dtype=torch.float64, device=DEV)
+    mean = torch.full((E, nn), float("nan"), dtype=torch.float64, device=DEV)
+    mean2 = torch.full_like(mean, float("nan"))
+    print(f"[el_recover] {dtype}", flush=True)
+    ctx.el_recover(d, ms, S, T(t), u, mean)
+    ctx.el_recover_mean(d, ms, Mn, T(t), mean2)
+    Sr = S.to(torch.float64).cpu().numpy()
+    Mr = Mn.to(torch.float64).cpu().numpy()
+    u_ref = orecover.recover(Sr, ind, t)
+    assert rel_err(u.cpu().numpy(), u_ref) <= 1e-13
+    assert rel_err(mean.cpu().numpy(), orecover.mean_intensity(od, u_ref)) <= 1e-13
+    assert rel_err(mean2.cpu().numpy(), orecover.recover(Mr, ind, t)) <= 1e-13
 
 
 def _gpu_pipeline(ctx, p, n_a, g, nx, ny, hh, kap, sig, g_side, tol=1e-12, outputs=True):
@@ -172,7 +210,14 @@ def test_full_size_32x32_sampled_and_energy(ctx):
     assert rel_err(u[:, od.out_rows].reshape(-1), gpu["t"][outd].reshape(-1)) <= 1e-10
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+# balance after the rescaling, relative to the largest inflow weight: the
+# rescaled entries are rounded back to the storage type
+CONSERVE_TOL = {torch.float64: 1e-12, torch.float32: 2e-6, torch.float16: 2e-3}
+# change of exact operators (which already balance) beyond their rounding
+CONSERVE_KEEP = {torch.float64: 1e-13, torch.float32: 1e-6, torch.float16: 1e-3}
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
 def test_conserve_energy_balance(ctx, dtype):
     """el_conserve leaves exact operators unchanged (they already satisfy the
     per-element energy balance) and restores the balance of perturbed ones."""
@@ -189,12 +234,12 @@ def test_conserve_energy_balance(ctx, dtype):
         ab = np.einsum("n,enm->em", np.tile(o.W, n_a), (0.5 * h[:, None, None] * np.tile(kap, (1, n_a))[:, :, None]) * S)
         return np.einsum("o,eom->em", wout, O) + ab - win[None, :]
 
-    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    tol = CONSERVE_TOL[dtype]
     O = T(i2o).to(dtype)
     S = T(i2s).to(dtype)
     print(f"[el_conserve] {dtype}", flush=True)
     ctx.el_conserve(d, T(h), T(kap), O, S)
-    assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= (1e-13 if dtype == torch.float64 else 1e-6)
+    assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= CONSERVE_KEEP[dtype]
     rng = np.random.default_rng(0)
     Op = T(i2o * (1 + 0.02 * rng.standard_normal(i2o.shape))).to(dtype)
     mask = torch.ones(20, dtype=torch.uint8, device=DEV)
@@ -205,6 +250,46 @@ def test_conserve_energy_balance(ctx, dtype):
     keep = np.arange(20) != 5
     assert np.abs(bal[keep]).max() <= tol * np.abs(win).max()
     assert np.abs(bal[5]).max() > 1e-4            # masked element untouched
+
+
+@pytest.mark.parametrize("odt", [torch.float16, torch.bfloat16])
+def test_conserve_out_of_place_rounds_once(ctx, odt):
+    """float32 operators corrected into a float16 / bfloat16 output: the
+    float32 in-place correction rounded to the 16-bit type (bit-exact up to
+    ties); masked elements are copied unchanged; overlapping or widening
+    outputs are refused."""
+    from paper_2308_02467_amd import el
+    p, n_a = 3, 8
+    o = LocalDisc(p, n_a)
+    E = 16
+    h, kap, sig = inputs.training_draws(E, o.xi, seed=8)
+    i2o, i2s, _ = local_solve_batch(o, h, kap, sig)
+    d = el.disc(p, n_a)
+    rng = np.random.default_rng(5)
+    O32 = T(i2o * (1 + 0.01 * rng.standard_normal(i2o.shape))).to(torch.float32)
+    S32 = T(i2s).to(torch.float32)
+    mask = torch.ones(E, dtype=torch.uint8, device=DEV)
+    mask[3] = 0
+    out = torch.full(O32.shape, float("nan"), dtype=odt, device=DEV)
+    print(f"[el_conserve] float32 -> {odt}", flush=True)
+    ctx.el_conserve(d, T(h), T(kap), O32, S32, mask, out=out)
+    src = O32.clone()
+    ctx.el_conserve(d, T(h), T(kap), O32, S32, mask)
+    # the kernel rounds the FP64 product once; the reference rounds it to FP32
+    # first: they may differ only where the FP32 value is a tie between two
+    # neighbours of the 16-bit type
+    ref = O32.to(odt)
+    bad = out != ref
+    assert torch.all(out[bad].double() + ref[bad].double() == 2 * O32[bad].double())
+    assert int(bad.sum()) <= 1e-3 * bad.numel()
+    assert torch.equal(out[3], src[3].to(odt))
+    assert not torch.equal(out[0], src[0].to(odt))
+    overlap = O32.view(-1).view(odt)[2:2 + O32.numel()]       # inside in2out's memory, not at its start
+    with pytest.raises(el.ElError):
+        ctx.el_conserve(d, T(h), T(kap), O32, S32, mask, out=overlap)
+    wide = torch.empty(O32.shape, dtype=torch.float64, device=DEV)
+    with pytest.raises(el.ElError):
+        ctx.el_conserve(d, T(h), T(kap), O32, S32, mask, out=wide)
 
 
 # Batched uneven meshes in one call (sizes in the spirit of the 16^2 ... 128^2
@@ -304,7 +389,7 @@ def test_batched_single_mesh_converged_and_empty_rhs(ctx):
     assert rep[1]["restarts"] >= 1
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
 def test_conserve_in2mean_form(ctx, dtype):
     """The balance with the ordinate-averaged operator: exact (in2out, in2mean)
     pairs are left unchanged and perturbed ones are restored."""
@@ -316,12 +401,12 @@ def test_conserve_in2mean_form(ctx, dtype):
     d = el.disc(p, n_a)
     wout = np.array([o.omega[j] * o.sn[k, f] for (f, k, j, nd, r) in o.out_tab])
     win = np.array([-o.omega[j] * o.sn[k, f] for (f, k, j, nd, r) in o.in_tab])
-    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    tol = CONSERVE_TOL[dtype]
     O = T(i2o).to(dtype)
     Mn = T(i2m).to(dtype)
     print(f"[el_conserve] in2mean {dtype}", flush=True)
     ctx.el_conserve(d, T(h), T(kap), O, in2mean=Mn)
-    assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= (1e-13 if dtype == torch.float64 else 1e-6)
+    assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= CONSERVE_KEEP[dtype]
     rng = np.random.default_rng(2)
     Op = T(i2o * (1 + 0.02 * rng.standard_normal(i2o.shape))).to(dtype)
     ctx.el_conserve(d, T(h), T(kap), Op, in2mean=Mn)
