@@ -128,14 +128,14 @@ template <typename OpT, bool IMP>
 __global__ void __launch_bounds__(kMVThreads) k_bmatvec(DiscDev dv, const BMesh* __restrict__ ms, int n_mesh,
                                                          const BState* __restrict__ st, int pred,
                                                          const double* __restrict__ x, double* __restrict__ y) {
-  extern __shared__ double tin[];
+  extern __shared__ double sm[];
   const int mi = mesh_of_elem(ms, n_mesh, blockIdx.x);
   if (skip(st[mi], pred)) return;
   const BMesh M = ms[mi];
   const int e = (int)((int64_t)blockIdx.x - M.e0);
   const MeshDev md{M.n_x, M.n_y, M.n_vf};
   matvec_element<OpT, IMP>(dv, md, e, reinterpret_cast<const OpT*>(M.op) + (size_t)e * dv.m * dv.m, x + M.d0,
-                           y + M.d0, tin);
+                           y + M.d0, sm);
 }
 
 // ---- vector kernels (one block = kChunk DOFs of one mesh) ---------------------
@@ -472,7 +472,7 @@ struct Batch {
   // imp: y = (I - P) x (true residuals); otherwise y = P x (Arnoldi)
   template <bool IMP>
   void matvec_t(hipStream_t s, int pred, const double* x, double* y) const {
-    const size_t smem = sizeof(double) * m;
+    const size_t smem = matvec_smem_bytes(m);
     with_op_type(op_dtype, [&](auto tag) {
       using T = decltype(tag);
       hipLaunchKernelGGL((k_bmatvec<T, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st, pred,

@@ -68,9 +68,9 @@ __global__ void k_trace_rhs(DiscDev dv, MeshDev ms, SideData sd, int64_t n_trace
 template <typename OpT>
 __global__ void __launch_bounds__(kMVThreads) k_matvec(DiscDev dv, MeshDev ms, const OpT* __restrict__ op,
                                                         const double* __restrict__ x, double* __restrict__ y) {
-  extern __shared__ double tin[];
+  extern __shared__ double sm[];
   const int e = blockIdx.x;
-  matvec_element<OpT>(dv, ms, e, op + (size_t)e * dv.m * dv.m, x, y, tin);
+  matvec_element<OpT>(dv, ms, e, op + (size_t)e * dv.m * dv.m, x, y, sm);
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -105,7 +105,7 @@ el_status launch_trace_matvec(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh&
                               int op_dtype, const double* x, double* y) {
   MeshDev ms{mesh.n_x, mesh.n_y, (mesh.n_x + 1) * mesh.n_y};
   const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
-  const size_t smem = sizeof(double) * de->host.m;
+  const size_t smem = matvec_smem_bytes(de->host.m);
   with_op_type(op_dtype, [&](auto tag) {
     using T = decltype(tag);
     hipLaunchKernelGGL(k_matvec<T>, dim3((unsigned)E), dim3(kMVThreads), smem, ctx->stream, de->view, ms,

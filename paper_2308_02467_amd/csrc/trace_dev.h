@@ -127,20 +127,77 @@ __device__ inline double row_dot<_Float16>(const _Float16* __restrict__ row, con
   return acc;
 }
 
+// R rows of one element operator against the gathered inflow traces at
+// once: groups of 8 lanes, 16-byte loads.  The loads of a batch of KB chunks
+// per lane and row are all issued before any product (R KB = 16 loads in
+// flight per lane; m is a multiple of 8, so chunks never straddle the row
+// end).  rows[r]: start of row r; a[r]: its partial sum of this lane.
+template <typename OpT>
+struct RowShape {
+  static constexpr int V = 16 / sizeof(OpT);          // entries per 16-byte chunk
+  static constexpr int R = sizeof(OpT) == 2 ? 4 : 2;  // rows per group and pass
+  static constexpr int KB = 16 / R;                   // chunks per lane and row in a batch
+};
+
+template <typename OpT>
+__device__ inline void row_dots(const OpT* const (&rows)[RowShape<OpT>::R], const double* tin, int m, int gl,
+                                double (&a)[RowShape<OpT>::R]) {
+  constexpr int V = RowShape<OpT>::V, R = RowShape<OpT>::R, KB = RowShape<OpT>::KB;
+  typedef OpT vec __attribute__((ext_vector_type(V)));
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = 0.0;
+  for (int cb = V * gl; cb < m; cb += KB * 8 * V) {
+    vec v[R][KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int c = cb + 8 * V * k;
+      if (c < m) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r][k] = *reinterpret_cast<const vec*>(rows[r] + c);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int c = cb + 8 * V * k;
+      if (c < m) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const double t = tin[c + u];
+#pragma unroll
+          for (int r = 0; r < R; ++r) a[r] += op_to_double(v[r][k][u]) * t;
+        }
+      }
+    }
+  }
+}
+
+// LDS of one element's product: inflow traces, the x values at the outflow
+// DOFs, and the outflow DOF indices
+__host__ __device__ inline size_t matvec_smem_bytes(int m) { return (2 * sizeof(double) + sizeof(int)) * (size_t)m; }
+
 // IMP: y = x - in2out_e x_in at the outflow DOFs of element e and y = x on
 // the domain-inflow DOFs it sees, i.e. y = (I - P) x; !IMP: y = in2out_e x_in
 // and 0 on the domain-inflow DOFs, i.e. y = P x.  x, y: the mesh's trace
-// vectors; tin: m doubles of LDS.
+// vectors; sm: matvec_smem_bytes(m) of LDS.  Every index and x value the
+// element needs is fetched up front, one per thread, so the row loop waits
+// only on the operator stream.
 template <typename OpT, bool IMP = true>
 __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int e, const OpT* __restrict__ op_e,
-                                      const double* __restrict__ x, double* __restrict__ y, double* tin) {
+                                      const double* __restrict__ x, double* __restrict__ y, double* sm) {
   const int i = e % ms.n_x, j = e / ms.n_x;
   const int m = dv.m;
+  double* tin = sm;                                  // [m]
+  double* xo = sm + m;                               // [m]
+  int* odof = reinterpret_cast<int*>(sm + 2 * m);    // [m]
   for (int t = threadIdx.x; t < m; t += kMVThreads) {
     const int f = dv.in_f[t];
     const int F = face_of(ms, i, j, f);
     const int dof = (F * dv.n_a + dv.in_k[t]) * dv.q + dv.in_j[t];
+    const int Fo = face_of(ms, i, j, dv.out_f[t]);
+    const int od = (Fo * dv.n_a + dv.out_k[t]) * dv.q + dv.out_j[t];
     const double v = x[dof];
+    if (IMP) xo[t] = x[od];
+    odof[t] = od;
     tin[t] = v;
     if (on_domain_boundary(ms, i, j, f)) y[dof] = IMP ? v : 0.0;
   }
@@ -152,21 +209,21 @@ __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int 
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
     acc += __shfl_xor(acc, 4);
-    if (gl == 0) {
-      const int F = face_of(ms, i, j, dv.out_f[o]);
-      const int dof = (F * dv.n_a + dv.out_k[o]) * dv.q + dv.out_j[o];
-      y[dof] = IMP ? x[dof] - acc : acc;
-    }
+    if (gl == 0) y[odof[o]] = IMP ? xo[o] - acc : acc;
   };
-  // two rows per group at a time: twice the loads in flight
-  int o = wave * 8 + g;
-  for (; o + kRowStep < m; o += 2 * kRowStep) {
-    const double a0 = row_dot<OpT>(op_e + (size_t)o * m, tin, m, gl);
-    const double a1 = row_dot<OpT>(op_e + (size_t)(o + kRowStep) * m, tin, m, gl);
-    finish(o, a0);
-    finish(o + kRowStep, a1);
+  // R rows per group at a time (rows past the end repeat the group's first
+  // row: loaded, not stored)
+  constexpr int R = RowShape<OpT>::R;
+  for (int o = wave * 8 + g; o < m; o += R * kRowStep) {
+    const OpT* rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rows[r] = op_e + (size_t)(o + r * kRowStep < m ? o + r * kRowStep : o) * m;
+    double a[R];
+    row_dots<OpT>(rows, tin, m, gl, a);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (o + r * kRowStep < m) finish(o + r * kRowStep, a[r]);
   }
-  if (o < m) finish(o, row_dot<OpT>(op_e + (size_t)o * m, tin, m, gl));
 }
 
 }  // namespace el
