@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="elements per side")
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--accuracy", action="store_true",
                     help="GMRES tolerance sweep and operator-storage errors against a 1e-12 FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")

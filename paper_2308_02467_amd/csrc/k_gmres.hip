@@ -386,64 +386,90 @@ __global__ void k_bstart(int n_mesh, double* __restrict__ hs, BLay lay, BState* 
   s.inv = 1.0 / beta;
 }
 
-// Arnoldi column j: H[:, j] = h1 (+ h2), |w|, rotations, stopping test
-__global__ void k_bgivens(int j, int n_mesh, double* __restrict__ hs, BLay lay, BState* __restrict__ st, double tol,
-                          int max_iter) {
-  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mi >= n_mesh) return;
+// Arnoldi column j: H[:, j] = h1 (+ h2), |w|, rotations, stopping test.  One
+// 64-lane block per mesh: the column, the rotations and g are staged in LDS
+// by all lanes, lane 0 applies the rotations (a serial recurrence), all lanes
+// write back.
+__global__ void __launch_bounds__(64) k_bgivens(int j, int n_mesh, double* __restrict__ hs, BLay lay,
+                                                BState* __restrict__ st, double tol, int max_iter) {
+  __shared__ double col[kMaxCnt], c_s[kMaxCnt], s_n[kMaxCnt];
+  const int mi = blockIdx.x;
   BState& s = st[mi];
   if (!s.active) return;
+  const int t = threadIdx.x;
   double* B = hs + (size_t)mi * lay.S;
   const int ld = lay.R + 1;
-  double* col = B + lay.H + (size_t)j * ld;
+  double* colg = B + lay.H + (size_t)j * ld;
   const double* h1 = B + lay.h1;
   const double* h2 = B + lay.h2;
   double* cs = B + lay.cs;
   double* sn = B + lay.sn;
   double* g = B + lay.g;
+  const bool re = s.reorth;
   // Arnoldi on P: P v_j = V h + |w| v_{j+1}, so column j of the Hessenberg
   // matrix of I - P is e_j - h with -|w| below the diagonal
-  for (int i = 0; i <= j; ++i) col[i] = (i == j ? 1.0 : 0.0) - (s.reorth ? h1[i] + h2[i] : h1[i]);
-  const double hn = sqrt(fmax(s.reorth ? B[lay.sc + 3] : B[lay.sc + 2], 0.0));
-  s.reorths += s.reorth;
-  col[j + 1] = -hn;
-  for (int i = 0; i < j; ++i) {
-    const double a0 = col[i], a1 = col[i + 1];
-    col[i] = cs[i] * a0 + sn[i] * a1;
-    col[i + 1] = -sn[i] * a0 + cs[i] * a1;
+  for (int i = t; i <= j; i += 64) {
+    col[i] = (i == j ? 1.0 : 0.0) - (re ? h1[i] + h2[i] : h1[i]);
+    if (i < j) { c_s[i] = cs[i]; s_n[i] = sn[i]; }
   }
-  const double a0 = col[j], a1 = col[j + 1];
-  const double den = hypot(a0, a1);
-  cs[j] = a0 / den;
-  sn[j] = a1 / den;
-  col[j] = den;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  s.iters += 1;
-  s.kused = j + 1;
-  s.inv = hn > 0.0 ? 1.0 / hn : 0.0;
-  if (fabs(g[j + 1]) / s.bn <= tol || s.iters >= max_iter || hn == 0.0 || j + 1 == lay.R) s.active = 0;
+  __syncthreads();
+  if (t == 0) {
+    const double hn = sqrt(fmax(re ? B[lay.sc + 3] : B[lay.sc + 2], 0.0));
+    s.reorths += re;
+    col[j + 1] = -hn;
+    double a_prev = col[0];
+    for (int i = 0; i < j; ++i) {
+      const double a1 = col[i + 1];
+      col[i] = c_s[i] * a_prev + s_n[i] * a1;
+      a_prev = -s_n[i] * a_prev + c_s[i] * a1;
+    }
+    const double a0 = a_prev, a1 = col[j + 1];
+    const double den = hypot(a0, a1);
+    cs[j] = a0 / den;
+    sn[j] = a1 / den;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sn[j] * gj;
+    g[j] = cs[j] * gj;
+    s.iters += 1;
+    s.kused = j + 1;
+    s.inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (fabs(g[j + 1]) / s.bn <= tol || s.iters >= max_iter || hn == 0.0 || j + 1 == lay.R) s.active = 0;
+  }
+  __syncthreads();
+  for (int i = t; i <= j + 1; i += 64) colg[i] = col[i];
 }
 
-// end of a cycle: y = H^{-1} g (upper triangular)
-__global__ void k_bfinish(int n_mesh, double* __restrict__ hs, BLay lay, BState* __restrict__ st) {
-  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mi >= n_mesh) return;
+// end of a cycle: y = H^{-1} g (upper triangular), one 64-lane block per
+// mesh: y_k from the diagonal, then every lane updates its rows i < k
+// (column-oriented back substitution)
+__global__ void __launch_bounds__(64) k_bfinish(int n_mesh, double* __restrict__ hs, BLay lay,
+                                                BState* __restrict__ st) {
+  __shared__ double acc[kMaxCnt];
+  const int mi = blockIdx.x;
   BState& s = st[mi];
-  s.active = 0;
-  if (s.kused == 0) return;
+  const int n = s.kused;
+  __syncthreads();
+  if (threadIdx.x == 0) s.active = 0;
+  if (n == 0) return;
+  const int t = threadIdx.x;
   double* B = hs + (size_t)mi * lay.S;
   const int ld = lay.R + 1;
   const double* H = B + lay.H;
   const double* g = B + lay.g;
   double* y = B + lay.y;
-  for (int i = s.kused - 1; i >= 0; --i) {
-    double acc = g[i];
-    for (int k = i + 1; k < s.kused; ++k) acc -= H[i + (size_t)k * ld] * y[k];
-    y[i] = acc / H[i + (size_t)i * ld];
+  for (int i = t; i < n; i += 64) acc[i] = g[i];
+  __syncthreads();
+  for (int k = n - 1; k >= 0; --k) {
+    const double* hk = H + (size_t)k * ld;
+    const double yk = acc[k] / hk[k];
+    __syncthreads();
+    for (int i = t; i < k; i += 64) acc[i] -= hk[i] * yk;
+    if (t == 0) { acc[k] = yk; y[k] = yk; }
+    __syncthreads();
   }
-  s.restarts += 1;
+  if (t == 0) s.restarts += 1;
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -507,7 +533,7 @@ struct Batch {
     update(s, P_ACTIVE, cnt, lay.h1, w, 1.0, lay.sc + 2, cnt);
     dot(s, P_REORTH, cnt, w, 0, lay.h2);
     update(s, P_REORTH, cnt, lay.h2, w, 1.0, lay.sc + 3);
-    hipLaunchKernelGGL(k_bgivens, dim3(nblocks(n_mesh, 64)), dim3(64), 0, s, j, n_mesh, hs, lay, st, tol, max_iter);
+    hipLaunchKernelGGL(k_bgivens, dim3(n_mesh), dim3(64), 0, s, j, n_mesh, hs, lay, st, tol, max_iter);
     hipLaunchKernelGGL(k_bscale, dim3(nblk), dim3(kVThreads), 0, s, w, ms, n_mesh, st, P_ACTIVE);
   }
 };
@@ -647,7 +673,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
     } else {
       for (int j = 0; j < R; ++j) bt.step(s, j);
     }
-    hipLaunchKernelGGL(k_bfinish, dim3(nblocks(n_mesh, 64)), dim3(64), 0, s, n_mesh, bt.hs, lay, bt.st);
+    hipLaunchKernelGGL(k_bfinish, dim3(n_mesh), dim3(64), 0, s, n_mesh, bt.hs, lay, bt.st);
     hipLaunchKernelGGL(k_bupdate, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.V, Np, -1, bt.hs, lay, lay.y, bt.xcat,
                        -1.0, 0, bt.ms, n_mesh, bt.st, P_USED, bt.partials);
     stt = hip_check(ctx, hipGetLastError(), "el_trace_solve: step");
