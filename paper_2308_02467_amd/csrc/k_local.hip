@@ -603,6 +603,13 @@ __device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, 
   }
 }
 
+// doubles of the per-slot global scratch: the second panel of a pair (one
+// panel of doubles also holds it in FP32), plus two FP64 solution panels
+// with refinement
+__host__ __device__ inline size_t xbuf_doubles_per_slot(int npad, bool ir) {
+  return (size_t)npad * NB * (ir ? 3 : 1);
+}
+
 template <typename T, int MAXT>
 __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   typedef typename Acc<T>::type A4;
@@ -623,12 +630,15 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   int* perm_old = reinterpret_cast<int*>(bbuf + 2 * NB * NB);             // [npad]
   // iterative refinement scratch (only allocated when a.xbuf != null)
   unsigned long long* colmax = reinterpret_cast<unsigned long long*>(
-      reinterpret_cast<unsigned char*>(perm_old) + ((sizeof(int) * npad + 15) / 16) * 16);   // [NB]
-  double* xs = reinterpret_cast<double*>(colmax + NB);                    // [npad][ir_cols]
+      reinterpret_cast<unsigned char*>(perm_old) + ((sizeof(int) * npad + 15) / 16) * 16);   // [2][NB]
+  double* xs = reinterpret_cast<double*>(colmax + 2 * NB);                // [npad][ir_cols]
   const bool ir = sizeof(T) == 4 && a.refine;   // refinement only for the FP32 factorization
-  double* xg = ir ? a.xbuf + (size_t)blockIdx.x * npad * NB : nullptr;
-  T* rs = reinterpret_cast<T*>(a.xbuf + (size_t)blockIdx.x * npad * NB);   // second panel of a pair (the
-                                                                           // refinement reuses it later)
+  // per slot: the second panel of a pair (T), then the FP64 solutions of the
+  // refinement, one per panel of a pair
+  double* slot = a.xbuf + (size_t)blockIdx.x * xbuf_doubles_per_slot(npad, ir);
+  T* rs = reinterpret_cast<T*>(slot);
+  double* xg = ir ? slot + npad * NB : nullptr;
+  double* xg2 = ir ? slot + 2 * npad * NB : nullptr;
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -815,10 +825,10 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     __syncthreads();
 
     // ---- right-hand side panels: X = U^{-1} L^{-1} P (-B_hat), two at a
-    // time (the second in rs) when no refinement follows
+    // time (the second in rs)
     double elem_res = 0.0;
     for (int P0 = 0; P0 < mpad;) {
-      const bool two = !ir && P0 + NB < mpad;
+      const bool two = P0 + NB < mpad;
       for (int idx = tid; idx < npad * NB; idx += kThreads) {
         int r = idx >> 4, c = idx & 15;
         int col = P0 + c;
@@ -844,30 +854,48 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
       if (two) panel_solve2<T, MAXT>(pan, rs, bbuf, fac, inv, perm, npad, sflag[1], wave, lane);
       else panel_solve<T, MAXT>(pan, fac, inv, perm, npad, sflag[1], wave, lane);
       if (ir) {
-        // FP64 solution panel in HBM, refined with FP64 residuals and FP32 corrections
+        // FP64 solution panels in HBM, refined with FP64 residuals and FP32
+        // corrections (both panels of a pair until both meet the tolerance)
         for (int idx = tid; idx < npad * NB; idx += kThreads) {
           int r = idx >> 4, c = idx & 15;
           xg[r * NB + c] = (double)pan[r * LDP + c];
+          if (two) xg2[r * NB + c] = (double)rs[r * NB + c];
         }
         __threadfence_block();
         __syncthreads();
-        for (int it = 0;; ++it) {
-          if (tid < NB) colmax[tid] = 0ull;
-          __syncthreads();
-          if (a.ir_cols == 8) ir_residual<T, 8>(a, pan, perm, tau_e, tau_s, xg, xs, colmax, npad, P0, tid);
-          else if (a.ir_cols == 4) ir_residual<T, 4>(a, pan, perm, tau_e, tau_s, xg, xs, colmax, npad, P0, tid);
-          else ir_residual<T, 2>(a, pan, perm, tau_e, tau_s, xg, xs, colmax, npad, P0, tid);
-          double worst = 0.0;
+        auto residual = [&](const double* x, unsigned long long* cm, int p0) {
+          if (a.ir_cols == 8) ir_residual<T, 8>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid);
+          else if (a.ir_cols == 4) ir_residual<T, 4>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid);
+          else ir_residual<T, 2>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid);
+        };
+        auto worst_of = [&](const unsigned long long* cm, int p0) {
+          double w = 0.0;
           for (int c = 0; c < NB; ++c)
-            if (P0 + c < m) worst = fmax(worst, __longlong_as_double((long long)colmax[c]) / dv.in_val[P0 + c]);
+            if (p0 + c < m) w = fmax(w, __longlong_as_double((long long)cm[c]) / dv.in_val[p0 + c]);
+          return w;
+        };
+        for (int it = 0;; ++it) {
+          if (tid < 2 * NB) colmax[tid] = 0ull;
+          __syncthreads();
+          if (two) {
+            // the second panel's residual goes to rs, then the first's to pan
+            residual(xg2, colmax + NB, P0 + NB);
+            for (int idx = tid; idx < npad * NB; idx += kThreads) rs[idx] = pan[(idx >> 4) * LDP + (idx & 15)];
+            __threadfence_block();
+            __syncthreads();
+          }
+          residual(xg, colmax, P0);
+          const double worst = two ? fmax(worst_of(colmax, P0), worst_of(colmax + NB, P0 + NB)) : worst_of(colmax, P0);
           if (worst <= a.ir_tol || it >= a.ir_steps) {
             elem_res = fmax(elem_res, worst);
             break;
           }
-          panel_solve<T, MAXT>(pan, fac, inv, perm, npad, 0, wave, lane);
+          if (two) panel_solve2<T, MAXT>(pan, rs, bbuf, fac, inv, perm, npad, 0, wave, lane);
+          else panel_solve<T, MAXT>(pan, fac, inv, perm, npad, 0, wave, lane);
           for (int idx = tid; idx < npad * NB; idx += kThreads) {
             int r = idx >> 4, c = idx & 15;
             xg[r * NB + c] += (double)pan[r * LDP + c];
+            if (two) xg2[r * NB + c] += (double)rs[r * NB + c];
           }
           __threadfence_block();
           __syncthreads();
@@ -875,10 +903,12 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
       }
       // outputs (pan rows are volume DOFs in natural order)
       for (int half = 0; half < (two ? 2 : 1); ++half) {
+        const double* xsol = half == 0 ? xg : xg2;   // refined FP64 solution (with ir)
         if (half == 1) {
           // the second panel's solution: rs -> pan
           __syncthreads();
-          for (int idx = tid; idx < npad * NB; idx += kThreads) pan[(idx >> 4) * LDP + (idx & 15)] = rs[idx];
+          if (!ir)
+            for (int idx = tid; idx < npad * NB; idx += kThreads) pan[(idx >> 4) * LDP + (idx & 15)] = rs[idx];
           __syncthreads();
           P0 += NB;
         }
@@ -889,7 +919,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
           for (int idx = tid; idx < n * NB; idx += kThreads) {
             int r = idx >> 4, c = idx & 15;
             if (P0 + c < m) {
-              const double v = ir ? xg[r * NB + c] : (double)pan[r * LDP + c];
+              const double v = ir ? xsol[r * NB + c] : (double)pan[r * LDP + c];
               const int64_t o = ((int64_t)e * n + r) * m + P0 + c;
               if (a.in2sol) a.in2sol[o] = v;
               if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
@@ -903,7 +933,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
           for (int idx = tid; idx < m * NB; idx += kThreads) {
             int r = idx >> 4, c = idx & 15;
             if (P0 + c < m) {
-              const double v = ir ? xg[dv.out_row[r] * NB + c] : (double)pan[dv.out_row[r] * LDP + c];
+              const double v = ir ? xsol[dv.out_row[r] * NB + c] : (double)pan[dv.out_row[r] * LDP + c];
               const int64_t o = ((int64_t)e * m + r) * m + P0 + c;
               if (a.in2out) a.in2out[o] = v;
               if (a.b_i2o) a.b_i2o[o] = gemm::f2bf((float)v);
@@ -920,7 +950,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
             if (P0 + c < m) {
               double acc = 0.0;
               for (int k = 0; k < dv.n_a; ++k)
-                acc += ir ? xg[(k * nn + r) * NB + c] : (double)pan[(k * nn + r) * LDP + c];
+                acc += ir ? xsol[(k * nn + r) * NB + c] : (double)pan[(k * nn + r) * LDP + c];
               const double v = acc * s;
               const int64_t o = ((int64_t)e * nn + r) * m + P0 + c;
               if (a.in2mean) a.in2mean[o] = v;
@@ -952,7 +982,7 @@ __global__ void k_fill_int(int* p, int n, int v) {
 template <typename T>
 size_t lu_smem_bytes(int npad, int nn, int ir_cols) {
   size_t b = lds_base_bytes<T>(npad, nn) + sizeof(T) * 4 * NB * NB + ((sizeof(int) * (size_t)npad + 15) / 16) * 16;
-  if (ir_cols) b += NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * ir_cols;
+  if (ir_cols) b += 2 * NB * sizeof(unsigned long long) + sizeof(double) * (size_t)npad * ir_cols;
   return b + 16;
 }
 
@@ -1006,7 +1036,7 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   const int64_t slots = std::min<int64_t>(E, (int64_t)ctx->num_cus * 2);
   size_t fac_bytes = sizeof(T) * (size_t)slots * npan * npad * NB;
   size_t inv_bytes = sizeof(T) * (size_t)slots * npan * 2 * NB * NB;
-  size_t x_bytes = sizeof(double) * (size_t)slots * npad * NB;
+  size_t x_bytes = sizeof(double) * (size_t)slots * xbuf_doubles_per_slot(npad, ir);
   el_status st = ensure_ws(ctx, ctx->ws_local, fac_bytes + inv_bytes + x_bytes + 256);
   if (st) return st;
   st = ensure_ws(ctx, ctx->ws_small, 8192);
