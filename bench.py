@@ -81,8 +81,7 @@ def log(msg):
 
 
 MATVEC_SOURCES = ("paper_2308_02467_amd/csrc/trace_dev.h", "paper_2308_02467_amd/csrc/k_trace.hip")
-TRAFFIC_SUMMARY = {"float32": "profiles/k_matvec_float_128x128_p6_na16_hbm_traffic.md",
-                   "float16": "profiles/k_matvec_f16_128x128_p6_na16_hbm_traffic.md"}
+TRAFFIC_SUMMARY = {"float16": "profiles/k_matvec_f16_128x128_p6_na16_hbm_traffic.md"}
 MATVEC_KERNEL = {"float32": "k_matvec<float>", "float16": "k_matvec<_Float16>"}
 
 
