@@ -716,6 +716,8 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         double v = fabs((double)pan[r * LDP]);
         if (v > best) { best = v; bidx = r; }
       }
+      // (unrolled: the column c is a constant in each copy of the body)
+#pragma unroll
       for (int c = 0; c < NB; ++c) {
         const int col = J + c;
         for (int off = 32; off > 0; off >>= 1) {
@@ -741,6 +743,9 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         __syncthreads();
         const T piv = pan[col * LDP + c];
         const T rp = piv != T(0) ? T(1) / piv : T(0);
+        T pr[NB];   // pivot row right of the column
+#pragma unroll
+        for (int j = c + 1; j < NB; ++j) pr[j] = pan[col * LDP + j];
         best = -1.0;
         bidx = INT_MAX;
         for (int r = col + 1 + tid; r < npad; r += kThreads) {
@@ -748,8 +753,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
           T l = row[c] * rp;
           row[c] = l;
 #pragma unroll
-          for (int j = 0; j < NB; ++j)
-            if (j > c) row[j] -= l * pan[col * LDP + j];
+          for (int j = c + 1; j < NB; ++j) row[j] -= l * pr[j];
           if (c + 1 < NB) {
             double v = fabs((double)row[c + 1]);
             if (v > best) { best = v; bidx = r; }
@@ -757,22 +761,26 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         }
       }
       __syncthreads();
-      // inverses of the unit-lower and upper diagonal blocks (wave 0:
-      // lanes 0..15 columns of L^{-1}, lanes 16..31 columns of U^{-1})
-      if (wave == 0 && lane < 32) {
+      // inverses of the unit-lower and upper diagonal blocks: lane j of wave
+      // 0 computes column j of L^{-1}, lane j of wave 1 column j of U^{-1}.
+      // The entries of a column above (L) or below (U) the diagonal are
+      // exact zeros, so the substitutions run over full, uniform ranges
+      // (no divergence) and each row of the block is read once from LDS
+      // (the same address for all lanes).
+      if (wave < 2 && lane < NB) {
         const T* D = pan + J * LDP;
+        const int j = lane;
         T x[NB];
-        const int j = lane & 15;
-        if (lane < 16) {
+        if (wave == 0) {
 #pragma unroll
           for (int i = 0; i < NB; ++i) {
-            T s = (i == j) ? T(1) : T(0);
-            if (i > j) {
+            T r[NB];
 #pragma unroll
-              for (int k = 0; k < NB; ++k)
-                if (k >= j && k < i) s -= D[i * LDP + k] * x[k];
-            }
-            x[i] = (i < j) ? T(0) : s;
+            for (int k = 0; k < i; ++k) r[k] = D[i * LDP + k];
+            T s = (i == j) ? T(1) : T(0);
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= r[k] * x[k];
+            x[i] = s;
           }
           T* o = inv + (size_t)(J / NB) * 2 * NB * NB;
 #pragma unroll
@@ -780,11 +788,13 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         } else {
 #pragma unroll
           for (int ii = NB - 1; ii >= 0; --ii) {
+            T r[NB];
+#pragma unroll
+            for (int k = ii; k < NB; ++k) r[k] = D[ii * LDP + k];
             T s = (ii == j) ? T(1) : T(0);
 #pragma unroll
-            for (int k = 0; k < NB; ++k)
-              if (k > ii && k <= j) s -= D[ii * LDP + k] * x[k];
-            x[ii] = (ii > j) ? T(0) : s / D[ii * LDP + ii];
+            for (int k = ii + 1; k < NB; ++k) s -= r[k] * x[k];
+            x[ii] = (ii > j) ? T(0) : s / r[ii];
           }
           T* o = inv + (size_t)(J / NB) * 2 * NB * NB + NB * NB;
 #pragma unroll
