@@ -571,26 +571,42 @@ __device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, 
         for (int c = 0; c < XC; ++c) acc[c] = -xs[q * XC + c];
       } else {
         const int k = q / nn, nd = q - k * nn;
+        const int qd = dv.q, na = nd % qd, nb = nd / qd;
         const double* Trow = dv.T + ((size_t)k * nn + nd) * nn;
+        const double* xk = xs + (size_t)k * nn * XC;
 #pragma unroll
         for (int c = 0; c < XC; ++c) acc[c] = 0.0;
-        for (int j = 0; j < nn; ++j) {
-          const double t = Trow[j];
-          if (t != 0.0) {
-            const double* xr = xs + (k * nn + j) * XC;
+        // the transport block row has nonzeros only at trial nodes in the
+        // same node row (c', nb) or the same node column (na, d'): 2q - 1 of
+        // the nn entries
+        for (int u = 0; u < qd; ++u) {
+          const double t1 = Trow[nb * qd + u];
+          const double* xr = xk + (nb * qd + u) * XC;
 #pragma unroll
-            for (int c = 0; c < XC; ++c) acc[c] += t * xr[c];
+          for (int c = 0; c < XC; ++c) acc[c] += t1 * xr[c];
+          if (u != nb) {
+            const double t2 = Trow[u * qd + na];
+            const double* xq = xk + (u * qd + na) * XC;
+#pragma unroll
+            for (int c = 0; c < XC; ++c) acc[c] += t2 * xq[c];
           }
         }
         const double wd = dv.W[nd] * tau_e[nd], ws = dv.W[nd] * tau_s[nd];
         const double* Qr = dv.Q + k * dv.n_a;
+        double sc[XC];
+#pragma unroll
+        for (int c = 0; c < XC; ++c) sc[c] = 0.0;
+        for (int kp = 0; kp < dv.n_a; ++kp) {
+          const double qk = Qr[kp];
+          const double* xq = xs + (kp * nn + nd) * XC;
+#pragma unroll
+          for (int c = 0; c < XC; ++c) sc[c] += qk * xq[c];
+        }
 #pragma unroll
         for (int c = 0; c < XC; ++c) {
-          double sc = 0.0;
-          for (int kp = 0; kp < dv.n_a; ++kp) sc += Qr[kp] * xs[(kp * nn + nd) * XC + c];
           const int col = P0 + c0 + c;
           const double rv = (col < m && q == dv.in_row[col]) ? dv.in_val[col] : 0.0;
-          acc[c] = rv - (acc[c] + wd * xs[q * XC + c] - ws * sc);
+          acc[c] = rv - (acc[c] + wd * xs[q * XC + c] - ws * sc[c]);
         }
       }
 #pragma unroll
