@@ -563,6 +563,11 @@ __device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, 
       xs[idx] = xg[r * NB + c0 + c];
     }
     __syncthreads();
+    // running max of |residual| per column as bit patterns (a NaN beats
+    // every number), reduced over the wave before one atomic per column
+    unsigned long long mb[XC];
+#pragma unroll
+    for (int c = 0; c < XC; ++c) mb[c] = 0ull;
     for (int i = tid; i < npad; i += kThreads) {
       const int q = perm[i];
       double acc[XC];
@@ -612,8 +617,19 @@ __device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, 
 #pragma unroll
       for (int c = 0; c < XC; ++c) {
         pan[i * LDP + c0 + c] = (T)acc[c];
-        atomicMax(&colmax[c0 + c], (unsigned long long)__double_as_longlong(fabs(acc[c])));
+        const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(acc[c]));
+        mb[c] = b > mb[c] ? b : mb[c];
       }
+    }
+#pragma unroll
+    for (int c = 0; c < XC; ++c) {
+      unsigned long long v = mb[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+      }
+      if ((tid & 63) == 0) atomicMax(&colmax[c0 + c], v);
     }
     __syncthreads();
   }
