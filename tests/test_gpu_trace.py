@@ -347,6 +347,40 @@ def test_batched_uneven_meshes_parity(ctx):
         assert rel_err(t, ref["t"]) <= 1e-10, (oms.n_x, oms.n_y, rel_err(t, ref["t"]))
 
 
+@pytest.mark.parametrize("dtype", [torch.float16, torch.float32])
+def test_batched_rounded_operators_parity(ctx, dtype):
+    """GMRES over several meshes with FP16 / FP32 operators: the solution of
+    (I - P~) t = b with the rounded operators P~, against the oracle's direct
+    solve with the same rounded operators."""
+    from paper_2308_02467_amd import el
+    p, n_a = 3, 8
+    probs = _batched_problem(p, n_a)[:4]
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    gs = inputs.left_inflow(n_a)
+    meshes, ops, bs, ts, refs = [], [], [], [], []
+    for od, oms, hh, kap, sig in probs:
+        i2o, _, _ = local_solve_batch(od, hh, kap, sig)
+        op = T(i2o).to(dtype)
+        ind, outd = oms.element_dofs(od)
+        rounded = op.to(torch.float64).cpu().numpy()
+        refs.append(otrace.solve_direct(rounded, ind, outd, oms.boundary_vector_sides(od, gs)))
+        ms = el.mesh(oms.n_x, oms.n_y, oms.h)
+        nt = el.trace_size(d, ms)
+        b = torch.empty(nt, dtype=torch.float64, device=DEV)
+        ctx.el_trace_rhs(d, ms, gs, b)
+        meshes.append(ms)
+        ops.append(op)
+        bs.append(b)
+        ts.append(torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV))
+    print(f"[batched] el_trace_solve {dtype} n_mesh={len(meshes)}", flush=True)
+    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=1e-12, restart=20, max_iter=3000)
+    assert st == 0
+    for r, t, ref in zip(rep, ts, refs):
+        assert r["converged"] and r["relres"] <= 1e-12, r
+        assert rel_err(t.cpu().numpy(), ref) <= 1e-10
+
+
 def test_batched_graph_replays_match_eager(ctx):
     """The captured restart cycle gives bit-identical results to launching the
     same kernels one by one, on every replay, with other device work and
