@@ -606,6 +606,20 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     study = storage_study(args, ctx, net, d, ms, hh, kap, sig, g_side, b, mean_plain, E, n, m) \
         if args.storage_study else None
 
+    # the learned solution as the starting guess of the plain FP64 skeleton
+    # solve (an accurate solve at a fraction of the plain iterations)
+    warm = {"tol": 1e-8}
+    for name, guess in (("cold", None), ("from_learned", t)):
+        tw = torch.zeros_like(b) if guess is None else guess.clone()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        st, rw = ctx.el_trace_solve(d, [ms], [i2o_plain], [b], [tw], tol=1e-8, restart=args.restart,
+                                    max_iter=40000, x0=guess is not None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        warm[name] = {"iters": rw[0]["iters"], "gmres_ms": e0.elapsed_time(e1), "converged": rw[0]["converged"]}
+    del tw
+
     n_in = 1 + 2 * nn
     flop_el = 2.0 * (n_in * args.width + (args.depth - 1) * args.width ** 2 + args.width * (m * m + n * m))
     inf_ms = float(np.median(ph[:, 0]))
@@ -627,6 +641,7 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
                                "in2out_rel_err_median": float(np.median(op_raw))},
         "operator_storage": args.op_dtype,
         "storage_study": study,
+        "plain_gmres_warm_start": warm,
         "roofline_matvec": {"bound": "hbm",
                             "kernel": f"{MATVEC_KERNEL[args.op_dtype]} (element body shared with the GMRES product)",
                             "achieved": mv_gbs, "peak": HBM_PEAK_GBS,

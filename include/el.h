@@ -98,6 +98,8 @@ typedef struct {
   int max_iter;   /* total Arnoldi steps */
   int graph;      /* 1: replay each restart cycle as a captured HIP graph;
                      0: launch its kernels one by one (same kernels, same results) */
+  int x0;         /* 0: start from t = 0; 1: trace[] holds the starting guess
+                     on entry (for instance the learned solution) */
 } el_gmres_opts;
 
 typedef struct {
@@ -163,7 +165,8 @@ el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2o
                           int op_dtype, const double* x, double* y);
 
 /* Solve (I - P) t = b for n_mesh independent meshes of any sizes together
- * with restarted GMRES (Sec. 2.3): x0 = 0, Arnoldi on P (the Krylov space
+ * with restarted GMRES (Sec. 2.3) from t = 0 or from the guess in trace
+ * (opts->x0), Arnoldi on P (the Krylov space
  * of I - P is the same; the Hessenberg matrix of I - P follows exactly),
  * classical Gram-Schmidt with DGKS reorthogonalization (second pass when the
  * norm drops below 1/sqrt(2)), Givens rotations, FP64 vectors and reductions.  All meshes share every

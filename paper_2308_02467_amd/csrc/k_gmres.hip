@@ -602,6 +602,10 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
     he = hipMemcpyAsync(bt.bcat + hm[i].d0, b[i], sizeof(double) * hm[i].N, hipMemcpyDeviceToDevice, s);
   if (he != hipSuccess) return hip_check(ctx, he, "el_trace_solve: staging");
   hipLaunchKernelGGL(k_bzero, dim3(nblocks(Np, 256)), dim3(256), 0, s, bt.xcat, Np);
+  if (opts.x0)   // starting guess (the padding between segments stays zero)
+    for (int i = 0; i < n_mesh && he == hipSuccess; ++i)
+      he = hipMemcpyAsync(bt.xcat + hm[i].d0, trace[i], sizeof(double) * hm[i].N, hipMemcpyDeviceToDevice, s);
+  if (he != hipSuccess) return hip_check(ctx, he, "el_trace_solve: starting guess");
   // |b| per mesh (the state is not initialized yet: no skipping)
   hipLaunchKernelGGL(k_bdot, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.bcat, (int64_t)0, 0, bt.bcat, 1, bt.ms,
                      n_mesh, bt.st, P_ALL, bt.partials);
@@ -681,7 +685,9 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   }
   bool all_conv = true;
   for (int i = 0; i < n_mesh; ++i) {
-    he = hipMemcpyAsync(trace[i], bt.xcat + hm[i].d0, sizeof(double) * hm[i].N, hipMemcpyDeviceToDevice, s);
+    // b = 0 has the solution 0 whatever the starting guess
+    if (hst[i].bn == 0.0) he = hipMemsetAsync(trace[i], 0, sizeof(double) * hm[i].N, s);
+    else he = hipMemcpyAsync(trace[i], bt.xcat + hm[i].d0, sizeof(double) * hm[i].N, hipMemcpyDeviceToDevice, s);
     if (he != hipSuccess) return hip_check(ctx, he, "el_trace_solve: copy out");
     rep[i].iters = hst[i].iters;
     rep[i].restarts = hst[i].restarts;

@@ -381,6 +381,43 @@ def test_batched_rounded_operators_parity(ctx, dtype):
         assert rel_err(t.cpu().numpy(), ref) <= 1e-10
 
 
+def test_gmres_starting_guess(ctx):
+    """x0 = 1: starting from the converged solution takes no Arnoldi step and
+    returns it; starting from a perturbed one converges to the oracle's
+    solution; b = 0 returns 0 whatever the guess."""
+    from paper_2308_02467_amd import el
+    p, n_a, nx, ny = 3, 8, 4, 3
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, ny, field="sharp", seed=3)
+    i2o, _, _ = local_solve_batch(od, hh, kap, sig)
+    ind, outd = oms.element_dofs(od)
+    gs = inputs.left_inflow(n_a)
+    ref = otrace.solve_direct(i2o, ind, outd, oms.boundary_vector_sides(od, gs))
+    d, ms = el.disc(p, n_a), el.mesh(nx, ny, oms.h)
+    nt = el.trace_size(d, ms)
+    b = torch.empty(nt, dtype=torch.float64, device=DEV)
+    ctx.el_trace_rhs(d, ms, gs, b)
+    op = T(i2o)
+    t = torch.zeros(nt, dtype=torch.float64, device=DEV)
+    print("[el_trace_solve] cold", flush=True)
+    st, rep = ctx.el_trace_solve(d, [ms], [op], [b], [t], tol=1e-12, restart=20, max_iter=3000)
+    assert st == 0 and rep[0]["iters"] > 0
+    t_cold = t.clone()
+    print("[el_trace_solve] from the solution", flush=True)
+    st, rep = ctx.el_trace_solve(d, [ms], [op], [b], [t], tol=1e-12, restart=20, max_iter=3000, x0=True)
+    assert st == 0 and rep[0]["iters"] == 0 and torch.equal(t, t_cold)
+    rng = np.random.default_rng(9)
+    t.copy_(t_cold + T(1e-3 * rng.standard_normal(nt)))
+    print("[el_trace_solve] from a perturbed solution", flush=True)
+    st, rep = ctx.el_trace_solve(d, [ms], [op], [b], [t], tol=1e-12, restart=20, max_iter=3000, x0=True)
+    assert st == 0 and rep[0]["converged"] and rep[0]["iters"] > 0
+    assert rel_err(t.cpu().numpy(), ref) <= 1e-10
+    z = torch.zeros_like(b)
+    t.copy_(t_cold)
+    print("[el_trace_solve] zero rhs from a nonzero guess", flush=True)
+    st, rep = ctx.el_trace_solve(d, [ms], [op], [z], [t], tol=1e-12, restart=20, max_iter=3000, x0=True)
+    assert st == 0 and rep[0]["converged"] and torch.all(t == 0)
+
+
 def test_batched_graph_replays_match_eager(ctx):
     """The captured restart cycle gives bit-identical results to launching the
     same kernels one by one, on every replay, with other device work and
