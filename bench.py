@@ -71,6 +71,10 @@ def parse():
                     help="run only the realistic-cloud leg (256^2 elements, p=6, N_a=32, HG g=0.85, "
                          "log-normal sigma, learned in2mean form + FP32-refinement fallback)")
     ap.add_argument("--cloud-n", type=int, default=256)
+    ap.add_argument("--cloud-na", type=int, default=32, help="angular cells of the cloud leg")
+    ap.add_argument("--cloud-g", type=float, default=0.85, help="HG asymmetry of the cloud leg")
+    ap.add_argument("--cloud-angular", choices=("ordinates", "p0"), default="ordinates",
+                    help="angular discretization of the cloud leg (p0: the paper's piecewise-constant cells)")
     ap.add_argument("--cloud-train-samples", type=int, default=65536)
     ap.add_argument("--cloud-epochs", type=int, default=60)
     return ap.parse_args()
@@ -372,9 +376,10 @@ def cloud_main(args):
     dev = torch.device("cuda:0")
     ctx = el.Context(0)
     stream = torch.cuda.current_stream()
-    p, n_a, g, nx = 6, 32, 0.85, args.cloud_n
+    p, n_a, g, nx = 6, args.cloud_na, args.cloud_g, args.cloud_n
+    ang = el.EL_ANG_P0 if args.cloud_angular == "p0" else el.EL_ANG_ORDINATES
     h = 1.0 / nx
-    d = el.disc(p, n_a, g)
+    d = el.disc(p, n_a, g, ang)
     ms = el.mesh(nx, nx, h)
     nn, n, m = el.disc_sizes(d)
     E = nx * nx
@@ -496,10 +501,13 @@ def cloud_main(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16+" + {"float16": "f16", "float32": "f32"}[args.op_dtype] + "+f64", "data": "synthetic",
-        "config": {"workload": f"realistic cloud: {nx}x{nx} elements, p=6, N_a=32, HG g=0.85, log-normal sigma "
+        "config": {"workload": f"realistic cloud: {nx}x{nx} elements, p=6, N_a={n_a} "
+                               f"({'P0 angular cells' if args.cloud_angular == 'p0' else 'ordinates'}), "
+                               f"HG g={g}, log-normal sigma "
                                "(k^-5/3, mean 10, log-std 1, zero below threshold), kappa=0.05 sigma+0.01, "
                                "learned in2mean form + FP32-refinement fallback, FP64 GMRES",
-                   "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol, "gmres_restart": args.restart},
+                   "elements": E, "p": p, "n_a": n_a, "g": g, "angular": args.cloud_angular, "gmres_tol": args.tol,
+                   "gmres_restart": args.restart},
         "network": f"{1 + 2 * nn}-{args.width}x{args.depth}-{n_out} GELU (in2out + in2mean)",
         "train_samples": N, "epochs_run": len(hist), "final_train_loss": hist[-1] if hist else None,
         "pair_generation_s": t_gen, "training_s": t_train,

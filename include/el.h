@@ -64,6 +64,10 @@ typedef int el_status;
 #define EL_SCATTER_ISO 0
 #define EL_SCATTER_HG 1
 
+/* angular discretization on the N_a uniform cells of the unit circle */
+#define EL_ANG_ORDINATES 0  /* discrete ordinates at the cell centres */
+#define EL_ANG_P0 1         /* piecewise-constant (P0) angular elements (Sec. 2.4.1) */
+
 /* local-solve precision forms */
 #define EL_FP64 0     /* FP64 LU with partial pivoting */
 #define EL_FP32_IR 1  /* FP32 LU, FP64 residual, iterative refinement */
@@ -76,14 +80,20 @@ typedef int el_status;
 
 typedef struct el_ctx el_ctx;
 
-/* Discretization: Q_p in space, n_a ordinates (n_a % 4 == 0, 1 <= p <= 12),
- * scattering kind and Henyey-Greenstein asymmetry g_hg in [0, 1) (Sec. 2.1;
- * exponent 3/2, normalized so that sum_k' w_k' P[k][k'] = 1). */
+/* Discretization: Q_p in space, n_a angular cells (n_a % 4 == 0, 1 <= p <=
+ * 12), scattering kind and Henyey-Greenstein asymmetry g_hg in [0, 1)
+ * (Sec. 2.1; exponent 3/2, normalized so that sum_k' w_k' P[k][k'] = 1).
+ * angular = EL_ANG_ORDINATES: one direction per cell at its centre;
+ * EL_ANG_P0: piecewise-constant angular basis on the cells (Sec. 2.4.1), i.e.
+ * the cell averages of the direction, sin(pi/n_a)/(pi/n_a) times the centre
+ * direction (no cell straddles an axis, so the face fluxes average the same
+ * way), and the phase matrix averaged over pairs of cells. */
 typedef struct {
   int p;
   int n_a;
   int scatter;
   double g_hg;
+  int angular;
 } el_disc;
 
 /* Uniform mesh of n_x * n_y squares of side h, lower-left corner (x0, y0). */
@@ -129,6 +139,11 @@ el_status el_lgl(int p, double* xi_host, double* w_host);
 /* Volume row of each local inflow / outflow index (host int32 [m] each):
  * the bit-exact indexing contract above. */
 el_status el_index_tables(el_disc d, int32_t* in_rows_host, int32_t* out_rows_host);
+
+/* Angular tables of a discretization (host, no device needed): the
+ * direction of each cell s_host [n_a][2] (centre direction or cell average)
+ * and Q_host [n_a][n_a] = P[k][k'] w_k' (rows sum to 1).  Either may be NULL. */
+el_status el_angular_tables(el_disc d, double* s_host, double* Q_host);
 /* Number of trace DOFs of a mesh. */
 el_status el_trace_size(el_disc d, el_mesh mesh, int64_t* n_trace);
 /* Global trace DOF of every local inflow / outflow index, device int32 [E][m]. */

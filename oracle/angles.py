@@ -14,21 +14,36 @@ with c fixed by the normalization "integral of p over S equals 1".  On the
 discrete ordinates the normalization is imposed discretely,
 sum_k' w_k' P[k, k'] = 1 for every k, so discrete scattering conserves energy
 exactly.  g = 0 gives isotropic scattering, P = 1 / (2 pi).
+
+P0 angular elements (Sec. 2.4.1: piecewise-constant functions on the same
+uniform cells) give the same algebra with cell averages: the streaming
+direction of cell k is the average of s over the cell (written out with the
+antiderivatives of cos and sin), and the scattering kernel between cells k
+and k' is the average of p over the pair of cells (an adaptive double
+integral).
 """
 import numpy as np
 
 
-def ordinates(n_a):
-    """Return (theta, w, s): angles, weights and unit directions [n_a, 2]."""
+def ordinates(n_a, angular="ordinates"):
+    """Return (theta, w, s): cell-centre angles, weights and directions
+    [n_a, 2]; with angular == "p0" the directions are the cell averages of s."""
     if n_a < 4 or n_a % 4 != 0:
         raise ValueError("N_a must be a positive multiple of 4")
-    theta = (np.arange(n_a) + 0.5) * (2.0 * np.pi / n_a)
-    w = np.full(n_a, 2.0 * np.pi / n_a)
-    s = np.stack([np.cos(theta), np.sin(theta)], axis=1)
+    dth = 2.0 * np.pi / n_a
+    theta = (np.arange(n_a) + 0.5) * dth
+    w = np.full(n_a, dth)
+    if angular == "ordinates":
+        s = np.stack([np.cos(theta), np.sin(theta)], axis=1)
+    elif angular == "p0":
+        a, b = np.arange(n_a) * dth, (np.arange(n_a) + 1) * dth
+        s = np.stack([(np.sin(b) - np.sin(a)) / dth, (np.cos(a) - np.cos(b)) / dth], axis=1)
+    else:
+        raise ValueError("angular must be 'ordinates' or 'p0'")
     return theta, w, s
 
 
-def phase_matrix(n_a, g=0.0):
+def phase_matrix(n_a, g=0.0, angular="ordinates"):
     """P[k, k'] on the ordinates; rows satisfy sum_k' w_k' P[k, k'] = 1.
 
     g == 0 is the isotropic case 1/(2 pi) (which satisfies the discrete
@@ -40,7 +55,18 @@ def phase_matrix(n_a, g=0.0):
         return np.full((n_a, n_a), 1.0 / (2.0 * np.pi))
     if not (0.0 <= g < 1.0):
         raise ValueError("HG asymmetry must be in [0, 1)")
-    cosang = np.cos(theta[:, None] - theta[None, :])
-    raw = (1.0 - g * g) / (1.0 + g * g - 2.0 * g * cosang) ** 1.5
+    hg = lambda ang: (1.0 - g * g) / (1.0 + g * g - 2.0 * g * np.cos(ang)) ** 1.5
+    if angular == "ordinates":
+        raw = hg(theta[:, None] - theta[None, :])
+    elif angular == "p0":
+        # average over pairs of cells: the kernel depends on k - k' only
+        from scipy.integrate import dblquad
+        dth = 2.0 * np.pi / n_a
+        q = np.array([dblquad(lambda y, x: hg(dd * dth + x - y), 0.0, dth, 0.0, dth,
+                              epsabs=1e-15, epsrel=1e-13)[0] / dth ** 2 for dd in range(n_a)])
+        k = np.arange(n_a)
+        raw = q[(k[:, None] - k[None, :]) % n_a]
+    else:
+        raise ValueError("angular must be 'ordinates' or 'p0'")
     c = raw @ w                      # row integrals; equal for all rows (circulant)
     return raw / c[:, None]

@@ -45,17 +45,20 @@ FACE_NORMALS = np.array([[-1.0, 0.0], [1.0, 0.0], [0.0, -1.0], [0.0, 1.0]])
 
 
 class LocalDisc:
-    """Discretization data of one element type: Q_p in space, N_a ordinates."""
+    """Discretization data of one element type: Q_p in space, N_a angular
+    cells (discrete ordinates at the centres, or P0 elements: angular ==
+    "p0")."""
 
-    def __init__(self, p, n_a, g=0.0):
+    def __init__(self, p, n_a, g=0.0, angular="ordinates"):
         if p < 1:
             raise ValueError("p must be >= 1")
         self.p, self.n_a, self.g = int(p), int(n_a), float(g)
+        self.angular = angular
         self.q = self.p + 1
         self.xi, self.omega = lgl_nodes_weights(self.p)
         self.D = lagrange_diff_matrix(self.xi)
-        self.theta, self.w_ang, self.s = ordinates(self.n_a)
-        self.P = phase_matrix(self.n_a, self.g)
+        self.theta, self.w_ang, self.s = ordinates(self.n_a, angular)
+        self.P = phase_matrix(self.n_a, self.g, angular)
         q = self.q
         self.nn = q * q
         self.n = self.nn * self.n_a

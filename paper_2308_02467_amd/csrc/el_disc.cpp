@@ -66,6 +66,7 @@ bool build_disc(const el_disc& d, DiscHost& o, std::string& err) {
   }
   if (d.scatter != EL_SCATTER_ISO && d.scatter != EL_SCATTER_HG) { err = "bad scatter kind"; return false; }
   if (d.scatter == EL_SCATTER_HG && !(d.g_hg >= 0.0 && d.g_hg < 1.0)) { err = "g_hg must be in [0,1)"; return false; }
+  if (d.angular != EL_ANG_ORDINATES && d.angular != EL_ANG_P0) { err = "bad angular discretization"; return false; }
   o.p = d.p; o.q = d.p + 1; o.n_a = d.n_a; o.nn = o.q * o.q; o.n = o.nn * o.n_a; o.m = 2 * o.q * o.n_a;
   o.scatter = d.scatter; o.g = d.scatter == EL_SCATTER_HG ? d.g_hg : 0.0;
   const int q = o.q, p = o.p, na = o.n_a, nn = o.nn;
@@ -83,27 +84,64 @@ bool build_disc(const el_disc& d, DiscHost& o, std::string& err) {
   o.W.assign(nn, 0.0);
   for (int b = 0; b < q; ++b)
     for (int a = 0; a < q; ++a) o.W[b * q + a] = o.omega[a] * o.omega[b];
-  // ordinates at the centres of the uniform angular cells
+  // directions of the uniform angular cells: the centre direction
+  // (ordinates), or its average over the cell (P0 elements), which is the
+  // centre direction times sin(wa/2)/(wa/2)
   const double wa = 2.0 * M_PI / na;
+  const double avg = d.angular == EL_ANG_P0 ? std::sin(0.5 * wa) / (0.5 * wa) : 1.0;
   o.sx.resize(na); o.sy.resize(na);
   for (int k = 0; k < na; ++k) {
     double th = (k + 0.5) * wa;
-    o.sx[k] = std::cos(th);
-    o.sy[k] = std::sin(th);
+    o.sx[k] = avg * std::cos(th);
+    o.sy[k] = avg * std::sin(th);
   }
-  // Q[k][k'] = P[k][k'] w_k', rows normalized to sum 1
+  // Q[k][k'] = P[k][k'] w_k', rows normalized to sum 1.  The kernel depends
+  // on k - k' only: at the centre angle difference (ordinates), or averaged
+  // over pairs of cells (P0): the average of p(d wa + x - y) over x, y in
+  // [0, wa] is the integral of p(d wa + u) against the triangle
+  // (wa - |u|) / wa^2 on [-wa, wa] (Gauss-Legendre on each half).
+  const bool hg = o.scatter == EL_SCATTER_HG && o.g != 0.0;
+  auto kern = [&](double ang) {
+    const double g = o.g;
+    return (1.0 - g * g) / std::pow(1.0 + g * g - 2.0 * g * std::cos(ang), 1.5);
+  };
+  std::vector<double> qd(na, 1.0);
+  if (hg) {
+    // Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n)
+    const int ng = 48;
+    std::vector<double> gx(ng), gw(ng);
+    for (int i = 0; i < ng; ++i) {
+      double x = std::cos(M_PI * (i + 0.75) / (ng + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int k = 1; k < ng; ++k) { double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0); p0 = p1; p1 = p2; }
+        const double dp = ng * (x * p1 - p0) / (x * x - 1.0);
+        const double dx = p1 / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      double p0 = 1.0, p1 = x;
+      for (int k = 1; k < ng; ++k) { double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0); p0 = p1; p1 = p2; }
+      const double dp = ng * (x * p1 - p0) / (x * x - 1.0);
+      gx[i] = x;
+      gw[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    for (int dd = 0; dd < na; ++dd) {
+      if (d.angular != EL_ANG_P0) { qd[dd] = kern(dd * wa); continue; }
+      double acc = 0.0;
+      for (int i = 0; i < ng; ++i) {
+        const double u = 0.5 * wa * (gx[i] + 1.0);   // [0, wa]
+        const double tri = (wa - u) / (wa * wa);
+        acc += 0.5 * wa * gw[i] * tri * (kern(dd * wa + u) + kern(dd * wa - u));
+      }
+      qd[dd] = acc;
+    }
+  }
   o.Q.assign(na * na, 0.0);
   for (int k = 0; k < na; ++k) {
     double rs = 0.0;
     for (int kp = 0; kp < na; ++kp) {
-      double v;
-      if (o.scatter == EL_SCATTER_ISO || o.g == 0.0) {
-        v = 1.0;
-      } else {
-        double c = std::cos((k - kp) * wa);
-        double g = o.g;
-        v = (1.0 - g * g) / std::pow(1.0 + g * g - 2.0 * g * c, 1.5);
-      }
+      const double v = qd[((k - kp) % na + na) % na];
       o.Q[k * na + kp] = v;
       rs += v;
     }

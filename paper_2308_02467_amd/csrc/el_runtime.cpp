@@ -23,9 +23,9 @@ el_status hip_check(el_ctx* ctx, hipError_t e, const char* what) {
 }
 
 static std::string disc_key(const el_disc& d) {
-  char buf[96];
-  std::snprintf(buf, sizeof buf, "%d/%d/%d/%.17g", d.p, d.n_a, d.scatter,
-                d.scatter == EL_SCATTER_HG ? d.g_hg : 0.0);
+  char buf[112];
+  std::snprintf(buf, sizeof buf, "%d/%d/%d/%.17g/%d", d.p, d.n_a, d.scatter,
+                d.scatter == EL_SCATTER_HG ? d.g_hg : 0.0, d.angular);
   return buf;
 }
 
@@ -174,6 +174,16 @@ el_status el_index_tables(el_disc d, int32_t* in_rows_host, int32_t* out_rows_ho
   if (!build_disc(d, h, err)) return EL_ERR_ARG;
   if (in_rows_host) std::memcpy(in_rows_host, h.in_row.data(), h.m * sizeof(int32_t));
   if (out_rows_host) std::memcpy(out_rows_host, h.out_row.data(), h.m * sizeof(int32_t));
+  return EL_OK;
+}
+
+el_status el_angular_tables(el_disc d, double* s_host, double* Q_host) {
+  DiscHost h;
+  std::string err;
+  if (!build_disc(d, h, err)) return EL_ERR_ARG;
+  if (s_host)
+    for (int k = 0; k < h.n_a; ++k) { s_host[2 * k] = h.sx[k]; s_host[2 * k + 1] = h.sy[k]; }
+  if (Q_host) std::memcpy(Q_host, h.Q.data(), sizeof(double) * h.n_a * h.n_a);
   return EL_OK;
 }
 

@@ -28,6 +28,8 @@ EL_F64 = 0
 EL_BF16 = 1
 EL_F32 = 2
 EL_F16 = 3
+EL_ANG_ORDINATES = 0
+EL_ANG_P0 = 1
 
 _ERRNAMES = {EL_ERR_ARG: "EL_ERR_ARG", EL_ERR_HIP: "EL_ERR_HIP", EL_ERR_SINGULAR: "EL_ERR_SINGULAR",
              EL_ERR_NONFINITE: "EL_ERR_NONFINITE", EL_ERR_NOMEM: "EL_ERR_NOMEM"}
@@ -40,7 +42,8 @@ class ElError(RuntimeError):
 
 
 class el_disc(ctypes.Structure):
-    _fields_ = [("p", ctypes.c_int), ("n_a", ctypes.c_int), ("scatter", ctypes.c_int), ("g_hg", ctypes.c_double)]
+    _fields_ = [("p", ctypes.c_int), ("n_a", ctypes.c_int), ("scatter", ctypes.c_int), ("g_hg", ctypes.c_double),
+                ("angular", ctypes.c_int)]
 
 
 class el_mesh(ctypes.Structure):
@@ -80,6 +83,7 @@ _SIGS = {
                       ctypes.POINTER(ctypes.c_int64)],
     "el_lgl": [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "el_index_tables": [el_disc, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "el_angular_tables": [el_disc, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "el_trace_size": [el_disc, el_mesh, ctypes.POINTER(ctypes.c_int64)],
     "el_element_dofs": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_void_p],
     "el_local_solve": [ctypes.c_void_p, el_disc, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -138,8 +142,10 @@ def exported_symbols():
     return list(_SIGS)
 
 
-def disc(p, n_a, g_hg=0.0):
-    return el_disc(int(p), int(n_a), EL_SCATTER_HG if g_hg else EL_SCATTER_ISO, float(g_hg))
+def disc(p, n_a, g_hg=0.0, angular=None):
+    """angular: EL_ANG_ORDINATES (default) or EL_ANG_P0."""
+    return el_disc(int(p), int(n_a), EL_SCATTER_HG if g_hg else EL_SCATTER_ISO, float(g_hg),
+                   EL_ANG_ORDINATES if angular is None else int(angular))
 
 
 def mesh(n_x, n_y, h, x0=0.0, y0=0.0):
@@ -162,6 +168,18 @@ def lgl(p):
     if st != EL_OK:
         raise ElError(st, "el_lgl")
     return np.array(xi[:]), np.array(w[:])
+
+
+def angular_tables(d):
+    """(s [n_a, 2], Q [n_a, n_a]) of the discretization, from the host tables."""
+    import numpy as np
+    na = int(d.n_a)
+    sb = (ctypes.c_double * (2 * na))()
+    qb = (ctypes.c_double * (na * na))()
+    st = lib().el_angular_tables(d, sb, qb)
+    if st != EL_OK:
+        raise ElError(st, "el_angular_tables")
+    return np.array(sb).reshape(na, 2), np.array(qb).reshape(na, na)
 
 
 def index_tables(d):

@@ -129,9 +129,9 @@ def test_recover_operator_dtypes(ctx, dtype):
     assert rel_err(mean2.cpu().numpy(), orecover.recover(Mr, ind, t)) <= 1e-13
 
 
-def _gpu_pipeline(ctx, p, n_a, g, nx, ny, hh, kap, sig, g_side, tol=1e-12, outputs=True):
+def _gpu_pipeline(ctx, p, n_a, g, nx, ny, hh, kap, sig, g_side, tol=1e-12, outputs=True, angular=None):
     from paper_2308_02467_amd import el
-    d, ms = el.disc(p, n_a, g), el.mesh(nx, ny, 1.0 / max(nx, ny))
+    d, ms = el.disc(p, n_a, g, angular), el.mesh(nx, ny, 1.0 / max(nx, ny))
     nn, n, m = el.disc_sizes(d)
     E = nx * ny
     i2o = torch.empty((E, m, m), dtype=torch.float64, device=DEV)
@@ -186,6 +186,23 @@ def test_hg_pipeline_parity(ctx):
     gpu, rep, st = _gpu_pipeline(ctx, p, n_a, g, nx, nx, hh, kap, sig, gs)
     for k in ("t", "u", "mean"):
         assert rel_err(gpu[k], ref[k]) <= 1e-10, k
+
+
+@pytest.mark.parametrize("g", [0.0, 0.85])
+def test_p0_angular_pipeline_parity(ctx, g):
+    """P0 angular elements (cell-averaged directions and phase kernel): local
+    operators, skeleton solution and recovery against the oracle's P0 form."""
+    from paper_2308_02467_amd import el
+    p, n_a, nx = 3, 12, 4
+    _, oms, hh, kap, sig = mesh_problem(p, n_a, nx, g=g)
+    od = LocalDisc(p, n_a, g, "p0")
+    gs = inputs.left_inflow(n_a)
+    ref = oracle_pipeline(od, oms, hh, kap, sig, gs)
+    gpu, rep, st = _gpu_pipeline(ctx, p, n_a, g, nx, nx, hh, kap, sig, gs, angular=el.EL_ANG_P0)
+    for k in ("in2out", "in2sol", "in2mean", "t", "u", "mean"):
+        assert rel_err(gpu[k], ref[k]) <= 1e-10, k
+    # and the form matters: the ordinates differ from it
+    assert rel_err(gpu["in2out"], local_solve_batch(LocalDisc(p, n_a, g), hh, kap, sig)[0]) > 1e-4
 
 
 def test_full_size_32x32_sampled_and_energy(ctx):
