@@ -394,9 +394,10 @@ def cloud_main(args):
 
     # training elements: random elements of independently seeded fields
     rng = np.random.default_rng(7)
-    per = max(1, args.cloud_train_samples // 4)
+    n_fields = max(4, -(-args.cloud_train_samples // E))   # enough fields to draw without repeats
+    per = max(1, args.cloud_train_samples // n_fields)
     hs, ks, ss = [], [], []
-    for f in range(4):
+    for f in range(n_fields):
         kf, sf = inputs.lognormal_cloud(X, Y, seed=3000 + f)
         sel = rng.choice(E, size=per, replace=False)
         hs.append(np.full(per, h)); ks.append(kf[sel]); ss.append(sf[sel])
@@ -520,7 +521,7 @@ def cloud_main(args):
         "plain_step_ms": ref_local_ms + plain_gmres_ms,
         "plain": {"local_solve_ms": ref_local_ms, "gmres_ms": plain_gmres_ms, "gmres": rep_pl[0],
                   "mean_intensity_rel_l2_vs_reference": (d2p / r2p) ** 0.5,
-                  "note": "FP32 + refinement local solve (the FP64 factorization of n = 1568 does not fit one "
+                  "note": f"FP32 + refinement local solve (the FP64 factorization of n = {n} does not fit one "
                           "workgroup), float32 operators, GMRES at the learned step's tolerance"},
         "speedup_learned_vs_plain": (ref_local_ms + plain_gmres_ms) / ms_step,
     }
