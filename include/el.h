@@ -157,13 +157,19 @@ el_status el_element_dofs(el_ctx* ctx, el_disc d, el_mesh mesh, int32_t* in_dofs
  *   in2out [E][m][m], in2sol [E][n][m], in2mean [E][nn][m]   (NULL = skip),
  * and for EL_FP32_IR the final relative residual per element rel_resid [E]
  * (max over columns of ||R||_inf / ||B_hat col||_inf; NULL = skip).
+ * Volume source (Alg. 1 with f != 0): with src [E][n_a][nn] (nodal values
+ * of f per ordinate; NULL = none) one more right-hand side (h/2) W f is
+ * solved with the same factorization, giving f_u = A^{-1} (h/2) W f:
+ *   src2sol [E][n] = f_u, src2out [E][m] = its outflow rows (f_hat_u),
+ *   src2mean [E][nn] = its ordinate average            (NULL = skip).
  * Errors: EL_ERR_ARG (bad sizes / disc), EL_ERR_NONFINITE (non-finite or
  * negative coefficient; element named), EL_ERR_SINGULAR (zero pivot; element
  * named).  Synchronizes the stream to read the status flags. */
 el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E,
                          const double* h, const double* kappa, const double* sigma,
                          double* in2out, double* in2sol, double* in2mean,
-                         double* rel_resid);
+                         double* rel_resid, const double* src, double* src2out,
+                         double* src2sol, double* src2mean);
 
 /* ---- skeleton system (eq. hdg_global_mat) --------------------------------- */
 /* Right-hand side b [n_trace]: per-side boundary radiance g_side (host
@@ -171,6 +177,10 @@ el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E,
  * (nodal interpolation = the L2 projection P_M g with collocated LGL,
  * Sec. 2.2.2), 0 elsewhere. */
 el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_side_host, double* b);
+
+/* With a volume source: b[outflow DOFs of e] += src2out[e] (the f_hat_u of
+ * el_local_solve, [E][m]; every outflow DOF belongs to one element). */
+el_status el_trace_add_source(el_ctx* ctx, el_disc d, el_mesh mesh, const double* src2out, double* b);
 
 /* y = (I - P) x on one mesh: (P x)[out dofs of e] = in2out_e x[in dofs of e],
  * P = 0 on domain-inflow rows.  in2out is [E][m][m] FP64 (op_dtype EL_F64),
@@ -200,14 +210,16 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
                          const el_gmres_opts* opts_host, el_gmres_report* rep_host);
 
 /* ---- recovery (Alg. 1 step 4, eq. hdg_local_mat_sol, eq. ang_ave) ----------
- * u [E][n] = in2sol_e t[in dofs of e] (NULL = skip) and the mean intensity
+ * u [E][n] = in2sol_e t[in dofs of e] (+ src2sol [E][n], the f_u of a volume
+ * source; NULL = none) (u NULL = skip) and the mean intensity
  * mean [E][nn] = (1/N_a) sum_k u (NULL = skip).  in2sol is [E][n][m] in
  * op_dtype (EL_F64, EL_F32, EL_F16, EL_BF16). */
 el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
-                     const double* trace, double* u, double* mean);
-/* Mean intensity directly from in2mean [E][nn][m] in op_dtype. */
+                     const double* trace, double* u, double* mean, const double* src2sol);
+/* Mean intensity directly from in2mean [E][nn][m] in op_dtype (+ src2mean
+ * [E][nn], the ordinate average of f_u; NULL = none). */
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean,
-                          int op_dtype, const double* trace, double* mean);
+                          int op_dtype, const double* trace, double* mean, const double* src2mean);
 
 /* Forms of the volume operator that goes with in2out: the full in2sol
  * [n][m], or its ordinate average in2mean [nn][m] (the mean-intensity map,

@@ -94,9 +94,12 @@ el_status ensure_ws(el_ctx* ctx, Workspace& ws, size_t bytes);
 // launchers implemented in the .hip files
 el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,
                              const double* h, const double* kappa, const double* sigma,
-                             double* in2out, double* in2sol, double* in2mean, double* rel_resid);
+                             double* in2out, double* in2sol, double* in2mean, double* rel_resid,
+                             const double* src, double* s2out, double* s2sol, double* s2mean);
 // whether the FP64 factorization of this discretization fits one workgroup
 bool local_fp64_fits(el_ctx* ctx, el_ctx::DiscEntry* de);
+el_status launch_trace_add_source(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const double* s2out,
+                                  double* b);
 el_status launch_trace_rhs(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
                            const double* g_side_host, double* b);
 el_status launch_trace_matvec(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
@@ -108,9 +111,10 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
                           double* const* trace, const el_gmres_opts& opts, el_gmres_report* rep);
 el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
                          const void* in2sol, int op_dtype, const double* trace,
-                         double* u, double* mean);
+                         double* u, double* mean, const double* src2sol);
 el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh,
-                              const void* in2mean, int op_dtype, const double* trace, double* mean);
+                              const void* in2mean, int op_dtype, const double* trace, double* mean,
+                              const double* src2mean);
 el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* kappa,
                           const void* in2out, const void* in2vol, int form, int op_dtype, const uint8_t* mask,
                           void* out, int out_dtype);

@@ -206,7 +206,8 @@ el_status el_element_dofs(el_ctx* ctx, el_disc d, el_mesh mesh, int32_t* in_dofs
 
 el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E, const double* h,
                          const double* kappa, const double* sigma, double* in2out, double* in2sol,
-                         double* in2mean, double* rel_resid) {
+                         double* in2mean, double* rel_resid, const double* src, double* src2out,
+                         double* src2sol, double* src2mean) {
   if (!ctx) return EL_ERR_ARG;
   if (E < 0) return set_error(ctx, EL_ERR_ARG, "el_local_solve: E < 0");
   if (precision != EL_FP64 && precision != EL_FP32_IR)
@@ -217,7 +218,10 @@ el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E, const
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
-  return launch_local_solve(ctx, de, precision, E, h, kappa, sigma, in2out, in2sol, in2mean, rel_resid);
+  if (!src && (src2out || src2sol || src2mean))
+    return set_error(ctx, EL_ERR_ARG, "el_local_solve: source outputs without a source");
+  return launch_local_solve(ctx, de, precision, E, h, kappa, sigma, in2out, in2sol, in2mean, rel_resid, src,
+                            src2out, src2sol, src2mean);
 }
 
 el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_side_host, double* b) {
@@ -228,6 +232,16 @@ el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_sid
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
   return launch_trace_rhs(ctx, de, mesh, g_side_host, b);
+}
+
+el_status el_trace_add_source(el_ctx* ctx, el_disc d, el_mesh mesh, const double* src2out, double* b) {
+  if (!ctx) return EL_ERR_ARG;
+  if (!mesh_ok(mesh) || !src2out || !b) return set_error(ctx, EL_ERR_ARG, "el_trace_add_source: bad argument");
+  hipSetDevice(ctx->device);
+  el_ctx::DiscEntry* de;
+  el_status st = get_disc(ctx, d, &de);
+  if (st) return st;
+  return launch_trace_add_source(ctx, de, mesh, src2out, b);
 }
 
 el_status el_trace_matvec(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2out, int op_dtype,
@@ -268,7 +282,7 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
 }
 
 el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, int op_dtype,
-                     const double* trace, double* u, double* mean) {
+                     const double* trace, double* u, double* mean, const double* src2sol) {
   if (!ctx) return EL_ERR_ARG;
   if (!mesh_ok(mesh) || !in2sol || !trace || !op_dtype_ok(op_dtype))
     return set_error(ctx, EL_ERR_ARG, "el_recover: bad argument");
@@ -277,11 +291,11 @@ el_status el_recover(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2sol, i
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
-  return launch_recover(ctx, de, mesh, in2sol, op_dtype, trace, u, mean);
+  return launch_recover(ctx, de, mesh, in2sol, op_dtype, trace, u, mean, src2sol);
 }
 
 el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2mean, int op_dtype,
-                          const double* trace, double* mean) {
+                          const double* trace, double* mean, const double* src2mean) {
   if (!ctx) return EL_ERR_ARG;
   if (!mesh_ok(mesh) || !in2mean || !trace || !mean || !op_dtype_ok(op_dtype))
     return set_error(ctx, EL_ERR_ARG, "el_recover_mean: bad argument");
@@ -289,7 +303,7 @@ el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2m
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
   if (st) return st;
-  return launch_recover_mean(ctx, de, mesh, in2mean, op_dtype, trace, mean);
+  return launch_recover_mean(ctx, de, mesh, in2mean, op_dtype, trace, mean, src2mean);
 }
 
 el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa, void* in2out,

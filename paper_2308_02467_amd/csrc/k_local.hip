@@ -90,6 +90,10 @@ struct LuArgs {
   _Float16* h_i2s;        // float16 in2sol [E][n][m]
   _Float16* h_i2m;        // float16 in2mean [E][nn][m]
   uint16_t* pairs;        // bfloat16 (in2out, in2sol) [E][m*m + n*m] or (in2out, in2mean) [E][m*m + nn*m]
+  const double* src;      // volume source f at the nodes [E][n_a][nn], or null: one more right-hand side
+  double* s2out;          // its outflow response f_hat_u [E][m]
+  double* s2sol;          // its volume response f_u [E][n]
+  double* s2mean;         // ordinate average of f_u [E][nn]
   int pairs_form;         // EL_FORM_IN2SOL or EL_FORM_IN2MEAN
   const int32_t* emap;    // batch slot -> element index (inputs and outputs), or null
   T* fac;        // [slots][npan][npad][NB]
@@ -554,7 +558,7 @@ __host__ __device__ inline size_t lds_base_bytes(int npad, int nn) {
 template <typename T, int XC>
 __device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, const double* tau_e,
                                    const double* tau_s, const double* xg, double* xs, unsigned long long* colmax,
-                                   int npad, int P0, int tid) {
+                                   int npad, int P0, int tid, int64_t e, double he) {
   const DiscDev& dv = a.dv;
   const int n = dv.n, m = dv.m, nn = dv.nn;
   for (int c0 = 0; c0 < NB; c0 += XC) {
@@ -610,7 +614,8 @@ __device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, 
 #pragma unroll
         for (int c = 0; c < XC; ++c) {
           const int col = P0 + c0 + c;
-          const double rv = (col < m && q == dv.in_row[col]) ? dv.in_val[col] : 0.0;
+          const double rv = col < m ? (q == dv.in_row[col] ? dv.in_val[col] : 0.0)
+                                    : (col == m && a.src ? 0.5 * he * dv.W[nd] * a.src[e * n + q] : 0.0);
           acc[c] = rv - (acc[c] + wd * xs[q * XC + c] - ws * sc[c]);
         }
       }
@@ -645,6 +650,7 @@ __host__ __device__ inline size_t xbuf_doubles_per_slot(int npad, bool ir) {
 template <typename T, int MAXT>
 __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   typedef typename Acc<T>::type A4;
+  __shared__ unsigned long long src_max;   // bits of max |source column|
   extern __shared__ __align__(16) unsigned char smem[];
   const DiscDev& dv = a.dv;
   const int npad = a.npad, mpad = a.mpad, n = dv.n, m = dv.m, nn = dv.nn;
@@ -684,12 +690,25 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     __syncthreads();   // every thread has read the previous element's flags
     if (tid == 0) { sflag[0] = 0; sflag[1] = 0; }
     __syncthreads();
+    if (tid == 0) src_max = 0ull;
     for (int i = tid; i < nn; i += kThreads) {
       double kap = a.kappa[e * nn + i], sig = a.sigma[e * nn + i];
       bool ok = isfinite(kap) && isfinite(sig) && kap >= 0.0 && sig >= 0.0 && isfinite(he) && he > 0.0;
       if (!ok) sflag[1] = 1;
       tau_e[i] = 0.5 * he * (kap + sig);
       tau_s[i] = 0.5 * he * sig;
+    }
+    __syncthreads();
+    if (a.src) {
+      // largest entry of the source column (scale of its refinement residual)
+      unsigned long long mx = 0ull;
+      for (int i = tid; i < n; i += kThreads) {
+        const double f = a.src[e * n + i];
+        if (!isfinite(f)) sflag[1] = 1;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(0.5 * he * dv.W[i % nn] * f));
+        mx = bits > mx ? bits : mx;
+      }
+      atomicMax(&src_max, mx);
     }
     for (int r = tid; r < npad; r += kThreads) perm[r] = r;
     __syncthreads();
@@ -871,24 +890,28 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     double elem_res = 0.0;
     for (int P0 = 0; P0 < mpad;) {
       const bool two = P0 + NB < mpad;
+      // column col < m: -B_hat (one nonzero); column m: the source (h/2) W f
+      auto rhs = [&](int r, int col) {
+        const int q = perm[r];
+        if (col < m) return q == dv.in_row[col] ? (T)dv.in_val[col] : T(0);
+        if (col == m && a.src && q < n) {
+          const int nd = q % nn;
+          return (T)(0.5 * he * dv.W[nd] * a.src[e * n + q]);
+        }
+        return T(0);
+      };
       for (int idx = tid; idx < npad * NB; idx += kThreads) {
         int r = idx >> 4, c = idx & 15;
-        int col = P0 + c;
-        T v = T(0);
-        if (col < m && perm[r] == dv.in_row[col]) v = (T)dv.in_val[col];
-        pan[r * LDP + c] = v;
-        if (two) {
-          col += NB;
-          v = T(0);
-          if (col < m && perm[r] == dv.in_row[col]) v = (T)dv.in_val[col];
-          rs[r * NB + c] = v;
-        }
+        pan[r * LDP + c] = rhs(r, P0 + c);
+        if (two) rs[r * NB + c] = rhs(r, P0 + NB + c);
       }
       // first nonzero logical row of the panel(s)
       if (tid == 0) {
         int mn = npad;
-        for (int c = 0; c < (two ? 2 * NB : NB); ++c)
+        for (int c = 0; c < (two ? 2 * NB : NB); ++c) {
           if (P0 + c < m) mn = min(mn, pinv[dv.in_row[P0 + c]]);
+          else if (P0 + c == m && a.src) mn = 0;   // dense column
+        }
         sflag[1] = (mn / NB) * NB;
       }
       __threadfence_block();
@@ -906,14 +929,17 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         __threadfence_block();
         __syncthreads();
         auto residual = [&](const double* x, unsigned long long* cm, int p0) {
-          if (a.ir_cols == 8) ir_residual<T, 8>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid);
-          else if (a.ir_cols == 4) ir_residual<T, 4>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid);
-          else ir_residual<T, 2>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid);
+          if (a.ir_cols == 8) ir_residual<T, 8>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
+          else if (a.ir_cols == 4) ir_residual<T, 4>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
+          else ir_residual<T, 2>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
         };
         auto worst_of = [&](const unsigned long long* cm, int p0) {
           double w = 0.0;
-          for (int c = 0; c < NB; ++c)
-            if (p0 + c < m) w = fmax(w, __longlong_as_double((long long)cm[c]) / dv.in_val[p0 + c]);
+          for (int c = 0; c < NB; ++c) {
+            const double r = __longlong_as_double((long long)cm[c]);
+            if (p0 + c < m) w = fmax(w, r / dv.in_val[p0 + c]);
+            else if (p0 + c == m && a.src) w = fmax(w, r / fmax(__longlong_as_double((long long)src_max), 1e-300));
+          }
           return w;
         };
         for (int it = 0;; ++it) {
@@ -985,6 +1011,21 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
             }
           }
         }
+        if (a.src && P0 <= m && m < P0 + NB) {
+          // the source column: f_u, its outflow rows, its ordinate average
+          const int c = m - P0;
+          auto val = [&](int r) { return ir ? xsol[r * NB + c] : (double)pan[r * LDP + c]; };
+          if (a.s2sol)
+            for (int r = tid; r < n; r += kThreads) a.s2sol[(int64_t)e * n + r] = val(r);
+          if (a.s2out)
+            for (int r = tid; r < m; r += kThreads) a.s2out[(int64_t)e * m + r] = val(dv.out_row[r]);
+          if (a.s2mean)
+            for (int r = tid; r < nn; r += kThreads) {
+              double acc = 0.0;
+              for (int k = 0; k < dv.n_a; ++k) acc += val(k * nn + r);
+              a.s2mean[(int64_t)e * nn + r] = acc / dv.n_a;
+            }
+        }
         if (a.in2mean || a.b_i2m || a.f_i2m || a.h_i2m || pairs_mean) {
           const double s = 1.0 / dv.n_a;
           for (int idx = tid; idx < nn * NB; idx += kThreads) {
@@ -1048,6 +1089,10 @@ struct LocalOut {
   uint16_t* pairs = nullptr;
   int pairs_form = EL_FORM_IN2SOL;
   const int32_t* emap = nullptr;
+  const double* src = nullptr;
+  double* s2out = nullptr;
+  double* s2sol = nullptr;
+  double* s2mean = nullptr;
 };
 
 template <typename T>
@@ -1055,7 +1100,8 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
                       const double* kappa, const double* sigma, const LocalOut& out, double* rel_resid) {
   const DiscHost& dh = de->host;
   const int npad = (dh.n + NB - 1) / NB * NB;
-  const int mpad = (dh.m + NB - 1) / NB * NB;
+  // the source, if any, is right-hand side column m
+  const int mpad = (dh.m + (out.src ? 1 : 0) + NB - 1) / NB * NB;
   if (rel_resid) {
     hipLaunchKernelGGL(k_fill_double, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, ctx->stream, rel_resid, E, 0.0);
   }
@@ -1096,6 +1142,7 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   args.f_i2o = out.f_i2o; args.f_i2s = out.f_i2s;
   args.b_i2m = out.b_i2m; args.f_i2m = out.f_i2m; args.pairs_form = out.pairs_form;
   args.h_i2o = out.h_i2o; args.h_i2s = out.h_i2s; args.h_i2m = out.h_i2m;
+  args.src = out.src; args.s2out = out.s2out; args.s2sol = out.s2sol; args.s2mean = out.s2mean;
   char* base = reinterpret_cast<char*>(ctx->ws_local.ptr);
   args.fac = reinterpret_cast<T*>(base);
   args.inv = reinterpret_cast<T*>(base + fac_bytes);
@@ -1167,9 +1214,11 @@ bool local_fp64_fits(el_ctx* ctx, el_ctx::DiscEntry* de) {
 
 el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,
                              const double* h, const double* kappa, const double* sigma,
-                             double* in2out, double* in2sol, double* in2mean, double* rel_resid) {
+                             double* in2out, double* in2sol, double* in2mean, double* rel_resid,
+                             const double* src, double* s2out, double* s2sol, double* s2mean) {
   LocalOut o;
   o.in2out = in2out; o.in2sol = in2sol; o.in2mean = in2mean;
+  o.src = src; o.s2out = s2out; o.s2sol = s2sol; o.s2mean = s2mean;
   return run_local(ctx, de, precision, E, h, kappa, sigma, o, rel_resid);
 }
 

@@ -20,10 +20,12 @@ constexpr int kThreads = 256;
 // rows = number of operator rows (n for in2sol, nn for in2mean);
 // mode 0: u (and optional mean over ordinates) from in2sol;
 // mode 1: mean directly from in2mean.
+// add: the element's source response [E][rows] added to the rows, or null.
 template <typename OpT>
 __global__ void __launch_bounds__(kThreads) k_recover(DiscDev dv, MeshDev ms, const OpT* __restrict__ op,
                                                        int rows, int mode, const double* __restrict__ t,
-                                                       double* __restrict__ u, double* __restrict__ mean) {
+                                                       double* __restrict__ u, double* __restrict__ mean,
+                                                       const double* __restrict__ add) {
   extern __shared__ double sm[];
   double* tin = sm;             // [m]
   double* ub = sm + dv.m;       // [rows]
@@ -43,7 +45,7 @@ __global__ void __launch_bounds__(kThreads) k_recover(DiscDev dv, MeshDev ms, co
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
     acc += __shfl_xor(acc, 4);
-    if (gl == 0) ub[r] = acc;
+    if (gl == 0) ub[r] = add ? acc + add[(size_t)e * rows + r] : acc;
   }
   __syncthreads();
   if (mode == 1) {
@@ -156,7 +158,7 @@ el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const d
 }
 
 el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const void* in2sol,
-                         int op_dtype, const double* trace, double* u, double* mean) {
+                         int op_dtype, const double* trace, double* u, double* mean, const double* src2sol) {
   MeshDev ms{mesh.n_x, mesh.n_y, (mesh.n_x + 1) * mesh.n_y};
   const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
   const DiscHost& dh = de->host;
@@ -164,13 +166,13 @@ el_status launch_recover(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh
   with_op_type(op_dtype, [&](auto tag) {
     using T = decltype(tag);
     hipLaunchKernelGGL(k_recover<T>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const T*>(in2sol), dh.n, 0, trace, u, mean);
+                       reinterpret_cast<const T*>(in2sol), dh.n, 0, trace, u, mean, src2sol);
   });
   return hip_check(ctx, hipGetLastError(), "launch k_recover");
 }
 
 el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const void* in2mean,
-                              int op_dtype, const double* trace, double* mean) {
+                              int op_dtype, const double* trace, double* mean, const double* src2mean) {
   MeshDev ms{mesh.n_x, mesh.n_y, (mesh.n_x + 1) * mesh.n_y};
   const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
   const DiscHost& dh = de->host;
@@ -178,7 +180,7 @@ el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh&
   with_op_type(op_dtype, [&](auto tag) {
     using T = decltype(tag);
     hipLaunchKernelGGL(k_recover<T>, dim3((unsigned)E), dim3(kThreads), smem, ctx->stream, de->view, ms,
-                       reinterpret_cast<const T*>(in2mean), dh.nn, 1, trace, nullptr, mean);
+                       reinterpret_cast<const T*>(in2mean), dh.nn, 1, trace, nullptr, mean, src2mean);
   });
   return hip_check(ctx, hipGetLastError(), "launch k_recover(mean)");
 }

@@ -87,8 +87,10 @@ _SIGS = {
     "el_trace_size": [el_disc, el_mesh, ctypes.POINTER(ctypes.c_int64)],
     "el_element_dofs": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_void_p],
     "el_local_solve": [ctypes.c_void_p, el_disc, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "el_trace_rhs": [ctypes.c_void_p, el_disc, el_mesh, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
+    "el_trace_add_source": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_void_p],
     "el_trace_matvec": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_void_p],
     "el_tuning_report": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
@@ -97,9 +99,9 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(el_gmres_opts),
                        ctypes.POINTER(el_gmres_report)],
     "el_recover": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
-                   ctypes.c_void_p, ctypes.c_void_p],
+                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "el_recover_mean": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
-                        ctypes.c_void_p],
+                        ctypes.c_void_p, ctypes.c_void_p],
     "el_mean_l2": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                    ctypes.POINTER(ctypes.c_double)],
     "el_conserve": [ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -267,14 +269,19 @@ class Context:
 
     # -- local solve -----------------------------------------------------------
     def el_local_solve(self, d, h, kappa, sigma, precision=EL_FP64, in2out=None, in2sol=None, in2mean=None,
-                       rel_resid=None):
+                       rel_resid=None, src=None, src2out=None, src2sol=None, src2mean=None):
+        """src: nodal volume source [E][n_a][nn]; its responses f_hat_u
+        (src2out [E][m]), f_u (src2sol [E][n]) and their ordinate average
+        (src2mean [E][nn])."""
         nn, n, m = disc_sizes(d)
         E = h.numel()
         args = [_ptr(h, torch.float64, E, "h"), _ptr(kappa, torch.float64, E * nn, "kappa"),
                 _ptr(sigma, torch.float64, E * nn, "sigma"),
                 _ptr(in2out, torch.float64, E * m * m, "in2out"), _ptr(in2sol, torch.float64, E * n * m, "in2sol"),
                 _ptr(in2mean, torch.float64, E * nn * m, "in2mean"),
-                _ptr(rel_resid, torch.float64, E, "rel_resid")]
+                _ptr(rel_resid, torch.float64, E, "rel_resid"),
+                _ptr(src, torch.float64, E * n, "src"), _ptr(src2out, torch.float64, E * m, "src2out"),
+                _ptr(src2sol, torch.float64, E * n, "src2sol"), _ptr(src2mean, torch.float64, E * nn, "src2mean")]
         return self._check(lib().el_local_solve(self.h, d, int(precision), E, *args))
 
     def el_element_dofs(self, d, ms, in_dofs=None, out_dofs=None):
@@ -315,20 +322,28 @@ class Context:
                          reorth_passes=r.reorth_passes) for r in rep]
 
     # -- recovery ------------------------------------------------------------------
-    def el_recover(self, d, ms, in2sol, trace, u=None, mean=None):
+    def el_recover(self, d, ms, in2sol, trace, u=None, mean=None, src2sol=None):
         nn, n, _ = disc_sizes(d)
         E = ms.n_x * ms.n_y
         return self._check(lib().el_recover(self.h, d, ms, _ptr(in2sol, name="in2sol"), _op_dtype(in2sol),
                                             _ptr(trace, torch.float64, trace_size(d, ms), "trace"),
                                             _ptr(u, torch.float64, E * n, "u"),
-                                            _ptr(mean, torch.float64, E * nn, "mean")))
+                                            _ptr(mean, torch.float64, E * nn, "mean"),
+                                            _ptr(src2sol, torch.float64, E * n, "src2sol")))
 
-    def el_recover_mean(self, d, ms, in2mean, trace, mean):
+    def el_recover_mean(self, d, ms, in2mean, trace, mean, src2mean=None):
         nn, _, _ = disc_sizes(d)
         E = ms.n_x * ms.n_y
         return self._check(lib().el_recover_mean(self.h, d, ms, _ptr(in2mean, name="in2mean"), _op_dtype(in2mean),
                                                  _ptr(trace, torch.float64, trace_size(d, ms), "trace"),
-                                                 _ptr(mean, torch.float64, E * nn, "mean")))
+                                                 _ptr(mean, torch.float64, E * nn, "mean"),
+                                                 _ptr(src2mean, torch.float64, E * nn, "src2mean")))
+
+    def el_trace_add_source(self, d, ms, src2out, b):
+        _, _, m = disc_sizes(d)
+        E = ms.n_x * ms.n_y
+        return self._check(lib().el_trace_add_source(self.h, d, ms, _ptr(src2out, torch.float64, E * m, "src2out"),
+                                                     _ptr(b, torch.float64, trace_size(d, ms), "b")))
 
     def el_conserve(self, d, h, kappa, in2out, in2sol=None, mask=None, in2mean=None, out=None):
         """Energy-balance correction of in2out given in2sol or in2mean, in place

@@ -205,6 +205,69 @@ def test_p0_angular_pipeline_parity(ctx, g):
     assert rel_err(gpu["in2out"], local_solve_batch(LocalDisc(p, n_a, g), hh, kap, sig)[0]) > 1e-4
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_volume_source_pipeline_parity(ctx, precision):
+    """Alg. 1 with a volume source f: the source responses f_u and f_hat_u of
+    the local solve, the skeleton right-hand side with f_hat_u, the trace and
+    the recovered intensity against the oracle's source path."""
+    from paper_2308_02467_amd import el
+    p, n_a, g, nx = 3, 8, 0.5, 4
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, g=g)
+    E = nx * nx
+    X, Y = inputs.element_node_coords(nx, nx, oms.h, od.xi)
+    th = od.theta
+    f = (1.0 + 0.5 * np.sin(3 * X)[:, None, :] * np.cos(th)[None, :, None]
+         + 0.3 * Y[:, None, :] * np.sin(2 * th)[None, :, None])                # [E, n_a, nn]
+    gs = inputs.left_inflow(n_a)
+    i2o, i2s, _ = local_solve_batch(od, hh, kap, sig)
+    ind, outd = oms.element_dofs(od)
+    rhs = oms.boundary_vector_sides(od, gs)
+    fus, fhats = [], []
+    for e in range(E):
+        fu, fhat = od.source_solve(hh[e], kap[e], sig[e], f[e])
+        fus.append(fu)
+        fhats.append(fhat)
+        rhs[outd[e]] += fhat
+    fus, fhats = np.array(fus), np.array(fhats)
+    t_ref = otrace.solve_direct(i2o, ind, outd, rhs)
+    u_ref = np.einsum("enm,em->en", i2s, t_ref[ind]) + fus
+    mean_ref = orecover.mean_intensity(od, u_ref)
+
+    d, ms = el.disc(p, n_a, g), el.mesh(nx, nx, oms.h)
+    nn, n, m = el.disc_sizes(d)
+    prec = el.EL_FP64 if precision == "fp64" else el.EL_FP32_IR
+    o = torch.empty((E, m, m), dtype=torch.float64, device=DEV)
+    sv = torch.empty((E, n, m), dtype=torch.float64, device=DEV)
+    mv = torch.empty((E, nn, m), dtype=torch.float64, device=DEV)
+    s2out = torch.full((E, m), float("nan"), dtype=torch.float64, device=DEV)
+    s2sol = torch.full((E, n), float("nan"), dtype=torch.float64, device=DEV)
+    s2mean = torch.full((E, nn), float("nan"), dtype=torch.float64, device=DEV)
+    print(f"[el_local_solve] with source, {precision}", flush=True)
+    ctx.el_local_solve(d, T(hh), T(kap), T(sig), precision=prec, in2out=o, in2sol=sv, in2mean=mv, src=T(f),
+                       src2out=s2out, src2sol=s2sol, src2mean=s2mean)
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    assert rel_err(s2sol.cpu().numpy(), fus) <= tol
+    assert rel_err(s2out.cpu().numpy(), fhats) <= tol
+    assert rel_err(o.cpu().numpy(), i2o) <= tol
+    nt = el.trace_size(d, ms)
+    b = torch.empty(nt, dtype=torch.float64, device=DEV)
+    ctx.el_trace_rhs(d, ms, gs, b)
+    ctx.el_trace_add_source(d, ms, s2out, b)
+    assert rel_err(b.cpu().numpy(), rhs) <= tol
+    t = torch.empty(nt, dtype=torch.float64, device=DEV)
+    st, rep = ctx.el_trace_solve(d, [ms], [o], [b], [t], tol=1e-12, restart=30, max_iter=3000)
+    assert st == 0
+    u = torch.empty((E, n), dtype=torch.float64, device=DEV)
+    mean = torch.empty((E, nn), dtype=torch.float64, device=DEV)
+    mean2 = torch.empty((E, nn), dtype=torch.float64, device=DEV)
+    ctx.el_recover(d, ms, sv, t, u, mean, src2sol=s2sol)
+    ctx.el_recover_mean(d, ms, mv, t, mean2, src2mean=s2mean)
+    assert rel_err(t.cpu().numpy(), t_ref) <= tol
+    assert rel_err(u.cpu().numpy(), u_ref) <= tol
+    assert rel_err(mean.cpu().numpy(), mean_ref) <= tol
+    assert rel_err(mean2.cpu().numpy(), mean_ref) <= tol
+
+
 def test_full_size_32x32_sampled_and_energy(ctx):
     """The 32x32, p=6, N_a=16 Gaussian-cloud workload: sampled element
     operators vs the oracle, GMRES residual, global energy balance."""
