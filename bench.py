@@ -196,6 +196,18 @@ def main():
                               "flop_per_element": flop_el},
     }
 
+    # the same local solve with a volume source (one more right-hand side)
+    src = torch.ones((E, n), dtype=torch.float64, device=dev)
+    s2o = torch.empty((E, m), dtype=torch.float64, device=dev)
+    s2s = torch.empty((E, n), dtype=torch.float64, device=dev)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    ctx.el_local_solve(d, hh, kap, sig, in2out=i2o, in2sol=i2s, in2mean=i2m, src=src, src2out=s2o, src2sol=s2s)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain["local_solve_with_source_ms"] = e0.elapsed_time(e1)
+    del src, s2o, s2s
+
     # ---- FP32 LU + FP64 refinement (local solve only) -------------------------
     log("FP32 + refinement local solve")
     i2o_ir = torch.empty_like(i2o)
