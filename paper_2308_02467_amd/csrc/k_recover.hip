@@ -185,6 +185,28 @@ el_status launch_recover_mean(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh&
   return hip_check(ctx, hipGetLastError(), "launch k_recover(mean)");
 }
 
+// b[outflow DOF o of element e] += src2out[e][o] (each outflow DOF belongs to
+// exactly one element)
+__global__ void k_trace_add_source(DiscDev dv, MeshDev ms, int64_t E, const double* __restrict__ s2out,
+                                   double* __restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= E * dv.m) return;
+  const int64_t e = t / dv.m;
+  const int o = (int)(t - e * dv.m);
+  const int i = (int)(e % ms.n_x), j = (int)(e / ms.n_x);
+  const int F = face_of(ms, i, j, dv.out_f[o]);
+  b[(F * dv.n_a + dv.out_k[o]) * dv.q + dv.out_j[o]] += s2out[t];
+}
+
+el_status launch_trace_add_source(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const double* s2out,
+                                  double* b) {
+  MeshDev ms{mesh.n_x, mesh.n_y, (mesh.n_x + 1) * mesh.n_y};
+  const int64_t E = (int64_t)mesh.n_x * mesh.n_y;
+  hipLaunchKernelGGL(k_trace_add_source, dim3((unsigned)((E * de->host.m + 255) / 256)), dim3(256), 0, ctx->stream,
+                     de->view, ms, E, s2out, b);
+  return hip_check(ctx, hipGetLastError(), "launch k_trace_add_source");
+}
+
 el_status launch_mean_l2(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h, const double* a,
                          const double* ref, double* out_host) {
   const int nblk = 512;
