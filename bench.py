@@ -5,13 +5,16 @@ unit square, Q6 LGL (p = 6) x 16 discrete ordinates (n = 784 volume and
 m = 224 inflow DOFs per element), isotropic scattering, the smooth Gaussian
 cloud kappa = 0.01 + 0.5 G, sigma = 0.1 + 30 G (G a Gaussian bump of width
 0.2 at the centre), radiance 1 entering through the left side.  GMRES
-tolerance 1e-5 (restart 50): the plain FP64 solution is then within 1.3e-4
-relative L2 of the fully converged one (measured with --accuracy).
+tolerance 1e-5, restart 40, Krylov basis stored in FP32 (dot products, the
+solution and the restart residuals FP64; --gmres-basis float64 keeps it
+FP64): the plain FP64 solution is then within 1.3e-4 relative L2 of the
+fully converged one (measured with --accuracy).
 
 Steps (inputs resident in HBM before every timed region):
 * plain:   el_local_solve (FP64 LU) -> el_trace_rhs -> el_trace_solve -> el_recover
-* learned: el_infer (BF16 MFMA network, FP32 operator storage, plain fallback
-           outside the training box) -> el_conserve -> el_trace_rhs ->
+* learned: el_infer (BF16 MFMA network, FP32 outputs, plain fallback outside
+           the training box) -> el_conserve (energy-balance correction,
+           rounded once into FP16 operator storage) -> el_trace_rhs ->
            el_trace_solve -> el_recover
 The network (99-1024x4-225792, GELU) is first trained on pairs from the GPU
 local solver (not timed; reported).  value = elements per second of the whole
@@ -46,6 +49,8 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="elements per side")
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--gmres-basis", choices=("float64", "float32"), default="float32",
+                    help="storage of the Krylov basis (dot products and restart residuals stay FP64)")
     ap.add_argument("--accuracy", action="store_true",
                     help="GMRES tolerance sweep and operator-storage errors against a 1e-12 FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -87,6 +92,11 @@ def log(msg):
 MATVEC_SOURCES = ("paper_2308_02467_amd/csrc/trace_dev.h", "paper_2308_02467_amd/csrc/k_trace.hip")
 TRAFFIC_SUMMARY = {"float16": "profiles/k_matvec_f16_128x128_p6_na16_hbm_traffic.md"}
 MATVEC_KERNEL = {"float32": "k_matvec<float>", "float16": "k_matvec<_Float16>"}
+
+
+def gmres_basis(args):
+    import torch
+    return torch.float32 if args.gmres_basis == "float32" else torch.float64
 
 
 def matvec_source_hash():
@@ -166,7 +176,8 @@ def main():
         e[1].record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
         e[2].record(stream)
-        st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
+        st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000,
+                                     basis=gmres_basis(args))
         e[3].record(stream)
         ctx.el_recover(d, ms, i2s, t, u, mean)
         e[4].record(stream)
@@ -269,7 +280,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": workload, "elements": E, "p": p, "n_a": n_a, "gmres_tol": args.tol,
-                   "gmres_restart": args.restart},
+                   "gmres_restart": args.restart, "gmres_basis": args.gmres_basis},
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain": plain,
@@ -327,7 +338,7 @@ def batched_leg(args, ctx, el, inputs, stream):
         for ms, b in zip(meshes, bs):
             ctx.el_trace_rhs(d, ms, g_side, b)
         st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=args.tol, restart=args.restart, max_iter=20000,
-                                     graph=graph)
+                                     graph=graph, basis=gmres_basis(args))
         e[2].record(stream)
         for i, ms in enumerate(meshes):
             ctx.el_recover_mean(d, ms, i2m[offs[i]:offs[i + 1]], ts[i], means[i])
@@ -351,7 +362,7 @@ def batched_leg(args, ctx, el, inputs, stream):
     seq_iters = []
     for i, ms in enumerate(meshes):
         st, rp = ctx.el_trace_solve(d, [ms], [ops[i]], [bs[i]], [ts[i]], tol=args.tol, restart=args.restart,
-                                    max_iter=20000)
+                                    max_iter=20000, basis=gmres_basis(args))
         seq_iters.append(rp[0]["iters"])
     t_seq[1].record(stream)
     torch.cuda.synchronize()
@@ -465,7 +476,8 @@ def cloud_main(args):
     t_pl = torch.empty_like(b)
     e0, e1 = ev(), ev()
     e0.record(stream)
-    st, rep_pl = ctx.el_trace_solve(d, [ms], [ro], [b], [t_pl], tol=args.tol, restart=args.restart, max_iter=40000)
+    st, rep_pl = ctx.el_trace_solve(d, [ms], [ro], [b], [t_pl], tol=args.tol, restart=args.restart, max_iter=40000,
+                                    basis=gmres_basis(args))
     e1.record(stream)
     torch.cuda.synchronize()
     plain_gmres_ms = e0.elapsed_time(e1)
@@ -490,7 +502,8 @@ def cloud_main(args):
         ctx.el_conserve(d, hh, kap, lo32, in2mean=lm, mask=mask, out=None if lo is lo32 else lo)
         e[1].record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
-        st, rep = ctx.el_trace_solve(d, [ms], [lo], [b], [t], tol=args.tol, restart=args.restart, max_iter=40000)
+        st, rep = ctx.el_trace_solve(d, [ms], [lo], [b], [t], tol=args.tol, restart=args.restart, max_iter=40000,
+                                     basis=gmres_basis(args))
         e[2].record(stream)
         ctx.el_recover_mean(d, ms, lm, t, mean)
         e[3].record(stream)
@@ -520,7 +533,7 @@ def cloud_main(args):
                                "(k^-5/3, mean 10, log-std 1, zero below threshold), kappa=0.05 sigma+0.01, "
                                "learned in2mean form + FP32-refinement fallback, FP64 GMRES",
                    "elements": E, "p": p, "n_a": n_a, "g": g, "angular": args.cloud_angular, "gmres_tol": args.tol,
-                   "gmres_restart": args.restart},
+                   "gmres_restart": args.restart, "gmres_basis": args.gmres_basis},
         "network": f"{1 + 2 * nn}-{args.width}x{args.depth}-{n_out} GELU (in2out + in2mean)",
         "train_samples": N, "epochs_run": len(hist), "final_train_loss": hist[-1] if hist else None,
         "pair_generation_s": t_gen, "training_s": t_train,
@@ -585,7 +598,8 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
         op = lo if conserve else lo32
         e[1].record(stream)
         ctx.el_trace_rhs(d, ms, g_side, b)
-        st, rep = ctx.el_trace_solve(d, [ms], [op], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
+        st, rep = ctx.el_trace_solve(d, [ms], [op], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000,
+                                     basis=gmres_basis(args))
         e[2].record(stream)
         ctx.el_recover(d, ms, ls, t, None, mean)
         e[3].record(stream)
@@ -635,7 +649,7 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
         e0, e1 = ev(), ev()
         e0.record(stream)
         st, rw = ctx.el_trace_solve(d, [ms], [i2o_plain], [b], [tw], tol=1e-8, restart=args.restart,
-                                    max_iter=40000, x0=guess is not None)
+                                    max_iter=40000, x0=guess is not None, basis=gmres_basis(args))
         e1.record(stream)
         torch.cuda.synchronize()
         warm[name] = {"iters": rw[0]["iters"], "gmres_ms": e0.elapsed_time(e1), "converged": rw[0]["converged"]}
@@ -690,7 +704,8 @@ def storage_study(args, ctx, net, d, ms, hh, kap, sig, g_side, b, mean_plain, E,
     mean = torch.empty_like(mean_plain)
 
     def err(op_o, op_s):
-        ctx.el_trace_solve(d, [ms], [op_o], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000)
+        ctx.el_trace_solve(d, [ms], [op_o], [b], [t], tol=args.tol, restart=args.restart, max_iter=20000,
+                           basis=gmres_basis(args))
         ctx.el_recover(d, ms, op_s, t, None, mean)
         d2, r2 = ctx.el_mean_l2(d, hh, mean, mean_plain)
         return (d2 / r2) ** 0.5

@@ -110,6 +110,10 @@ typedef struct {
                      0: launch its kernels one by one (same kernels, same results) */
   int x0;         /* 0: start from t = 0; 1: trace[] holds the starting guess
                      on entry (for instance the learned solution) */
+  int basis;      /* storage of the Krylov basis: EL_F64, or EL_F32 (each
+                     basis vector rounded once; dot products, the solution
+                     and the restart residuals stay FP64; about half the
+                     bytes of the Gram-Schmidt sweeps) */
 } el_gmres_opts;
 
 typedef struct {

@@ -265,7 +265,8 @@ el_status el_trace_solve(el_ctx* ctx, el_disc d, int n_mesh, const el_mesh* mesh
   if (!op_dtype_ok(op_dtype))
     return set_error(ctx, EL_ERR_ARG, "el_trace_solve: op_dtype");
   const el_gmres_opts& o = *opts_host;
-  if (!(o.tol > 0) || o.restart < 1 || o.restart > 256 || o.max_iter < 1)
+  if (!(o.tol > 0) || o.restart < 1 || o.restart > 256 || o.max_iter < 1 ||
+      (o.basis != EL_F64 && o.basis != EL_F32))
     return set_error(ctx, EL_ERR_ARG, "el_trace_solve: bad GMRES options");
   for (int i = 0; i < n_mesh; ++i) {
     if (!mesh_ok(meshes_host[i]) || !in2out[i] || !b[i] || !trace[i]) {

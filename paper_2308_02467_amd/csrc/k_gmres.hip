@@ -21,8 +21,13 @@
 // Gram-Schmidt pass is needed less often.
 // One restart cycle (restart steps) is captured once as a HIP graph and
 // replayed; the host synchronizes once per cycle, after the true residual
-// b - (I - P) x of every mesh has been formed and tested.  x0 = 0; all
-// vectors, dot products and scalars are FP64.
+// b - (I - P) x of every mesh has been formed and tested.  x0 = 0 or a
+// given starting guess.  Dot products, scalars, the solution and the working
+// vectors are FP64; the stored basis V is FP64, or FP32 to halve the bytes
+// of the Gram-Schmidt sweeps (each v_j is rounded once, and the product of
+// step j takes the rounded v_j, so the Arnoldi relation holds for the stored
+// basis up to the rounding of its newest column; the true residual of every
+// restart stays FP64).
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -40,6 +45,8 @@ constexpr int kVThreads = 256;
 constexpr int kVec = 8;                       // values per thread in vector kernels
 constexpr int kChunk = kVThreads * kVec;      // DOFs per vector block
 constexpr int kMaxCnt = 258;                  // restart + 2
+constexpr int kGrp = 4;                       // basis vectors per pass of the sweep loops
+                                              // (their loads are in flight together)
 
 struct BMesh {
   int n_x, n_y, n_vf;
@@ -154,9 +161,19 @@ __device__ inline Span block_span(const BMesh* ms, int n_mesh) {
   return s;
 }
 
+// v[ix] for ix < lim, else 0, without a branch: the index is clamped into
+// the mesh segment (never empty) and the value selected, so the loads of a
+// sweep stay in flight together
+template <typename VT>
+__device__ inline double ld_masked(const VT* __restrict__ v, int64_t ix, int64_t lim) {
+  const double x = (double)v[ix < lim ? ix : lim - 1];
+  return ix < lim ? x : 0.0;
+}
+
 // partials[blk][i] = V[i] . w over the block chunk (i < cnt); with self also
 // partials[blk][cnt] = w . w.
-__global__ void __launch_bounds__(kVThreads) k_bdot(const double* __restrict__ V, int64_t ldv, int cnt,
+template <typename VT>
+__global__ void __launch_bounds__(kVThreads) k_bdot(const VT* __restrict__ V, int64_t ldv, int cnt,
                                                      const double* __restrict__ w, int self,
                                                      const BMesh* __restrict__ ms, int n_mesh,
                                                      const BState* __restrict__ st, int pred,
@@ -167,33 +184,35 @@ __global__ void __launch_bounds__(kVThreads) k_bdot(const double* __restrict__ V
   const int64_t base = sp.base + threadIdx.x;
   double wr[kVec];
 #pragma unroll
-  for (int v = 0; v < kVec; ++v) {
-    const int64_t ix = base + v * kVThreads;
-    wr[v] = ix < sp.lim ? w[ix] : 0.0;
-  }
+  for (int v = 0; v < kVec; ++v) wr[v] = ld_masked(w, base + v * kVThreads, sp.lim);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int i = 0;
-  for (; i + 2 <= cnt; i += 2) {
-    const double* v0 = V + (size_t)i * ldv;
-    const double* v1 = v0 + ldv;
-    double a0 = 0.0, a1 = 0.0;
+  for (; i + kGrp <= cnt; i += kGrp) {
+    double x[kGrp][kVec];
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) {
-      const int64_t ix = base + v * kVThreads;
-      if (ix < sp.lim) { a0 += v0[ix] * wr[v]; a1 += v1[ix] * wr[v]; }
+    for (int u = 0; u < kGrp; ++u) {
+      const VT* vu = V + (size_t)(i + u) * ldv;
+#pragma unroll
+      for (int v = 0; v < kVec; ++v) x[u][v] = ld_masked(vu, base + v * kVThreads, sp.lim);
     }
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-    if (lane == 0) { s[wave][i] = a0; s[wave][i + 1] = a1; }
+    double a[kGrp];
+#pragma unroll
+    for (int u = 0; u < kGrp; ++u) {
+      a[u] = 0.0;
+#pragma unroll
+      for (int v = 0; v < kVec; ++v) a[u] += x[u][v] * wr[v];
+      a[u] = wave_sum(a[u]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < kGrp; ++u) s[wave][i + u] = a[u];
+    }
   }
-  if (i < cnt) {
-    const double* v0 = V + (size_t)i * ldv;
+  for (; i < cnt; ++i) {
+    const VT* v0 = V + (size_t)i * ldv;
     double a0 = 0.0;
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) {
-      const int64_t ix = base + v * kVThreads;
-      if (ix < sp.lim) a0 += v0[ix] * wr[v];
-    }
+    for (int v = 0; v < kVec; ++v) a0 += ld_masked(v0, base + v * kVThreads, sp.lim) * wr[v];
     a0 = wave_sum(a0);
     if (lane == 0) s[wave][i] = a0;
   }
@@ -216,7 +235,8 @@ __global__ void __launch_bounds__(kVThreads) k_bdot(const double* __restrict__ V
 // w -= sign * sum_i c_i V[i] with c = the mesh's coefficients at offset coef
 // (cnt >= 0: cnt of them; cnt < 0: the mesh's kused); with norm also
 // partials[blk] = w . w of the updated chunk.
-__global__ void __launch_bounds__(kVThreads) k_bupdate(const double* __restrict__ V, int64_t ldv, int cnt,
+template <typename VT>
+__global__ void __launch_bounds__(kVThreads) k_bupdate(const VT* __restrict__ V, int64_t ldv, int cnt,
                                                         const double* __restrict__ hs, BLay lay, int coef,
                                                         double* __restrict__ w, double sign, int norm,
                                                         const BMesh* __restrict__ ms, int n_mesh,
@@ -234,33 +254,28 @@ __global__ void __launch_bounds__(kVThreads) k_bupdate(const double* __restrict_
   const int64_t base = sp.base + threadIdx.x;
   double wr[kVec];
 #pragma unroll
-  for (int v = 0; v < kVec; ++v) {
-    const int64_t ix = base + v * kVThreads;
-    wr[v] = ix < sp.lim ? w[ix] : 0.0;
-  }
+  for (int v = 0; v < kVec; ++v) wr[v] = ld_masked(w, base + v * kVThreads, sp.lim);
   int i = 0;
-  for (; i + 2 <= c; i += 2) {
-    const double* v0 = V + (size_t)i * ldv;
-    const double* v1 = v0 + ldv;
-    const double h0 = cs[i], h1 = cs[i + 1];
-    double x0[kVec], x1[kVec];
+  for (; i + kGrp <= c; i += kGrp) {
+    double x[kGrp][kVec];
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) {
-      const int64_t ix = base + v * kVThreads;
-      x0[v] = ix < sp.lim ? v0[ix] : 0.0;
-      x1[v] = ix < sp.lim ? v1[ix] : 0.0;
+    for (int u = 0; u < kGrp; ++u) {
+      const VT* vu = V + (size_t)(i + u) * ldv;
+#pragma unroll
+      for (int v = 0; v < kVec; ++v) x[u][v] = ld_masked(vu, base + v * kVThreads, sp.lim);
     }
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) wr[v] = (wr[v] - h0 * x0[v]) - h1 * x1[v];
+    for (int u = 0; u < kGrp; ++u) {
+      const double hu = cs[i + u];
+#pragma unroll
+      for (int v = 0; v < kVec; ++v) wr[v] -= hu * x[u][v];
+    }
   }
-  if (i < c) {
-    const double* v0 = V + (size_t)i * ldv;
+  for (; i < c; ++i) {
+    const VT* v0 = V + (size_t)i * ldv;
     const double h0 = cs[i];
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) {
-      const int64_t ix = base + v * kVThreads;
-      if (ix < sp.lim) wr[v] -= h0 * v0[ix];
-    }
+    for (int v = 0; v < kVec; ++v) wr[v] -= h0 * ld_masked(v0, base + v * kVThreads, sp.lim);
   }
 #pragma unroll
   for (int v = 0; v < kVec; ++v) {
@@ -288,10 +303,38 @@ __global__ void __launch_bounds__(kVThreads) k_bscale(double* __restrict__ w, co
   const BState& S = st[sp.mi];
   if (skip(S, pred)) return;
   const double s = S.inv;
+  const int64_t base = sp.base + threadIdx.x;
+  double x[kVec];
+#pragma unroll
+  for (int v = 0; v < kVec; ++v) x[v] = ld_masked(w, base + v * kVThreads, sp.lim);
 #pragma unroll
   for (int v = 0; v < kVec; ++v) {
-    const int64_t ix = sp.base + threadIdx.x + v * kVThreads;
-    if (ix < sp.lim) w[ix] *= s;
+    const int64_t ix = base + v * kVThreads;
+    if (ix < sp.lim) w[ix] = x[v] * s;
+  }
+}
+
+// FP32 basis: v = w * inv of the mesh rounded to FP32 once, stored as the
+// basis column vb and, widened, as the FP64 input vd of the next product
+__global__ void __launch_bounds__(kVThreads) k_bscale_to(const double* __restrict__ w, double* __restrict__ vd,
+                                                          float* __restrict__ vb, const BMesh* __restrict__ ms,
+                                                          int n_mesh, const BState* __restrict__ st, int pred) {
+  const Span sp = block_span(ms, n_mesh);
+  const BState& S = st[sp.mi];
+  if (skip(S, pred)) return;
+  const double s = S.inv;
+  const int64_t base = sp.base + threadIdx.x;
+  double x[kVec];
+#pragma unroll
+  for (int v = 0; v < kVec; ++v) x[v] = ld_masked(w, base + v * kVThreads, sp.lim);
+#pragma unroll
+  for (int v = 0; v < kVec; ++v) {
+    const int64_t ix = base + v * kVThreads;
+    if (ix < sp.lim) {
+      const float r = (float)(x[v] * s);
+      vb[ix] = r;
+      vd[ix] = (double)r;
+    }
   }
 }
 
@@ -486,7 +529,11 @@ struct Batch {
   BLay lay;
   double tol;
   int max_iter;
-  double* V;         // [R + 1][Np]
+  bool f32;          // FP32 basis
+  double* V;         // FP64 basis [R + 1][Np] (null with the FP32 basis)
+  float* Vf;         // FP32 basis [R + 1][Np] (null with the FP64 basis)
+  double* W;         // FP32 basis: working vector w [Np]
+  double* vd;        // FP32 basis: the newest basis vector in FP64 [Np]
   double* tmp;       // [Np]
   double* bcat;      // [Np]
   double* xcat;      // [Np]
@@ -511,30 +558,49 @@ struct Batch {
   }
   void dot(hipStream_t s, int pred, int cnt, const double* w, int self, int dst, int decide = -1) const {
     const int outc = cnt + (self ? 1 : 0);
-    hipLaunchKernelGGL(k_bdot, dim3(nblk), dim3(kVThreads), 0, s, V, Np, cnt, w, self, ms, n_mesh, st, pred,
-                       partials);
+    if (f32)
+      hipLaunchKernelGGL(k_bdot<float>, dim3(nblk), dim3(kVThreads), 0, s, Vf, Np, cnt, w, self, ms, n_mesh, st,
+                         pred, partials);
+    else
+      hipLaunchKernelGGL(k_bdot<double>, dim3(nblk), dim3(kVThreads), 0, s, V, Np, cnt, w, self, ms, n_mesh, st,
+                         pred, partials);
     hipLaunchKernelGGL(k_breduce, dim3(outc, n_mesh), dim3(256), 0, s, partials, outc, ms, st, pred, hs, lay, dst,
                        decide);
   }
   // w -= sign V c; with dst >= 0 also |w|^2 into hs[dst]
   void update(hipStream_t s, int pred, int cnt, int coef, double* w, double sign, int dst, int decide = -1) const {
-    hipLaunchKernelGGL(k_bupdate, dim3(nblk), dim3(kVThreads), 0, s, V, Np, cnt, hs, lay, coef, w, sign,
-                       dst >= 0 ? 1 : 0, ms, n_mesh, st, pred, partials);
+    if (f32)
+      hipLaunchKernelGGL(k_bupdate<float>, dim3(nblk), dim3(kVThreads), 0, s, Vf, Np, cnt, hs, lay, coef, w, sign,
+                         dst >= 0 ? 1 : 0, ms, n_mesh, st, pred, partials);
+    else
+      hipLaunchKernelGGL(k_bupdate<double>, dim3(nblk), dim3(kVThreads), 0, s, V, Np, cnt, hs, lay, coef, w, sign,
+                         dst >= 0 ? 1 : 0, ms, n_mesh, st, pred, partials);
     if (dst >= 0)
       hipLaunchKernelGGL(k_breduce, dim3(1, n_mesh), dim3(256), 0, s, partials, 1, ms, st, pred, hs, lay, dst,
                          decide);
   }
+  // v_0 = r / |r| from r in the working vector (FP64 basis: V[0])
+  void start_vector(hipStream_t s) const {
+    if (f32)
+      hipLaunchKernelGGL(k_bscale_to, dim3(nblk), dim3(kVThreads), 0, s, W, vd, Vf, ms, n_mesh, st, P_ACTIVE);
+    else
+      hipLaunchKernelGGL(k_bscale, dim3(nblk), dim3(kVThreads), 0, s, V, ms, n_mesh, st, P_ACTIVE);
+  }
   // one Arnoldi step j on every active mesh
   void step(hipStream_t s, int j) const {
     const int cnt = j + 1;
-    double* w = V + (size_t)(j + 1) * Np;
-    matvec(s, P_ACTIVE, V + (size_t)j * Np, w, false);
+    double* w = f32 ? W : V + (size_t)(j + 1) * Np;
+    matvec(s, P_ACTIVE, f32 ? vd : V + (size_t)j * Np, w, false);
     dot(s, P_ACTIVE, cnt, w, 1, lay.h1);
     update(s, P_ACTIVE, cnt, lay.h1, w, 1.0, lay.sc + 2, cnt);
     dot(s, P_REORTH, cnt, w, 0, lay.h2);
     update(s, P_REORTH, cnt, lay.h2, w, 1.0, lay.sc + 3);
     hipLaunchKernelGGL(k_bgivens, dim3(n_mesh), dim3(64), 0, s, j, n_mesh, hs, lay, st, tol, max_iter);
-    hipLaunchKernelGGL(k_bscale, dim3(nblk), dim3(kVThreads), 0, s, w, ms, n_mesh, st, P_ACTIVE);
+    if (f32)
+      hipLaunchKernelGGL(k_bscale_to, dim3(nblk), dim3(kVThreads), 0, s, W, vd, Vf + (size_t)(j + 1) * Np, ms,
+                         n_mesh, st, P_ACTIVE);
+    else
+      hipLaunchKernelGGL(k_bscale, dim3(nblk), dim3(kVThreads), 0, s, w, ms, n_mesh, st, P_ACTIVE);
   }
 };
 
@@ -567,7 +633,10 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   }
   if (E > INT_MAX || nblk > INT_MAX / 2) return set_error(ctx, EL_ERR_ARG, "el_trace_solve: batch too large");
   const BLay lay = make_layout(R);
-  const size_t v_bytes = sizeof(double) * (size_t)(R + 4) * Np;
+  const bool f32 = opts.basis == EL_F32;
+  // tmp, b, x (+ w and v_j with the FP32 basis) in FP64, then the basis
+  const size_t v_bytes = sizeof(double) * (size_t)(f32 ? 5 : 3) * Np +
+                         (f32 ? sizeof(float) : sizeof(double)) * (size_t)(R + 1) * Np;
   const size_t p_bytes = sizeof(double) * (size_t)nblk * (R + 2);
   const size_t h_bytes = sizeof(double) * (size_t)n_mesh * lay.S;
   const size_t s_bytes = (sizeof(BState) * n_mesh + 255) / 256 * 256;
@@ -586,12 +655,23 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   bt.lay = lay;
   bt.tol = opts.tol;
   bt.max_iter = opts.max_iter;
+  bt.f32 = f32;
   char* base = reinterpret_cast<char*>(ctx->ws_gmres.ptr);
-  bt.V = reinterpret_cast<double*>(base);
-  bt.tmp = bt.V + (size_t)(R + 1) * Np;
+  bt.tmp = reinterpret_cast<double*>(base);
   bt.bcat = bt.tmp + Np;
   bt.xcat = bt.bcat + Np;
-  bt.partials = bt.xcat + Np;
+  if (f32) {
+    bt.V = nullptr;
+    bt.W = bt.xcat + Np;
+    bt.vd = bt.W + Np;
+    bt.Vf = reinterpret_cast<float*>(bt.vd + Np);
+    bt.partials = reinterpret_cast<double*>(bt.Vf + (size_t)(R + 1) * Np);   // Np is a multiple of kChunk
+  } else {
+    bt.V = bt.xcat + Np;
+    bt.Vf = nullptr;
+    bt.W = bt.vd = nullptr;
+    bt.partials = bt.V + (size_t)(R + 1) * Np;
+  }
   bt.hs = bt.partials + (size_t)nblk * (R + 2);
   bt.st = reinterpret_cast<BState*>(reinterpret_cast<char*>(bt.hs) + h_bytes);
   bt.ms = reinterpret_cast<BMesh*>(reinterpret_cast<char*>(bt.st) + s_bytes);
@@ -607,8 +687,8 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
       he = hipMemcpyAsync(bt.xcat + hm[i].d0, trace[i], sizeof(double) * hm[i].N, hipMemcpyDeviceToDevice, s);
   if (he != hipSuccess) return hip_check(ctx, he, "el_trace_solve: starting guess");
   // |b| per mesh (the state is not initialized yet: no skipping)
-  hipLaunchKernelGGL(k_bdot, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.bcat, (int64_t)0, 0, bt.bcat, 1, bt.ms,
-                     n_mesh, bt.st, P_ALL, bt.partials);
+  hipLaunchKernelGGL(k_bdot<double>, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.bcat, (int64_t)0, 0, bt.bcat, 1,
+                     bt.ms, n_mesh, bt.st, P_ALL, bt.partials);
   hipLaunchKernelGGL(k_breduce, dim3(1, n_mesh), dim3(256), 0, s, bt.partials, 1, bt.ms, bt.st, P_ALL, bt.hs, lay,
                      lay.sc + 0, -1);
   hipLaunchKernelGGL(k_binit, dim3(nblocks(n_mesh, 64)), dim3(64), 0, s, n_mesh, bt.hs, lay, bt.st);
@@ -618,7 +698,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   // graph of one restart cycle, cached on the context
   std::ostringstream key;
   key << base << ':' << R << ':' << n_mesh << ':' << E << ':' << Np << ':' << nblk << ':' << op_dtype << ':'
-      << (const void*)de << ':' << opts.tol << ':' << opts.max_iter;
+      << (const void*)de << ':' << opts.tol << ':' << opts.max_iter << ':' << f32;
   bool use_graph = opts.graph != 0;
   if (use_graph && (ctx->gm_key != key.str() || !ctx->gm_exec)) {
     if (ctx->gm_exec) {
@@ -647,17 +727,19 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
 
   std::vector<BState> hst(n_mesh);
   for (;;) {
-    // true residual r = b - (I - P) x into V[0], its norm, test, v0 = r / |r|
+    // true residual r = b - (I - P) x into V[0] (FP32 basis: into w), its
+    // norm, test, v0 = r / |r|
+    double* r = f32 ? bt.W : bt.V;
     bt.matvec(s, P_NOT_DONE, bt.xcat, bt.tmp, true);
-    hipLaunchKernelGGL(k_bsub, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.bcat, bt.tmp, bt.V, bt.ms, n_mesh, bt.st,
+    hipLaunchKernelGGL(k_bsub, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.bcat, bt.tmp, r, bt.ms, n_mesh, bt.st,
                        P_NOT_DONE);
-    hipLaunchKernelGGL(k_bdot, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.V, (int64_t)0, 0, bt.V, 1, bt.ms, n_mesh,
+    hipLaunchKernelGGL(k_bdot<double>, dim3(bt.nblk), dim3(kVThreads), 0, s, r, (int64_t)0, 0, r, 1, bt.ms, n_mesh,
                        bt.st, P_NOT_DONE, bt.partials);
     hipLaunchKernelGGL(k_breduce, dim3(1, n_mesh), dim3(256), 0, s, bt.partials, 1, bt.ms, bt.st, P_NOT_DONE,
                        bt.hs, lay, lay.sc + 1, -1);
     hipLaunchKernelGGL(k_bstart, dim3(nblocks(n_mesh, 64)), dim3(64), 0, s, n_mesh, bt.hs, lay, bt.st, opts.tol,
                        opts.max_iter);
-    hipLaunchKernelGGL(k_bscale, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.V, bt.ms, n_mesh, bt.st, P_ACTIVE);
+    bt.start_vector(s);
     he = hipMemcpyAsync(hst.data(), bt.st, sizeof(BState) * n_mesh, hipMemcpyDeviceToHost, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) return hip_check(ctx, he, "el_trace_solve: cycle");
@@ -678,8 +760,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
       for (int j = 0; j < R; ++j) bt.step(s, j);
     }
     hipLaunchKernelGGL(k_bfinish, dim3(n_mesh), dim3(64), 0, s, n_mesh, bt.hs, lay, bt.st);
-    hipLaunchKernelGGL(k_bupdate, dim3(bt.nblk), dim3(kVThreads), 0, s, bt.V, Np, -1, bt.hs, lay, lay.y, bt.xcat,
-                       -1.0, 0, bt.ms, n_mesh, bt.st, P_USED, bt.partials);
+    bt.update(s, P_USED, -1, lay.y, bt.xcat, -1.0, -1);
     stt = hip_check(ctx, hipGetLastError(), "el_trace_solve: step");
     if (stt) return stt;
   }

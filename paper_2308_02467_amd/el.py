@@ -63,7 +63,7 @@ EL_FORM_IN2SOL, EL_FORM_IN2MEAN = 0, 1
 
 class el_gmres_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("graph", ctypes.c_int), ("x0", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("x0", ctypes.c_int), ("basis", ctypes.c_int)]
 
 
 class el_gmres_report(ctypes.Structure):
@@ -304,8 +304,11 @@ class Context:
                                                  _ptr(x, torch.float64, nt, "x"), _ptr(y, torch.float64, nt, "y")))
 
     def el_trace_solve(self, d, meshes, in2outs, bs, traces, tol=1e-12, restart=50, max_iter=2000, graph=True,
-                       x0=False):
-        """x0: start from the values in traces instead of zero."""
+                       x0=False, basis=torch.float64):
+        """x0: start from the values in traces instead of zero; basis: storage
+        of the Krylov basis (torch.float64 or torch.float32)."""
+        if basis not in (torch.float64, torch.float32):
+            raise ValueError("basis must be torch.float64 or torch.float32")
         k = len(meshes)
         M = (el_mesh * k)(*meshes)
         ops = (ctypes.c_void_p * k)(*[_ptr(t, name="in2out") for t in in2outs])
@@ -314,7 +317,8 @@ class Context:
             raise ValueError("all operators must share one dtype")
         B = (ctypes.c_void_p * k)(*[_ptr(b, torch.float64, trace_size(d, ms), "b") for b, ms in zip(bs, meshes)])
         X = (ctypes.c_void_p * k)(*[_ptr(x, torch.float64, trace_size(d, ms), "trace") for x, ms in zip(traces, meshes)])
-        opts = el_gmres_opts(float(tol), int(restart), int(max_iter), int(bool(graph)), int(bool(x0)))
+        opts = el_gmres_opts(float(tol), int(restart), int(max_iter), int(bool(graph)), int(bool(x0)),
+                             EL_F32 if basis == torch.float32 else EL_F64)
         rep = (el_gmres_report * k)()
         st = lib().el_trace_solve(self.h, d, k, M, ops, dt.pop(), B, X, ctypes.byref(opts), rep)
         self._check(st, allow_warn=True)

@@ -386,7 +386,7 @@ def _batched_problem(p, n_a):
     return probs
 
 
-def _batched_gpu(ctx, p, n_a, probs, graph, tol=1e-12):
+def _batched_gpu(ctx, p, n_a, probs, graph, tol=1e-12, basis=torch.float64):
     from paper_2308_02467_amd import el
     d = el.disc(p, n_a)
     nn, n, m = el.disc_sizes(d)
@@ -410,16 +410,21 @@ def _batched_gpu(ctx, p, n_a, probs, graph, tol=1e-12):
         bs.append(b)
         ts.append(torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV))
         e0 += h.size
-    print(f"[batched] el_trace_solve n_mesh={len(meshes)} graph={graph}", flush=True)
-    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=tol, restart=20, max_iter=3000, graph=graph)
+    print(f"[batched] el_trace_solve n_mesh={len(meshes)} graph={graph} basis={basis}", flush=True)
+    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=tol, restart=20, max_iter=3000, graph=graph,
+                                 basis=basis)
     torch.cuda.synchronize()
     return st, rep, [t.cpu().numpy() for t in ts]
 
 
-def test_batched_uneven_meshes_parity(ctx):
+@pytest.mark.parametrize("basis", [torch.float64, torch.float32])
+def test_batched_uneven_meshes_parity(ctx, basis):
+    """Several meshes in one GMRES against the oracle's direct solves; with
+    the FP32 Krylov basis the restart residuals are still FP64, so the same
+    tolerance is reached."""
     p, n_a = 3, 8
     probs = _batched_problem(p, n_a)
-    st, rep, ts = _batched_gpu(ctx, p, n_a, probs, graph=True)
+    st, rep, ts = _batched_gpu(ctx, p, n_a, probs, graph=True, basis=basis)
     assert st == 0
     for (od, oms, hh, kap, sig), r, t in zip(probs, rep, ts):
         ref = oracle_pipeline(od, oms, hh, kap, sig, inputs.left_inflow(n_a))
@@ -498,17 +503,18 @@ def test_gmres_starting_guess(ctx):
     assert st == 0 and rep[0]["converged"] and torch.all(t == 0)
 
 
-def test_batched_graph_replays_match_eager(ctx):
+@pytest.mark.parametrize("basis", [torch.float64, torch.float32])
+def test_batched_graph_replays_match_eager(ctx, basis):
     """The captured restart cycle gives bit-identical results to launching the
     same kernels one by one, on every replay, with other device work and
     synchronizations between the solves."""
     p, n_a = 3, 8
     probs = _batched_problem(p, n_a)
-    _, rep0, ref = _batched_gpu(ctx, p, n_a, probs, graph=False)
+    _, rep0, ref = _batched_gpu(ctx, p, n_a, probs, graph=False, basis=basis)
     for it in range(3):
         junk = torch.randn(1 << 20, dtype=torch.float64, device=DEV)
         (junk * 2).sum().item()
-        _, rep, ts = _batched_gpu(ctx, p, n_a, probs, graph=True)
+        _, rep, ts = _batched_gpu(ctx, p, n_a, probs, graph=True, basis=basis)
         for a, b, r, r0 in zip(ts, ref, rep, rep0):
             assert np.array_equal(a, b), it
             assert r == r0, it
