@@ -317,6 +317,14 @@ el_status el_net_num_params(const el_net* net, int64_t* n_params);
  * receives the size needed including the NUL.  Never fails. */
 el_status el_tuning_report(char* buf, size_t cap, size_t* len);
 
+/* Block tile of the network GEMMs in this process: -1 (default) = chosen
+ * per shape by the autotuner; 0 = 128x128, 1 = 64x128, 2 = 128x64,
+ * 3 = 256x256 with operand tiles loaded straight into LDS (only GEMMs
+ * with k-contiguous operands and K a multiple of 64; the others keep the
+ * autotuned tile).  For tests that pin one tile.  EL_ERR_ARG for another
+ * value. */
+el_status el_gemm_tile(int variant);
+
 /* Training pairs from the local solver (FP64 LU; FP32 LU with FP64
  * refinement when the FP64 factorization does not fit one workgroup, as at
  * n = 1568): y [E][n_out] bfloat16 (round to nearest even) = (in2out,

@@ -3,6 +3,7 @@
 // range check and plain-solver fallback.  All GEMMs run on the BF16 matrix
 // cores (gemm_bf16.h) with FP32 accumulation; master weights and optimizer
 // state are FP32.
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <type_traits>
@@ -240,6 +241,37 @@ struct EpiF32 {
   __device__ void flush() {}
 };
 
+// Epilogue of a wave's TM x TN MFMA tiles of 32 x 32 (wave tile at rows mw,
+// columns nw).  Output layout of the 32x32 MFMA (measured on gfx950):
+// register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  The
+// per-column data of all TN columns is fetched first (columns past N read
+// column N - 1 and are never stored) and waited for once, so that the
+// guarded stores that follow wait for nothing (a wait inside the guarded
+// blocks would also wait for the stores before it).
+template <int TM, int TN, typename Epi>
+__device__ inline void store_tiles(Epi& epi, const gemm::f32x16 (&acc)[TM][TN], int mw, int nw, int M, int N,
+                                   int lane, int z) {
+  const int lr = lane & 31, hi = lane >> 5;
+  decltype(epi.col(0)) cols[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) cols[j] = epi.col(min(nw + 32 * j + lr, N - 1));
+  __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = nw + 32 * j + lr;
+    if (n < N) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = mw + 32 * i + 8 * (r >> 2) + 4 * hi + (r & 3);
+          if (m < M) epi(m, n, acc[i][j][r], z, cols[j]);
+        }
+    }
+  }
+  epi.flush();
+}
+
 // at least two workgroups per CU (LDS), so the registers of a wave must fit
 // 2 waves/SIMD
 template <bool A_KC, bool B_KC, int TM, int TN, typename Epi>
@@ -337,23 +369,190 @@ __global__ void __launch_bounds__(gemm::kThreads) __attribute__((amdgpu_waves_pe
     }
     __syncthreads();
   }
-  // output layout of the 32x32 MFMA (measured on gfx950): register r of lane
-  // l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
+  store_tiles<TM, TN>(epi, acc, m0 + wm * 32 * TM, n0 + wn * 32 * TN, M, N, lane, blockIdx.z);
+}
+
+// Large-tile variants for k-contiguous operands with K a multiple of 64: a
+// 256 x 256 block tile, 8 waves of 128 x 64 (4 x 2 MFMA tiles of 32 x 32),
+// operand tiles moved from HBM straight into LDS by global_load_lds_dwordx4
+// (no register staging, so the accumulators of the larger wave tile fit),
+// NS LDS stages of BK k (128 KB in all), loads NS - 1 tiles ahead, one
+// barrier per k tile.  A row of an operand tile is BK / 8 chunks of 16 bytes
+// (8 k); chunk c of row r sits at position c ^ f(r) of the row (f(r) = r % 8
+// for 8 chunks, (r / 2) % 4 for 4), so the 16-byte fragment reads of
+// consecutive rows at one chunk spread over the banks.  One load instruction
+// of a wave fills 1 KB: lane l writes position l % (BK / 8) of row
+// l / (BK / 8) of its group of rows, so it fetches the chunk that belongs
+// there.  Per k16 step a wave reads 6 fragments for 8 MFMAs (the 64 x 64
+// wave tile of k_mm reads 4 for 4).
+namespace gemm_lds {
+constexpr int BM = 256, BN = 256;
+constexpr int TM = 4;                               // MFMA tiles per wave along M (2 waves of 128 rows)
+// TN MFMA tiles per wave along N: 2 (8 waves of 128 x 64) or 4 (4 waves of
+// 128 x 128, accumulators in the AGPRs)
+template <int TN>
+constexpr int threads() { return 64 * 2 * (BN / (32 * TN)); }
+constexpr size_t kSmem = 128 * 1024;                // NS x BK x (BM + BN) x 2 bytes
+template <int BK>
+__device__ inline int swz(int r) { return BK == 64 ? (r & 7) : ((r >> 1) & 3); }
+// s_waitcnt immediate that waits until at most n vector memory operations
+// are outstanding (expcnt and lgkmcnt left alone)
+constexpr int vmcnt_imm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
+}  // namespace gemm_lds
+
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+
+// one R x BK operand tile (rows r0.., k0..k0+BK-1) into LDS S; rows past the
+// operand are clamped to its last row (their products are never stored)
+template <int BK, int R, int NW>
+__device__ inline void lds_tile_load(const uint16_t* __restrict__ G, int64_t ld, int rows, int r0, int k0,
+                                     lds_u16* S, int wave, int lane) {
+  constexpr int CPR = BK / 8;                        // 16-byte chunks per row
+  constexpr int RPI = 64 / CPR;                      // rows per load instruction
+  constexpr int NI = R / RPI / NW;                   // instructions per wave
+  const int sub = lane / CPR;
+  const int c = (lane % CPR) ^ gemm_lds::swz<BK>(sub);
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int n = n0 + wn * 32 * TN + 32 * j + lr;
-    if (n < N) {
-      const auto c = epi.col(n);
+  for (int t = 0; t < NI; ++t) {
+    const int q = wave * NI + t;                     // row group of the tile
+    const int r = min(r0 + q * RPI + sub, rows - 1);
+    const uint16_t* src = G + (int64_t)r * ld + k0 + c * 8;
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                     reinterpret_cast<__attribute__((address_space(3))) void*>(S + q * 512), 16, 0,
+                                     0);
+  }
+}
+
+template <int BK, int NS, int TN, typename Epi>
+__global__ void __launch_bounds__(gemm_lds::threads<TN>()) k_mm_lds(const uint16_t* __restrict__ A, int64_t lda,
+                                                                     const uint16_t* __restrict__ B, int64_t ldb,
+                                                                     int M, int N, int K, int k_split, Epi epi) {
+  using namespace gemm;
+  using gemm_lds::BM;
+  using gemm_lds::BN;
+  using gemm_lds::TM;
+  static_assert(NS * BK * (BM + BN) * 2 <= (int)gemm_lds::kSmem, "LDS stages");
+  constexpr int NW = gemm_lds::threads<TN>() / 64;   // waves
+  constexpr int WN = NW / 2;                         // waves along N
+  constexpr int kTile = BM * BK;                     // bf16 per operand tile
+  constexpr int LW = (BM + BN) * BK / 8 / 64 / NW;   // load instructions per wave per k tile
+  extern __shared__ __align__(16) uint16_t lds_mm_big[];
+  lds_u16* L = (lds_u16*)lds_mm_big;   // the dynamic LDS array, as an LDS-space pointer
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  int tile_m, tile_n;
+  {
+    // the XCD-aware tile order of k_mm
+    const int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+    const int T = tm * tn;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, loc = b >> 3;
+    const int pid = xcd * (T >> 3) + min(xcd, T & 7) + loc;
+    constexpr int G = 8;
+    const int group = pid / (G * tn), first = group * G;
+    const int gsz = min(tm - first, G);
+    tile_m = first + (pid % (G * tn)) % gsz;
+    tile_n = (pid % (G * tn)) / gsz;
+  }
+  const int m0 = tile_m * BM, n0 = tile_n * BN;
+  const int kb = blockIdx.z * k_split;
+  const int ke = min(K, kb + k_split);
+  const int nsteps = kb < ke ? (ke - kb) / BK : 0;   // the host checks that 64 divides both
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  auto stage_a = [&](int st) { return L + st * 2 * kTile; };
+  auto stage_b = [&](int st) { return L + st * 2 * kTile + kTile; };
+  auto load_tile = [&](int t) {
+    const int k = kb + t * BK;
+    lds_tile_load<BK, BM, NW>(A, lda, M, m0, k, stage_a(t % NS), wave, lane);
+    lds_tile_load<BK, BN, NW>(B, ldb, N, n0, k, stage_b(t % NS), wave, lane);
+  };
+#pragma unroll
+  for (int t = 0; t < NS - 1; ++t)
+    if (t < nsteps) load_tile(t);
+  const int lr = lane & 31, hi = lane >> 5;
+  const int sw = gemm_lds::swz<BK>(lr);
+  for (int s = 0; s < nsteps; ++s) {
+    // tile s has landed (the loads of the tiles after it may still be in
+    // flight) for every wave, and every wave is done with tile s - 1
+    const int pending = min(NS - 2, nsteps - 1 - s);
+    if constexpr (NS > 2) {
+      if (pending >= 2) __builtin_amdgcn_s_waitcnt(gemm_lds::vmcnt_imm(2 * LW));
+      else if (pending == 1) __builtin_amdgcn_s_waitcnt(gemm_lds::vmcnt_imm(LW));
+      else __builtin_amdgcn_s_waitcnt(gemm_lds::vmcnt_imm(0));
+      static_assert(NS <= 4, "wait counts for more stages");
+    } else {
+      (void)pending;
+      __builtin_amdgcn_s_waitcnt(gemm_lds::vmcnt_imm(0));
+    }
+    // a bare barrier: the wait above covers the LDS writes of this wave's
+    // loads, and every LDS read of the previous tile has returned (the MFMAs
+    // consumed it); __syncthreads would add a fence that waits for all loads
+    // in flight, the later tiles' included
+    asm volatile("s_barrier" ::: "memory");
+    if (s + NS - 1 < nsteps) load_tile(s + NS - 1);
+    const lds_u16* as = stage_a(s % NS) + (wm * 32 * TM + lr) * BK;
+    const lds_u16* bs = stage_b(s % NS) + (wn * 32 * TN + lr) * BK;
+    // fragments of the next k16 step are read while this one multiplies
+    bf16x8 af[2][TM], bfr[2][TN];
+    auto frags = [&](int ks, int b) {
+      const int off = (((ks >> 3) + hi) ^ sw) << 3;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        af[b][i] = *reinterpret_cast<const __attribute__((address_space(3))) bf16x8*>(as + 32 * i * BK + off);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bfr[b][j] = *reinterpret_cast<const __attribute__((address_space(3))) bf16x8*>(bs + 32 * j * BK + off);
+    };
+    frags(0, 0);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const int b = (ks >> 4) & 1;
+      if (ks + 16 < BK) frags(ks + 16, b ^ 1);
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = m0 + wm * 32 * TM + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          if (m < M) epi(m, n, acc[i][j][r], blockIdx.z, c);
-        }
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[b][i], bfr[b][j], acc[i][j], 0, 0, 0);
     }
   }
-  epi.flush();
+  store_tiles<TM, TN>(epi, acc, m0 + wm * 32 * TM, n0 + wn * 32 * TN, M, N, lane, blockIdx.z);
+}
+
+// whether k_mm_lds can take a GEMM (k-contiguous operands, 16-byte aligned
+// rows, K and the split-K chunk multiples of 64)
+inline bool mm_lds_ok(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t K, int splits) {
+  int64_t ks = (K + splits - 1) / splits;
+  ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
+  return K % 64 == 0 && ks % 64 == 0 && lda % 8 == 0 && ldb % 8 == 0 &&
+         reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
+}
+
+template <int BK, int NS, int TN, typename Epi>
+el_status mm_lds(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M, int64_t N,
+                 int64_t K, int splits, Epi epi) {
+  if (!mm_lds_ok(A, lda, B, ldb, K, splits))
+    return set_error(ctx, EL_ERR_ARG, "internal GEMM: the direct-to-LDS tile needs K % 64 == 0 and aligned rows");
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mm_lds<BK, NS, TN, Epi>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds::kSmem);
+    if (e != hipSuccess) return hip_check(ctx, e, "hipFuncSetAttribute(k_mm_lds)");
+    attr_set = true;
+  }
+  int64_t ks = (K + splits - 1) / splits;
+  ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
+  const int nz = (int)((K + ks - 1) / ks);
+  const int64_t tiles = ((M + gemm_lds::BM - 1) / gemm_lds::BM) * ((N + gemm_lds::BN - 1) / gemm_lds::BN);
+  if (tiles > INT_MAX / 2) return set_error(ctx, EL_ERR_ARG, "internal GEMM: too many tiles");
+  hipLaunchKernelGGL((k_mm_lds<BK, NS, TN, Epi>), dim3((unsigned)tiles, 1, (unsigned)nz), dim3(gemm_lds::threads<TN>()),
+                     gemm_lds::kSmem, ctx->stream, A, lda, B, ldb, (int)M, (int)N, (int)K, (int)ks, epi);
+  return hip_check(ctx, hipGetLastError(), "launch k_mm_lds");
 }
 
 template <bool A_KC, bool B_KC, int TM, int TN, typename Epi>
@@ -391,12 +590,19 @@ el_status mm_t(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, i
 // (the loss accumulation) use the default.  Choices are kept per process.
 struct TileVariant {
   int tm, tn;
+  bool lds;   // k_mm_lds (k-contiguous operands only)
 };
-constexpr TileVariant kVariants[] = {{2, 2}, {1, 2}, {2, 1}};
+constexpr TileVariant kVariants[] = {{2, 2, false}, {1, 2, false}, {2, 1, false}, {4, 4, true}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, std::vector<float>>> g_tune;   // key -> (choice, ms per variant)
+std::atomic<int> g_force_tile{-1};   // >= 0: this variant wherever it applies (el_gemm_tile)
+
+template <bool A_KC, bool B_KC>
+bool variant_applies(int v, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t K, int splits) {
+  return !kVariants[v].lds || (A_KC && B_KC && mm_lds_ok(A, lda, B, ldb, K, splits));
+}
 
 template <bool A_KC, bool B_KC, typename Epi>
 el_status mm_variant(el_ctx* ctx, int v, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M,
@@ -404,6 +610,15 @@ el_status mm_variant(el_ctx* ctx, int v, const uint16_t* A, int64_t lda, const u
   switch (v) {
     case 1: return mm_t<A_KC, B_KC, 1, 2, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
     case 2: return mm_t<A_KC, B_KC, 2, 1, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
+    case 3:
+      // 8 waves of 128 x 64, k tiles of 64 in two stages (on the 128^2, p = 6
+      // output layer faster than k tiles of 32 in four stages or 4 waves of
+      // 128 x 128)
+      if constexpr (A_KC && B_KC) {
+        return mm_lds<64, 2, 2, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi);
+      } else {
+        return set_error(ctx, EL_ERR_ARG, "internal GEMM: the direct-to-LDS tile needs k-contiguous operands");
+      }
     default: return mm_t<A_KC, B_KC, 2, 2, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
   }
 }
@@ -412,6 +627,9 @@ template <bool A_KC, bool B_KC, typename Epi>
 el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M, int64_t N,
              int64_t K, int splits, Epi epi, bool m_fast = false) {
   if (M <= 0 || N <= 0) return EL_OK;
+  const int forced = g_force_tile.load();
+  if (forced >= 0 && variant_applies<A_KC, B_KC>(forced, A, lda, B, ldb, K, splits))
+    return mm_variant<A_KC, B_KC, Epi>(ctx, forced, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
   if constexpr (!Epi::kRepeatable) {
     return mm_variant<A_KC, B_KC, Epi>(ctx, 0, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
   } else {
@@ -432,6 +650,10 @@ el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int
         return hip_check(ctx, hipGetLastError(), "autotune events");
       int best = 0;
       for (int v = 0; v < kNumVariants; ++v) {
+        if (!variant_applies<A_KC, B_KC>(v, A, lda, B, ldb, K, splits)) {
+          ms[v] = INFINITY;   // not a candidate for this GEMM
+          continue;
+        }
         el_status st = mm_variant<A_KC, B_KC, Epi>(ctx, v, A, lda, B, ldb, M, N, K, splits, epi, m_fast);   // warm-up
         if (st) return st;
         hipEventRecord(e0, ctx->stream);
@@ -1086,13 +1308,21 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
   return st;
 }
 
+el_status el_gemm_tile(int variant) {
+  if (variant < -1 || variant >= kNumVariants) return EL_ERR_ARG;
+  g_force_tile.store(variant);
+  return EL_OK;
+}
+
 el_status el_tuning_report(char* buf, size_t cap, size_t* len) {
   std::ostringstream os;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& kv : g_tune) {
       const TileVariant v = kVariants[kv.second.first];
-      os << kv.first << " -> tile " << 64 * v.tm << "x" << 64 * v.tn << " (ms:";
+      os << kv.first << " -> tile " << 64 * v.tm << "x" << 64 * v.tn
+         << (v.lds ? " direct-to-LDS" : "")
+         << " (ms:";
       for (float t : kv.second.second) os << ' ' << t;
       os << ")\n";
     }

@@ -93,6 +93,7 @@ _SIGS = {
     "el_trace_add_source": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_void_p],
     "el_trace_matvec": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_void_p],
+    "el_gemm_tile": [ctypes.c_int],
     "el_tuning_report": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "el_trace_solve": [ctypes.c_void_p, el_disc, ctypes.c_int, ctypes.POINTER(el_mesh),
                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
@@ -551,3 +552,11 @@ def tuning_report():
     buf = ctypes.create_string_buffer(max(n.value, 1))
     lib().el_tuning_report(buf, n.value, None)
     return buf.value.decode()
+
+
+def gemm_tile(variant):
+    """Pin the block tile of the network GEMMs (el_gemm_tile); -1 restores the
+    autotuner."""
+    st = lib().el_gemm_tile(int(variant))
+    if st != 0:
+        raise ValueError(f"el_gemm_tile: bad variant {variant}")

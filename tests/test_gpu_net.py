@@ -63,15 +63,28 @@ def _raw_inputs(rng, B, nn):
     return np.concatenate([h, rng.uniform(0.01, 3, (B, nn)), rng.uniform(0.05, 30, (B, nn))], axis=1)
 
 
-@pytest.mark.parametrize("n_in,width,depth,n_out,act", [(9, 64, 2, 96, 0), (19, 128, 3, 200, 1),
-                                                         (99, 1024, 4, 1024, 0), (99, 256, 1, 225792, 0)])
-def test_forward_parity(ctx, n_in, width, depth, n_out, act):
+@pytest.fixture
+def gemm_tile():
+    """Pins the GEMM block tile for one test and restores the autotuner."""
+    from paper_2308_02467_amd import el
+    yield el.gemm_tile
+    el.gemm_tile(-1)
+
+
+# tile -1: the autotuner's choice; 3: the 256 x 256 direct-to-LDS tile for
+# every GEMM that can take it (k-contiguous operands, K % 64 == 0)
+@pytest.mark.parametrize("tile", [-1, 3])
+@pytest.mark.parametrize("n_in,width,depth,n_out,act,B", [(9, 64, 2, 96, 0, 6), (19, 128, 3, 200, 1, 6),
+                                                           (99, 1024, 4, 1024, 0, 6), (99, 256, 1, 225792, 0, 6),
+                                                           (99, 256, 2, 1000, 0, 700)])
+def test_forward_parity(ctx, gemm_tile, tile, n_in, width, depth, n_out, act, B):
     rng = np.random.default_rng(n_in + width)
     hn = _host_net(rng, n_in, width, depth, n_out, act)
     net = _load(ctx, hn, n_in, width, depth, n_out, act)
-    x = _raw_inputs(rng, 6, (n_in - 1) // 2).astype(np.float32)
-    y = torch.empty((6, n_out), dtype=torch.float32, device=DEV)
-    print(f"[el_net_forward] {n_in}-{width}x{depth}-{n_out}", flush=True)
+    x = _raw_inputs(rng, B, (n_in - 1) // 2).astype(np.float32)
+    y = torch.empty((B, n_out), dtype=torch.float32, device=DEV)
+    gemm_tile(tile)
+    print(f"[el_net_forward] {n_in}-{width}x{depth}-{n_out} B={B} tile={tile}", flush=True)
     net.forward(torch.from_numpy(x).to(DEV), y)
     X0 = features(x.astype(np.float64), hn["fm"].astype(np.float64), hn["fs"].astype(np.float64), hn["k0"])
     ref, _ = hn["oracle"].forward(X0, bf16=True)
@@ -79,12 +92,14 @@ def test_forward_parity(ctx, n_in, width, depth, n_out, act):
     net.close()
 
 
-def test_gradients_and_adam(ctx):
+@pytest.mark.parametrize("tile", [-1, 3])
+def test_gradients_and_adam(ctx, gemm_tile, tile):
     from paper_2308_02467_amd import el
     n_in, width, depth, n_out, B = 9, 64, 3, 128, 48
     rng = np.random.default_rng(11)
     hn = _host_net(rng, n_in, width, depth, n_out)
     net = _load(ctx, hn, n_in, width, depth, n_out)
+    gemm_tile(tile)
     x = _raw_inputs(rng, B, 4).astype(np.float32)
     y_raw = rng.uniform(-0.5, 0.5, (B, n_out))
     y16 = torch.from_numpy(y_raw.astype(np.float32)).to(torch.bfloat16)
