@@ -432,9 +432,11 @@ def test_batched_uneven_meshes_parity(ctx, basis):
         assert rel_err(t, ref["t"]) <= 1e-10, (oms.n_x, oms.n_y, rel_err(t, ref["t"]))
 
 
+@pytest.mark.parametrize("basis", [torch.float64, torch.float32])
 @pytest.mark.parametrize("dtype", [torch.float16, torch.float32])
-def test_batched_rounded_operators_parity(ctx, dtype):
-    """GMRES over several meshes with FP16 / FP32 operators: the solution of
+def test_batched_rounded_operators_parity(ctx, dtype, basis):
+    """GMRES over several meshes with FP16 / FP32 operators (the storage of
+    the learned step), with either Krylov basis: the solution of
     (I - P~) t = b with the rounded operators P~, against the oracle's direct
     solve with the same rounded operators."""
     from paper_2308_02467_amd import el
@@ -458,8 +460,8 @@ def test_batched_rounded_operators_parity(ctx, dtype):
         ops.append(op)
         bs.append(b)
         ts.append(torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV))
-    print(f"[batched] el_trace_solve {dtype} n_mesh={len(meshes)}", flush=True)
-    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=1e-12, restart=20, max_iter=3000)
+    print(f"[batched] el_trace_solve {dtype} basis={basis} n_mesh={len(meshes)}", flush=True)
+    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=1e-12, restart=20, max_iter=3000, basis=basis)
     assert st == 0
     for r, t, ref in zip(rep, ts, refs):
         assert r["converged"] and r["relres"] <= 1e-12, r
