@@ -63,3 +63,17 @@ def test_bad_disc_rejected():
         el.disc_sizes(el.disc(6, 6))
     with pytest.raises(el.ElError):
         el.disc_sizes(el.disc(0, 8))
+
+
+def test_gemm_tile_pin_validates_its_argument():
+    """el_gemm_tile is host-only: -1 (autotuner) and the four tiles are
+    accepted, anything else is EL_ERR_ARG and leaves the setting alone."""
+    from paper_2308_02467_amd import el
+    L = el.lib()
+    for v in (-1, 0, 1, 2, 3, -1):
+        assert L.el_gemm_tile(v) == 0, v
+    for v in (-2, 4, 1 << 20):
+        assert L.el_gemm_tile(v) != 0, v
+    with pytest.raises(ValueError):
+        el.gemm_tile(7)
+    el.gemm_tile(-1)
