@@ -153,7 +153,13 @@ __device__ inline void row_dots(const OpT* const (&rows)[RowShape<OpT>::R], cons
       const int c = cb + 8 * V * k;
       if (c < m) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r][k] = *reinterpret_cast<const vec*>(rows[r] + c);
+        for (int r = 0; r < R; ++r) {
+          // FP32 / FP64 operators stream with non-temporal loads (11-13 %
+          // faster at 128^2); for 16-bit operators plain loads are faster
+          const vec* src = reinterpret_cast<const vec*>(rows[r] + c);
+          if constexpr (sizeof(OpT) >= 4) v[r][k] = __builtin_nontemporal_load(src);
+          else v[r][k] = *src;
+        }
       }
     }
 #pragma unroll
