@@ -169,6 +169,12 @@ __device__ inline double ld_masked(const VT* __restrict__ v, int64_t ix, int64_t
   const double x = (double)v[ix < lim ? ix : lim - 1];
   return ix < lim ? x : 0.0;
 }
+// the same for the basis vectors, streamed with non-temporal loads
+template <typename VT>
+__device__ inline double ld_masked_nt(const VT* __restrict__ v, int64_t ix, int64_t lim) {
+  const double x = (double)__builtin_nontemporal_load(v + (ix < lim ? ix : lim - 1));
+  return ix < lim ? x : 0.0;
+}
 
 // partials[blk][i] = V[i] . w over the block chunk (i < cnt); with self also
 // partials[blk][cnt] = w . w.
@@ -193,7 +199,7 @@ __global__ void __launch_bounds__(kVThreads) k_bdot(const VT* __restrict__ V, in
     for (int u = 0; u < kGrp; ++u) {
       const VT* vu = V + (size_t)(i + u) * ldv;
 #pragma unroll
-      for (int v = 0; v < kVec; ++v) x[u][v] = ld_masked(vu, base + v * kVThreads, sp.lim);
+      for (int v = 0; v < kVec; ++v) x[u][v] = ld_masked_nt(vu, base + v * kVThreads, sp.lim);
     }
     double a[kGrp];
 #pragma unroll
@@ -212,7 +218,7 @@ __global__ void __launch_bounds__(kVThreads) k_bdot(const VT* __restrict__ V, in
     const VT* v0 = V + (size_t)i * ldv;
     double a0 = 0.0;
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) a0 += ld_masked(v0, base + v * kVThreads, sp.lim) * wr[v];
+    for (int v = 0; v < kVec; ++v) a0 += ld_masked_nt(v0, base + v * kVThreads, sp.lim) * wr[v];
     a0 = wave_sum(a0);
     if (lane == 0) s[wave][i] = a0;
   }
@@ -262,7 +268,7 @@ __global__ void __launch_bounds__(kVThreads) k_bupdate(const VT* __restrict__ V,
     for (int u = 0; u < kGrp; ++u) {
       const VT* vu = V + (size_t)(i + u) * ldv;
 #pragma unroll
-      for (int v = 0; v < kVec; ++v) x[u][v] = ld_masked(vu, base + v * kVThreads, sp.lim);
+      for (int v = 0; v < kVec; ++v) x[u][v] = ld_masked_nt(vu, base + v * kVThreads, sp.lim);
     }
 #pragma unroll
     for (int u = 0; u < kGrp; ++u) {
@@ -275,7 +281,7 @@ __global__ void __launch_bounds__(kVThreads) k_bupdate(const VT* __restrict__ V,
     const VT* v0 = V + (size_t)i * ldv;
     const double h0 = cs[i];
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) wr[v] -= h0 * ld_masked(v0, base + v * kVThreads, sp.lim);
+    for (int v = 0; v < kVec; ++v) wr[v] -= h0 * ld_masked_nt(v0, base + v * kVThreads, sp.lim);
   }
 #pragma unroll
   for (int v = 0; v < kVec; ++v) {
