@@ -378,9 +378,9 @@ __global__ void __launch_bounds__(gemm::kThreads) __attribute__((amdgpu_waves_pe
 // (no register staging, so the accumulators of the larger wave tile fit),
 // NS LDS stages of BK k (128 KB in all), loads NS - 1 tiles ahead, one
 // barrier per k tile.  A row of an operand tile is BK / 8 chunks of 16 bytes
-// (8 k); chunk c of row r sits at position c ^ f(r) of the row (f(r) = r % 8
-// for 8 chunks, (r / 2) % 4 for 4), so the 16-byte fragment reads of
-// consecutive rows at one chunk spread over the banks.  One load instruction
+// (8 k); chunk c of row r sits at position c ^ f(r) of the row (gemm_lds::swz),
+// so the 16-byte fragment reads of consecutive rows at one chunk spread over
+// all banks.  One load instruction
 // of a wave fills 1 KB: lane l writes position l % (BK / 8) of row
 // l / (BK / 8) of its group of rows, so it fetches the chunk that belongs
 // there.  Per k16 step a wave reads 6 fragments for 8 MFMAs (the 64 x 64
@@ -393,8 +393,13 @@ constexpr int TM = 4;                               // MFMA tiles per wave along
 template <int TN>
 constexpr int threads() { return 64 * 2 * (BN / (32 * TN)); }
 constexpr size_t kSmem = 128 * 1024;                // NS x BK x (BM + BN) x 2 bytes
+// chunk position of row r: conflict-free 16-byte fragment reads of 32
+// consecutive rows whether a read is served 8 lanes at a time over 32 banks
+// or 16 lanes at a time over 64 banks (rows r and r + 8 must differ too)
 template <int BK>
-__device__ inline int swz(int r) { return BK == 64 ? (r & 7) : ((r >> 1) & 3); }
+__device__ inline int swz(int r) {
+  return BK == 64 ? ((r & 7) ^ ((r >> 3) & 1)) : (((r >> 1) & 3) ^ ((r >> 3) & 1));
+}
 // s_waitcnt immediate that waits until at most n vector memory operations
 // are outstanding (expcnt and lgkmcnt left alone)
 constexpr int vmcnt_imm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
@@ -411,10 +416,10 @@ __device__ inline void lds_tile_load(const uint16_t* __restrict__ G, int64_t ld,
   constexpr int RPI = 64 / CPR;                      // rows per load instruction
   constexpr int NI = R / RPI / NW;                   // instructions per wave
   const int sub = lane / CPR;
-  const int c = (lane % CPR) ^ gemm_lds::swz<BK>(sub);
 #pragma unroll
   for (int t = 0; t < NI; ++t) {
     const int q = wave * NI + t;                     // row group of the tile
+    const int c = (lane % CPR) ^ gemm_lds::swz<BK>(q * RPI + sub);
     const int r = min(r0 + q * RPI + sub, rows - 1);
     const uint16_t* src = G + (int64_t)r * ld + k0 + c * 8;
     __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
