@@ -125,7 +125,7 @@ def recorded_traffic(op_dtype):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2308_02467_amd import el, inputs

@@ -77,3 +77,14 @@ def test_gemm_tile_pin_validates_its_argument():
     with pytest.raises(ValueError):
         el.gemm_tile(7)
     el.gemm_tile(-1)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message (one GPU only)."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
