@@ -63,6 +63,7 @@ def parse():
                     help="fraction of the training after which lr drops 10x (0 = constant)")
     ap.add_argument("--width", type=int, default=1024)
     ap.add_argument("--depth", type=int, default=4)
+    ap.add_argument("--act", choices=("gelu", "elu"), default="gelu", help="hidden-layer activation")
     ap.add_argument("--no-conserve", action="store_true", help="skip the energy-balance correction")
     ap.add_argument("--op-dtype", choices=("float16", "float32"), default="float16",
                     help="storage of the learned operators (in2out and in2sol)")
@@ -92,6 +93,10 @@ def log(msg):
 MATVEC_SOURCES = ("paper_2308_02467_amd/csrc/trace_dev.h", "paper_2308_02467_amd/csrc/k_trace.hip")
 TRAFFIC_SUMMARY = {"float16": "profiles/k_matvec_f16_128x128_p6_na16_hbm_traffic.md"}
 MATVEC_KERNEL = {"float32": "k_matvec<float>", "float16": "k_matvec<_Float16>"}
+
+
+def act_code(el, args):
+    return el.EL_ACT_ELU if args.act == "elu" else el.EL_ACT_GELU
 
 
 def gmres_basis(args):
@@ -431,7 +436,7 @@ def cloud_main(args):
     x, y = learned.training_set(ctx, d, N, form=el.EL_FORM_IN2MEAN, draws=draws)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
-    net = el.Net.create(ctx, 1 + 2 * nn, args.width, args.depth, n_out, seed=0)
+    net = el.Net.create(ctx, 1 + 2 * nn, args.width, args.depth, n_out, act=act_code(el, args), seed=0)
     net.fit_normalization(x, y)
     t0 = time.perf_counter()
     hist = learned.train(net, x, y, args.cloud_epochs, batch=4096, lr=1e-3, time_limit=args.train_time_limit,
@@ -534,7 +539,7 @@ def cloud_main(args):
                                "learned in2mean form + FP32-refinement fallback, FP64 GMRES",
                    "elements": E, "p": p, "n_a": n_a, "g": g, "angular": args.cloud_angular, "gmres_tol": args.tol,
                    "gmres_restart": args.restart, "gmres_basis": args.gmres_basis},
-        "network": f"{1 + 2 * nn}-{args.width}x{args.depth}-{n_out} GELU (in2out + in2mean)",
+        "network": f"{1 + 2 * nn}-{args.width}x{args.depth}-{n_out} {args.act.upper()} (in2out + in2mean)",
         "train_samples": N, "epochs_run": len(hist), "final_train_loss": hist[-1] if hist else None,
         "pair_generation_s": t_gen, "training_s": t_train,
         "phases_ms": {"infer_fallback_and_correction": float(np.median(ph[:, 0])),
@@ -563,7 +568,7 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     from paper_2308_02467_amd import learned
     dev = hh.device
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    net = el.Net.create(ctx, 1 + 2 * nn, args.width, args.depth, m * m + n * m, seed=0)
+    net = el.Net.create(ctx, 1 + 2 * nn, args.width, args.depth, m * m + n * m, act=act_code(el, args), seed=0)
     log(f"learned: {args.train_samples} training pairs")
     t0 = time.perf_counter()
     x, y = learned.training_set(ctx, d, args.train_samples)
@@ -659,7 +664,7 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
     flop_el = 2.0 * (n_in * args.width + (args.depth - 1) * args.width ** 2 + args.width * (m * m + n * m))
     inf_ms = float(np.median(ph[:, 0]))
     out = {
-        "network": f"{n_in}-{args.width}x{args.depth}-{m * m + n * m} GELU, BF16 MFMA, FP32 accumulate",
+        "network": f"{n_in}-{args.width}x{args.depth}-{m * m + n * m} {args.act.upper()}, BF16 MFMA, FP32 accumulate",
         "train_samples": args.train_samples, "epochs_run": len(hist),
         "final_train_loss": hist[-1] if hist else None,
         "pair_generation_s": t_gen, "training_s": t_train,
