@@ -63,7 +63,7 @@ def parse():
                     help="fraction of the training after which lr drops 10x (0 = constant)")
     ap.add_argument("--width", type=int, default=1024)
     ap.add_argument("--depth", type=int, default=4)
-    ap.add_argument("--act", choices=("gelu", "elu"), default="gelu", help="hidden-layer activation")
+    ap.add_argument("--act", choices=("gelu", "elu", "linear"), default="gelu", help="hidden-layer activation")
     ap.add_argument("--no-conserve", action="store_true", help="skip the energy-balance correction")
     ap.add_argument("--op-dtype", choices=("float16", "float32"), default="float16",
                     help="storage of the learned operators (in2out and in2sol)")
@@ -96,7 +96,7 @@ MATVEC_KERNEL = {"float32": "k_matvec<float>", "float16": "k_matvec<_Float16>"}
 
 
 def act_code(el, args):
-    return el.EL_ACT_ELU if args.act == "elu" else el.EL_ACT_GELU
+    return {"gelu": el.EL_ACT_GELU, "elu": el.EL_ACT_ELU, "linear": el.EL_ACT_LINEAR}[args.act]
 
 
 def gmres_basis(args):

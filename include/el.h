@@ -272,12 +272,13 @@ el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h,
  * for the matrix-core GEMMs, FP32 accumulation. */
 #define EL_ACT_GELU 0
 #define EL_ACT_ELU 1
+#define EL_ACT_LINEAR 2  /* identity on the hidden layers: the linear network of the ablations of Sec. 3.1 */
 
 typedef struct {
   int n_in;        /* raw inputs per element, 1 + 2*nn */
   int width;       /* hidden width */
   int depth;       /* hidden layers (>= 1) */
-  int act;         /* EL_ACT_GELU or EL_ACT_ELU */
+  int act;         /* EL_ACT_GELU, EL_ACT_ELU or EL_ACT_LINEAR */
   int64_t n_out;   /* m*m + n*m (in2sol form) or m*m + nn*m (in2mean form) */
   uint64_t seed;   /* initialization: W, b ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) */
 } el_net_desc;

@@ -3,7 +3,8 @@
 Sec. 2.4.1: x_i = f_i(A_i x_{i-1} + b_i), f_i a nonlinear activation on the
 hidden layers and the identity on the output layer.  Sec. 3.1: mean
 absolute error loss, Adam optimizer.  GELU is the exact erf form
-GELU(z) = z Phi(z); ELU(z) = z (z > 0), exp(z) - 1 otherwise.
+GELU(z) = z Phi(z); ELU(z) = z (z > 0), exp(z) - 1 otherwise; "linear" is the
+identity (the linear network of the Sec. 3.1 ablations).
 
 Input of one element: x = (h, kappa[nn], sigma[nn]).  Features: log10 h and
 log10 max(h v / 2, 1e-12) for every nodal kappa and sigma (the
@@ -30,12 +31,16 @@ def bf16_round(a):
 
 
 def act(kind, z):
+    if kind == "linear":
+        return np.asarray(z, dtype=np.float64)
     if kind == "elu":
         return np.where(z > 0, z, np.expm1(np.minimum(z, 0.0)))
     return 0.5 * z * (1.0 + erf(z / np.sqrt(2.0)))
 
 
 def dact(kind, z):
+    if kind == "linear":
+        return np.ones_like(np.asarray(z, dtype=np.float64))
     if kind == "elu":
         return np.where(z > 0, 1.0, np.exp(np.minimum(z, 0.0)))
     return 0.5 * (1.0 + erf(z / np.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)

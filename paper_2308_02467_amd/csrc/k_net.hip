@@ -120,10 +120,12 @@ __global__ void k_features(const float* __restrict__ x32, const double* __restri
 }
 
 __device__ inline float act_f(int act, float z) {
+  if (act == EL_ACT_LINEAR) return z;
   if (act == EL_ACT_ELU) return z > 0.f ? z : expm1f(z);
   return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
 }
 __device__ inline float act_df(int act, float z) {
+  if (act == EL_ACT_LINEAR) return 1.f;
   if (act == EL_ACT_ELU) return z > 0.f ? 1.f : expf(z);
   return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
@@ -873,7 +875,7 @@ el_status alloc_net(el_ctx* ctx, el_net* net) {
 
 bool desc_ok(const el_net_desc& d) {
   return d.n_in >= 3 && d.n_in % 2 == 1 && d.width >= 16 && d.width % 8 == 0 && d.depth >= 1 && d.depth <= 16 &&
-         d.n_out >= 1 && d.n_out % 8 == 0 && (d.act == EL_ACT_GELU || d.act == EL_ACT_ELU);
+         d.n_out >= 1 && d.n_out % 8 == 0 && (d.act == EL_ACT_GELU || d.act == EL_ACT_ELU || d.act == EL_ACT_LINEAR);
 }
 
 // scratch layout for a batch of B rows

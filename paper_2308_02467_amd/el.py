@@ -58,6 +58,7 @@ class el_net_desc(ctypes.Structure):
 
 EL_ACT_GELU = 0
 EL_ACT_ELU = 1
+EL_ACT_LINEAR = 2
 EL_FORM_IN2SOL, EL_FORM_IN2MEAN = 0, 1
 
 

@@ -49,7 +49,7 @@ def _host_net(rng, n_in, width, depth, n_out, act=0):
     ym = rng.uniform(-0.1, 0.1, n_out).astype(np.float32)
     ys = rng.uniform(0.01, 0.2, n_out).astype(np.float32)
     return dict(k0=k0, P=P, theta=theta, fm=fm, fs=fs, ym=ym, ys=ys,
-                oracle=MLP(Ws, bs, "gelu" if act == 0 else "elu"))
+                oracle=MLP(Ws, bs, {0: "gelu", 1: "elu", 2: "linear"}[act]))
 
 
 def _load(ctx, hn, n_in, width, depth, n_out, act=0, box=(0, 1e9, 0, 1e9, 0, 1e9)):
@@ -76,7 +76,7 @@ def gemm_tile():
 @pytest.mark.parametrize("tile", [-1, 3])
 @pytest.mark.parametrize("n_in,width,depth,n_out,act,B", [(9, 64, 2, 96, 0, 6), (19, 128, 3, 200, 1, 6),
                                                            (99, 1024, 4, 1024, 0, 6), (99, 256, 1, 225792, 0, 6),
-                                                           (99, 256, 2, 1000, 0, 700)])
+                                                           (99, 256, 2, 1000, 0, 700), (19, 128, 3, 200, 2, 6)])
 def test_forward_parity(ctx, gemm_tile, tile, n_in, width, depth, n_out, act, B):
     rng = np.random.default_rng(n_in + width)
     hn = _host_net(rng, n_in, width, depth, n_out, act)

@@ -20,7 +20,7 @@ def _rand_mlp(rng, n_in, width, depth, n_out, kind):
     return MLP(Ws, bs, kind)
 
 
-@pytest.mark.parametrize("kind", ["gelu", "elu"])
+@pytest.mark.parametrize("kind", ["gelu", "elu", "linear"])
 def test_activation_derivative_fd(kind):
     z = np.linspace(-4, 4, 101)
     z = z[np.abs(z) > 1e-3]
@@ -32,7 +32,7 @@ def test_activation_derivative_fd(kind):
         assert abs(act(kind, np.array([10.0]))[0] - 10.0) < 1e-12
 
 
-@pytest.mark.parametrize("kind", ["gelu", "elu"])
+@pytest.mark.parametrize("kind", ["gelu", "elu", "linear"])
 def test_mae_gradients_match_finite_differences(kind):
     rng = np.random.default_rng(4)
     net = _rand_mlp(rng, 7, 12, 3, 5, kind)
@@ -113,3 +113,19 @@ def test_blob_roundtrip():
     u = el.unpack_net_blob(blob)
     assert u["step"] == 7 and u["box"] == [1, 2, 3, 4, 5, 6] and np.array_equal(u["theta"], th)
     assert len(blob) == el.HEADER_BYTES + 4 * (2 * 9 + 2 * 24 + 3 * P)
+
+
+def test_linear_network_is_one_affine_map():
+    """With the identity activation the network collapses to a single affine
+    map x -> x A^T + c, A = W_D ... W_0, c = W_D(...(W_1 b_0 + b_1)...) + b_D,
+    built here by folding the layers one at a time from the input side."""
+    rng = np.random.default_rng(8)
+    net = _rand_mlp(rng, 9, 16, 3, 5, "linear")
+    X = rng.standard_normal((7, 9))
+    A = np.eye(9)
+    c = np.zeros(9)
+    for W, b in zip(net.Ws, net.bs):
+        A = W @ A
+        c = W @ c + b
+    out, _ = net.forward(X)
+    assert np.abs(out - (X @ A.T + c)).max() < 1e-12
