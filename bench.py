@@ -76,6 +76,11 @@ def parse():
     ap.add_argument("--cloud", action="store_true",
                     help="run only the realistic-cloud leg (256^2 elements, p=6, N_a=32, HG g=0.85, "
                          "log-normal sigma, learned in2mean form + FP32-refinement fallback)")
+    ap.add_argument("--paper-generator", action="store_true",
+                    help="run only the element-training study with the paper's coefficient generator "
+                         "(P0 cells, N_a=28, g=0.8, albedo 1, 800 training / 200 test fields, batch 50, "
+                         "networks of 1-4 layers)")
+    ap.add_argument("--pg-time-limit", type=float, default=60.0, help="training seconds per network")
     ap.add_argument("--cloud-n", type=int, default=256)
     ap.add_argument("--cloud-na", type=int, default=32, help="angular cells of the cloud leg")
     ap.add_argument("--cloud-g", type=float, default=0.85, help="HG asymmetry of the cloud leg")
@@ -137,6 +142,9 @@ def main():
 
     if args.cloud:
         print(json.dumps(cloud_main(args)))
+        return
+    if args.paper_generator:
+        print(json.dumps(paper_generator_main(args)))
         return
 
     dev = torch.device("cuda:0")
@@ -387,6 +395,67 @@ def batched_leg(args, ctx, el, inputs, stream):
     del i2o, i2m
     torch.cuda.empty_cache()
     return out
+
+
+def paper_generator_main(args):
+    """Element training as in the paper's numerical setting (Sec. 3.1): P0
+    angular cells, N_a = 28, HG g = 0.8, albedo 1 (kappa = 0), reference-element
+    scattering fields from the paper's generator (Alg. 2, A_sigma = 10,
+    c_sm = 2; h = 2 so that the reference-element coefficient is sigma), 800
+    training and 200 test fields, hidden width 2 N_in, ELU, MAE, batch 50, lr
+    divided by 10 late.  Networks of 1 to 4 layers (1 layer: the linear map).
+    Test error: relative L2 of the inferred in2out and in2mean of each test
+    field against its local solve (FP32 + refinement to 1e-13)."""
+    import torch
+    from paper_2308_02467_amd import el, inputs, learned
+    dev = torch.device("cuda:0")
+    ctx = el.Context(0)
+    p, n_a = 6, 28
+    d = el.disc(p, n_a, 0.8, el.EL_ANG_P0)
+    nn, n, m = el.disc_sizes(d)
+    xi, _ = el.lgl(p)
+    n_tr, n_te = 800, 200
+    sig = inputs.legendre_smooth_draws(n_tr + n_te, xi, seed=1234, a_sigma=10.0, c_sm=2.0)
+    h = np.full(n_tr + n_te, 2.0)
+    kap = np.zeros_like(sig)
+    x, y = learned.training_set(ctx, d, n_tr + n_te, form=el.EL_FORM_IN2MEAN, draws=(h, kap, sig), log=False)
+    x_tr, y_tr = x[:n_tr].contiguous(), y[:n_tr].contiguous()
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    H, K, S = T(h[n_tr:]), T(kap[n_tr:]), T(sig[n_tr:])
+    ref_o = torch.empty((n_te, m, m), dtype=torch.float64, device=dev)
+    ref_m = torch.empty((n_te, nn, m), dtype=torch.float64, device=dev)
+    # FP32 + refinement (residual <= 1e-13): the FP64 factorization of n = 1372 does not fit one workgroup
+    ctx.el_local_solve(d, H, K, S, precision=el.EL_FP32_IR, in2out=ref_o, in2mean=ref_m)
+    n_in = 1 + 2 * nn
+    width = (2 * n_in + 7) // 8 * 8
+    n_out = m * m + nn * m
+    rows = []
+    for layers in (1, 2, 3, 4):
+        act = el.EL_ACT_LINEAR if layers == 1 else el.EL_ACT_ELU
+        net = el.Net.create(ctx, n_in, width, max(1, layers - 1), n_out, act=act, seed=0)
+        net.fit_normalization(x_tr, y_tr)
+        t0 = time.perf_counter()
+        hist = learned.train(net, x_tr, y_tr, 100000, batch=50, lr=1e-3, time_limit=args.pg_time_limit,
+                             decay_at=0.7, log=False)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        po = torch.empty((n_te, m, m), dtype=torch.float32, device=dev)
+        pm = torch.empty((n_te, nn, m), dtype=torch.float32, device=dev)
+        net.infer(d, H, K, S, in2out=po, in2mean=pm, fallback=False)
+        torch.cuda.synchronize()
+        eo = ((po.double() - ref_o).flatten(1).norm(dim=1) / ref_o.flatten(1).norm(dim=1)).cpu().numpy()
+        em = ((pm.double() - ref_m).flatten(1).norm(dim=1) / ref_m.flatten(1).norm(dim=1)).cpu().numpy()
+        rows.append({"layers": layers, "network": f"{n_in}-{width}x{max(1, layers - 1)}-{n_out} "
+                     + ("linear" if layers == 1 else "ELU"), "epochs": len(hist),
+                     "final_train_loss": hist[-1] if hist else None, "training_s": t_train,
+                     "test_in2out_rel_l2_mean": float(eo.mean()), "test_in2out_rel_l2_median": float(np.median(eo)),
+                     "test_in2mean_rel_l2_mean": float(em.mean())})
+        log(f"paper generator: {layers} layers, test in2out error {eo.mean():.3e}")
+        net.close()
+    ctx.close()
+    return {"study": "element training with the paper's coefficient generator", "p": p, "n_a": n_a,
+            "angular": "p0", "g": 0.8, "albedo": 1.0, "train": n_tr, "test": n_te, "batch": 50,
+            "a_sigma": 10.0, "c_sm": 2.0, "networks": rows}
 
 
 def cloud_main(args):

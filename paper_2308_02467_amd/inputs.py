@@ -121,6 +121,29 @@ def training_draws(n, xi, seed=1234, log_sigma=(-2.0, 2.0), log_kappa=(-3.0, 0.5
     return h, kappa, sigma
 
 
+def legendre_smooth_draws(n, xi, seed=1234, a_sigma=10.0, c_sm=2.0):
+    """n reference-element scattering fields sigma [n, q*q] following the
+    paper's optical-coefficient generator (Sec. 2.4.2, Alg. 2): modal
+    Legendre coefficients exp(-c_sm ((m/p)^2 + (n/p)^2)) (X_mn - 1/2) with
+    X_mn ~ U[0, 1] (the printed minus between the two squares is read as a
+    plus, so that both directions are damped), mapped to the nodes xi x xi,
+    shifted to a zero minimum, scaled to a unit maximum and multiplied by a
+    U[0, a_sigma] amplitude.  Node nd = b q + a is (xi_a, xi_b)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    q = xi.size
+    p = q - 1
+    rng = np.random.default_rng(seed)
+    L = np.stack([np.polynomial.legendre.legval(xi, np.eye(q)[k]) for k in range(q)])   # L[k][i] = L_k(xi_i)
+    kk = np.arange(q) / p
+    damp = np.exp(-c_sm * (kk[:, None] ** 2 + kk[None, :] ** 2))                    # [m (x), n (y)]
+    coef = damp[None] * (rng.uniform(0.0, 1.0, size=(n, q, q)) - 0.5)
+    # sigma(xi_a, xi_b) = sum_mn coef_mn L_m(xi_a) L_n(xi_b)
+    nodal = np.einsum("emn,ma,nb->eba", coef, L, L).reshape(n, q * q)
+    nodal -= nodal.min(axis=1, keepdims=True)
+    nodal /= np.maximum(nodal.max(axis=1, keepdims=True), 1e-300)
+    return nodal * rng.uniform(0.0, a_sigma, size=(n, 1))
+
+
 def left_inflow(n_a):
     """Per-side boundary radiance g_side [4, n_a] (sides W, E, S, N).
 
