@@ -81,6 +81,7 @@ def parse():
                          "(P0 cells, N_a=28, g=0.8, albedo 1, 800 training / 200 test fields, batch 50, "
                          "networks of 1-4 layers)")
     ap.add_argument("--pg-time-limit", type=float, default=60.0, help="training seconds per network")
+    ap.add_argument("--pg-train", type=int, default=800, help="training fields of the generator study")
     ap.add_argument("--cloud-n", type=int, default=256)
     ap.add_argument("--cloud-na", type=int, default=32, help="angular cells of the cloud leg")
     ap.add_argument("--cloud-g", type=float, default=0.85, help="HG asymmetry of the cloud leg")
@@ -414,8 +415,10 @@ def paper_generator_main(args):
     d = el.disc(p, n_a, 0.8, el.EL_ANG_P0)
     nn, n, m = el.disc_sizes(d)
     xi, _ = el.lgl(p)
-    n_tr, n_te = 800, 200
-    sig = inputs.legendre_smooth_draws(n_tr + n_te, xi, seed=1234, a_sigma=10.0, c_sm=2.0)
+    n_tr, n_te = args.pg_train, 200
+    # the test fields are the same whatever the training size
+    sig = np.concatenate([inputs.legendre_smooth_draws(n_tr, xi, seed=1234, a_sigma=10.0, c_sm=2.0),
+                          inputs.legendre_smooth_draws(n_te, xi, seed=4321, a_sigma=10.0, c_sm=2.0)])
     h = np.full(n_tr + n_te, 2.0)
     kap = np.zeros_like(sig)
     x, y = learned.training_set(ctx, d, n_tr + n_te, form=el.EL_FORM_IN2MEAN, draws=(h, kap, sig), log=False)
