@@ -82,6 +82,8 @@ def parse():
                          "networks of 1-4 layers)")
     ap.add_argument("--pg-time-limit", type=float, default=60.0, help="training seconds per network")
     ap.add_argument("--pg-train", type=int, default=800, help="training fields of the generator study")
+    ap.add_argument("--pg-floor", type=float, default=0.0,
+                    help="constant added to every generated field (0: the generator as printed)")
     ap.add_argument("--cloud-n", type=int, default=256)
     ap.add_argument("--cloud-na", type=int, default=32, help="angular cells of the cloud leg")
     ap.add_argument("--cloud-g", type=float, default=0.85, help="HG asymmetry of the cloud leg")
@@ -419,6 +421,7 @@ def paper_generator_main(args):
     # the test fields are the same whatever the training size
     sig = np.concatenate([inputs.legendre_smooth_draws(n_tr, xi, seed=1234, a_sigma=10.0, c_sm=2.0),
                           inputs.legendre_smooth_draws(n_te, xi, seed=4321, a_sigma=10.0, c_sm=2.0)])
+    sig += args.pg_floor
     h = np.full(n_tr + n_te, 2.0)
     kap = np.zeros_like(sig)
     x, y = learned.training_set(ctx, d, n_tr + n_te, form=el.EL_FORM_IN2MEAN, draws=(h, kap, sig), log=False)
@@ -458,7 +461,7 @@ def paper_generator_main(args):
     ctx.close()
     return {"study": "element training with the paper's coefficient generator", "p": p, "n_a": n_a,
             "angular": "p0", "g": 0.8, "albedo": 1.0, "train": n_tr, "test": n_te, "batch": 50,
-            "a_sigma": 10.0, "c_sm": 2.0, "networks": rows}
+            "a_sigma": 10.0, "c_sm": 2.0, "floor": args.pg_floor, "networks": rows}
 
 
 def cloud_main(args):
