@@ -267,9 +267,9 @@ def main():
 
     learned = None
     if not args.no_learned:
-        i2s = i2m = u = None
+        i2s = u = None
         torch.cuda.empty_cache()
-        learned = learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o, mean, stream, E, nn, n, m)
+        learned = learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o, i2m, mean, stream, E, nn, n, m)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -635,7 +635,8 @@ def cloud_main(args):
     return out
 
 
-def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_plain, stream, E, nn, n, m):
+def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, i2m_plain, mean_plain, stream, E, nn, n,
+                m):
     """Train the element network on pairs from the GPU local solver, then time
     the learned solve on the same workload and compare its mean intensity
     with the plain FP64 solve."""
@@ -733,6 +734,15 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, mean_p
         e1.record(stream)
         torch.cuda.synchronize()
         warm[name] = {"iters": rw[0]["iters"], "gmres_ms": e0.elapsed_time(e1), "converged": rw[0]["converged"]}
+        if guess is None:
+            # errors against the plain FP64 solution converged to 1e-8
+            mean_conv = torch.empty_like(mean_plain)
+            ctx.el_recover_mean(d, ms, i2m_plain, tw, mean_conv)
+            dl, rl = ctx.el_mean_l2(d, hh, mean, mean_conv)
+            dp, rp = ctx.el_mean_l2(d, hh, mean_plain, mean_conv)
+            warm["learned_mean_rel_l2_vs_converged"] = (dl / rl) ** 0.5
+            warm["plain_mean_rel_l2_vs_converged"] = (dp / rp) ** 0.5
+            del mean_conv
     del tw
 
     n_in = 1 + 2 * nn
