@@ -5,10 +5,11 @@ unit square, Q6 LGL (p = 6) x 16 discrete ordinates (n = 784 volume and
 m = 224 inflow DOFs per element), isotropic scattering, the smooth Gaussian
 cloud kappa = 0.01 + 0.5 G, sigma = 0.1 + 30 G (G a Gaussian bump of width
 0.2 at the centre), radiance 1 entering through the left side.  GMRES
-tolerance 1e-5, restart 40, Krylov basis stored in FP32 (dot products, the
+tolerance 3e-5, restart 40, Krylov basis stored in FP32 (dot products, the
 solution and the restart residuals FP64; --gmres-basis float64 keeps it
-FP64): the plain FP64 solution is then within 1.3e-4 relative L2 of the
-fully converged one (measured with --accuracy).
+FP64): every run reports the learned and the plain mean intensity against
+the plain FP64 solve converged to 1e-8 (about 5e-4 and 4e-4 at 128^2, inside
+the 1e-3 of the metric).
 
 Steps (inputs resident in HBM before every timed region):
 * plain:   el_local_solve (FP64 LU) -> el_trace_rhs -> el_trace_solve -> el_recover
@@ -47,7 +48,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="elements per side")
-    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--tol", type=float, default=3e-5,
+                    help="GMRES relative residual of the timed solves (3e-5 keeps both the learned and the plain "
+                         "mean intensity within 1e-3 of the converged plain solution, measured in every run)")
     ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--gmres-basis", choices=("float64", "float32"), default="float32",
                     help="storage of the Krylov basis (dot products and restart residuals stay FP64)")
