@@ -88,3 +88,21 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_recorded_matvec_traffic_is_tied_to_the_source():
+    """The roofline's measured traffic comes from the committed counter
+    summary only while the skeleton-product sources keep its hash; other
+    operator types have no recorded traffic."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    text = open(os.path.join(ROOT, bench.TRAFFIC_SUMMARY["float16"])).read()
+    m = re.search(r"traffic_bytes_per_launch k_matvec<_Float16> = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
+    assert m is not None
+    if m.group(2) == bench.matvec_source_hash():
+        assert bench.recorded_traffic("float16") == float(m.group(1))
+    else:
+        assert bench.recorded_traffic("float16") is None
+    assert bench.recorded_traffic("float32") is None
