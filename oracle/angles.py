@@ -43,6 +43,34 @@ def ordinates(n_a, angular="ordinates"):
     return theta, w, s
 
 
+def _hg_kernel(n_a, g, angular):
+    """Unnormalized Henyey-Greenstein kernel between ordinates (or the cell-pair
+    averages for P0 cells), exponent 3/2 as in Sec. 2.1."""
+    theta, _, _ = ordinates(n_a)
+    hg = lambda ang: (1.0 - g * g) / (1.0 + g * g - 2.0 * g * np.cos(ang)) ** 1.5
+    if angular == "ordinates":
+        return hg(theta[:, None] - theta[None, :])
+    if angular == "p0":
+        # average over pairs of cells: the kernel depends on k - k' only
+        from scipy.integrate import dblquad
+        dth = 2.0 * np.pi / n_a
+        q = np.array([dblquad(lambda y, x: hg(dd * dth + x - y), 0.0, dth, 0.0, dth,
+                              epsabs=1e-15, epsrel=1e-13)[0] / dth ** 2 for dd in range(n_a)])
+        k = np.arange(n_a)
+        return q[(k[:, None] - k[None, :]) % n_a]
+    raise ValueError("angular must be 'ordinates' or 'p0'")
+
+
+def hg_normalization(n_a, g, angular="ordinates"):
+    """The constant c of Sec. 2.1 as fixed discretely: the row sum
+    sum_k' w_k' (unnormalized kernel)[k, k'] (equal for every row: the kernel
+    is circulant)."""
+    if not (0.0 < g < 1.0):
+        raise ValueError("HG asymmetry must be in (0, 1)")
+    _, w, _ = ordinates(n_a)
+    return float((_hg_kernel(n_a, g, angular) @ w)[0])
+
+
 def phase_matrix(n_a, g=0.0, angular="ordinates"):
     """P[k, k'] on the ordinates; rows satisfy sum_k' w_k' P[k, k'] = 1.
 
@@ -50,23 +78,14 @@ def phase_matrix(n_a, g=0.0, angular="ordinates"):
     normalization exactly); otherwise the Henyey-Greenstein kernel with the
     paper's exponent 3/2, normalized discretely.
     """
-    theta, w, _ = ordinates(n_a)
     if g == 0.0:
+        ordinates(n_a)
         return np.full((n_a, n_a), 1.0 / (2.0 * np.pi))
     if not (0.0 <= g < 1.0):
         raise ValueError("HG asymmetry must be in [0, 1)")
-    hg = lambda ang: (1.0 - g * g) / (1.0 + g * g - 2.0 * g * np.cos(ang)) ** 1.5
-    if angular == "ordinates":
-        raw = hg(theta[:, None] - theta[None, :])
-    elif angular == "p0":
-        # average over pairs of cells: the kernel depends on k - k' only
-        from scipy.integrate import dblquad
-        dth = 2.0 * np.pi / n_a
-        q = np.array([dblquad(lambda y, x: hg(dd * dth + x - y), 0.0, dth, 0.0, dth,
-                              epsabs=1e-15, epsrel=1e-13)[0] / dth ** 2 for dd in range(n_a)])
-        k = np.arange(n_a)
-        raw = q[(k[:, None] - k[None, :]) % n_a]
-    else:
+    if angular not in ("ordinates", "p0"):
         raise ValueError("angular must be 'ordinates' or 'p0'")
+    _, w, _ = ordinates(n_a)
+    raw = _hg_kernel(n_a, g, angular)
     c = raw @ w                      # row integrals; equal for all rows (circulant)
     return raw / c[:, None]

@@ -32,6 +32,22 @@ def test_activation_derivative_fd(kind):
         assert abs(act(kind, np.array([10.0]))[0] - 10.0) < 1e-12
 
 
+def test_activation_tabulated_values():
+    """Values fixed by the definitions, not by the oracle's formula: the exact
+    GELU is z Phi(z), so GELU(1) = Phi(1) and GELU(-1) = -(1 - Phi(1)) with
+    the standard normal CDF value Phi(1) = 0.8413447460685429 (the tanh
+    approximation of GELU is 1.5e-4 off at z = 1); ELU(-1) = 1/e - 1; the
+    derivative of the exact GELU at 1 is Phi(1) + phi(1), phi(1) =
+    0.24197072451914337."""
+    phi1, dens1 = 0.8413447460685429, 0.24197072451914337
+    g = act("gelu", np.array([1.0, -1.0]))
+    assert abs(g[0] - phi1) <= 1e-15 and abs(g[1] + (1.0 - phi1)) <= 1e-15
+    assert abs(dact("gelu", np.array([1.0]))[0] - (phi1 + dens1)) <= 1e-15
+    assert abs(act("elu", np.array([-1.0]))[0] - (1.0 / np.e - 1.0)) <= 1e-16
+    assert act("elu", np.array([2.5]))[0] == 2.5
+    assert abs(dact("elu", np.array([-1.0]))[0] - 1.0 / np.e) <= 1e-16
+
+
 @pytest.mark.parametrize("kind", ["gelu", "elu", "linear"])
 def test_mae_gradients_match_finite_differences(kind):
     rng = np.random.default_rng(4)

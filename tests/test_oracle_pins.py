@@ -100,6 +100,30 @@ def test_phase_normalization_and_symmetry(g):
         assert np.allclose(P, 1 / (2 * math.pi))
 
 
+@pytest.mark.parametrize("g", [0.5, 0.8, 0.85])
+def test_hg_normalization_closed_form(g):
+    """The HG constant of Sec. 2.1 on the circle, with the exponent 3/2:
+    integral over [0, 2 pi) of (1 - g^2) / (1 + g^2 - 2 g cos t)^{3/2} dt
+    = 4 E(k^2) / (1 - g) with k^2 = 4 g / (1 + g)^2 (complete elliptic
+    integral of the second kind; the exponent 1 would give 2 pi instead).
+    * ordinates: the periodic trapezoidal sum converges geometrically, at
+      N_a = 256 to round-off;
+    * P0 cells: summing the cell-pair averages over k' integrates the kernel
+      over one full period for every x in the cell, so the discrete constant
+      equals the integral at any N_a (here the paper's N_a = 28).
+    Also the entries themselves at N_a = 256: P[k, k] -> (1 + g) / (4 (1 - g) E)
+    and, opposite, P[k, k + N_a/2] -> (1 - g)^2 / ((1 + g)^2 4 E)."""
+    from scipy.special import ellipe
+    from oracle.angles import hg_normalization
+    E2 = ellipe(4 * g / (1 + g) ** 2)
+    c = 4 * E2 / (1 - g)
+    assert abs(hg_normalization(256, g) - c) <= 1e-12 * c
+    assert abs(hg_normalization(28, g, "p0") - c) <= 1e-11 * c
+    P = phase_matrix(256, g)
+    assert abs(P[0, 0] - (1 + g) / (4 * (1 - g) * E2)) <= 1e-12 * P[0, 0]
+    assert abs(P[5, 5 + 128] - (1 - g) ** 2 / ((1 + g) ** 2 * 4 * E2)) <= 1e-12 * P[5, 5 + 128]
+
+
 # ---- sizes printed in the paper ------------------------------------------------
 def test_sizes_match_paper():
     """Sec. 2.4.1: A_i2o is 2(p_x+p_y+2)(N_a/2)(p_a+1) square, A_i2m is
