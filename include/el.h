@@ -237,7 +237,9 @@ el_status el_recover_mean(el_ctx* ctx, el_disc d, el_mesh mesh, const void* in2m
  * (outflow = inflow - absorption, obtained by testing the local equations
  * with v = 1 and summing over ordinates; w = face quadrature weight times
  * |s.n|); with in2mean the absorption is N_a sum_nd W_nd (h kappa_nd / 2)
- * in2mean[nd][i].  Each column of in2out is rescaled so that this holds.  Not part of the paper's method: a post-processing option for the
+ * in2mean[nd][i].  Each column i of in2out is multiplied by the one factor
+ * s_i = (w_i - absorption_i) / sum_o w_o in2out[o][i] that makes this hold
+ * (the column is left as it is when either is not positive).  Not part of the paper's method: a post-processing option for the
  * learned operators.  in2vol = in2sol or in2mean (form); in2out and in2vol
  * in op_dtype (EL_F64, EL_F32, EL_F16, EL_BF16).  The corrected in2out goes
  * to out in out_dtype: out = NULL or out = in2out corrects in place (out_dtype

@@ -78,6 +78,7 @@ struct el_ctx {
   el::Workspace ws_local;    // LU factors
   el::Workspace ws_gmres;    // Krylov basis and scratch
   el::Workspace ws_small;    // flags, reductions
+  el::Workspace ws_infer;    // el_infer: range mask (when the caller passes none) and fallback index
   int num_cus = 256;
   // captured GMRES restart cycle (rebuilt when the batch shape changes)
   hipStream_t cap_stream = nullptr;

@@ -131,6 +131,7 @@ el_status el_destroy(el_ctx* ctx) {
   hipFree(ctx->ws_local.ptr);
   hipFree(ctx->ws_gmres.ptr);
   hipFree(ctx->ws_small.ptr);
+  hipFree(ctx->ws_infer.ptr);
   delete ctx;
   return EL_OK;
 }
@@ -148,7 +149,7 @@ const char* el_last_error(const el_ctx* ctx) {
 
 el_status el_workspace_bytes(const el_ctx* ctx, size_t* bytes) {
   if (!ctx || !bytes) return EL_ERR_ARG;
-  *bytes = ctx->ws_local.bytes + ctx->ws_gmres.bytes + ctx->ws_small.bytes;
+  *bytes = ctx->ws_local.bytes + ctx->ws_gmres.bytes + ctx->ws_small.bytes + ctx->ws_infer.bytes;
   return EL_OK;
 }
 

@@ -1254,13 +1254,13 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
   el_status st2 = ensure_ws(ctx, ctx->ws_small, 4096 + 1024);
   if (st2) return st2;
   int* dcount = reinterpret_cast<int*>(reinterpret_cast<char*>(ctx->ws_small.ptr) + 4096 + 512);
-  uint8_t* mask = in_range;
-  void* mask_alloc = nullptr;
-  if (!mask) {
-    st = hip_check(ctx, hipMalloc(&mask_alloc, E), "hipMalloc(mask)");
-    if (st) return st;
-    mask = reinterpret_cast<uint8_t*>(mask_alloc);
-  }
+  // context workspace: fallback index [E] int32, then the range mask [E]
+  // when the caller passes none (grown on demand, kept across calls)
+  const size_t idx_bytes = (sizeof(int32_t) * (size_t)E + 255) / 256 * 256;
+  st = ensure_ws(ctx, ctx->ws_infer, idx_bytes + (in_range ? 0 : (size_t)E));
+  if (st) return st;
+  int32_t* idx = reinterpret_cast<int32_t*>(ctx->ws_infer.ptr);
+  uint8_t* mask = in_range ? in_range : reinterpret_cast<uint8_t*>(ctx->ws_infer.ptr) + idx_bytes;
   for (int64_t e0 = 0; e0 < E; e0 += chunk) {
     const int64_t B = std::min(chunk, E - e0);
     Scratch s;
@@ -1292,25 +1292,17 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
   int64_t nfb = 0;
   if (!st) {
     // count and compact the elements outside the training box
-    void* idx = nullptr;
-    st = hip_check(ctx, hipMalloc(&idx, sizeof(int32_t) * E), "hipMalloc(fallback index)");
-    if (!st) {
-      hipLaunchKernelGGL(k_fill_int32, dim3(1), dim3(64), 0, ctx->stream, dcount, 1, 0);
-      hipLaunchKernelGGL(k_count_out, dim3(nblk(E)), dim3(256), 0, ctx->stream, mask, E,
-                         reinterpret_cast<int32_t*>(idx), dcount);
-      int hc = 0;
-      hipError_t e = hipMemcpyAsync(&hc, dcount, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-      st = hip_check(ctx, e, "el_infer count");
-      nfb = hc;
-      if (!st && fallback && hc > 0)
-        st = launch_local_solve_ex(ctx, de, precision, hc, h, kappa, sigma, reinterpret_cast<int32_t*>(idx), in2out,
-                                   in2vol, form, out_dtype, nullptr);
-      hipStreamSynchronize(ctx->stream);
-      hipFree(idx);
-    }
+    hipLaunchKernelGGL(k_fill_int32, dim3(1), dim3(64), 0, ctx->stream, dcount, 1, 0);
+    hipLaunchKernelGGL(k_count_out, dim3(nblk(E)), dim3(256), 0, ctx->stream, mask, E, idx, dcount);
+    int hc = 0;
+    hipError_t e = hipMemcpyAsync(&hc, dcount, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    st = hip_check(ctx, e, "el_infer count");
+    nfb = hc;
+    if (!st && fallback && hc > 0)
+      st = launch_local_solve_ex(ctx, de, precision, hc, h, kappa, sigma, idx, in2out, in2vol, form, out_dtype,
+                                 nullptr);
   }
-  if (mask_alloc) { hipStreamSynchronize(ctx->stream); hipFree(mask_alloc); }
   if (n_fallback_host) *n_fallback_host = nfb;
   return st;
 }

@@ -455,6 +455,18 @@ class Net:
               precision=EL_FP64, in2mean=None):
         """in2out and in2sol (network in the in2sol form) or in2mean (in2mean
         form): bfloat16, float16 or float32 device tensors of one dtype."""
+        E, dt, vol = self._infer_args(d, h, in2out, in2sol, in2mean)
+        nn, _, _ = disc_sizes(d)
+        nfb = ctypes.c_int64()
+        self.ctx._check(lib().el_infer(self.ctx.h, self.h, d, E, _ptr(h, torch.float64, E, "h"),
+                                       _ptr(kappa, torch.float64, E * nn, "kappa"),
+                                       _ptr(sigma, torch.float64, E * nn, "sigma"),
+                                       _ptr(in2out, name="in2out"), _ptr(vol, name="in2vol"), int(dt),
+                                       _ptr(in_range, torch.uint8, E, "in_range"), int(bool(fallback)),
+                                       int(precision), ctypes.byref(nfb)))
+        return nfb.value
+
+    def _infer_args(self, d, h, in2out, in2sol, in2mean):
         nn, n, m = disc_sizes(d)
         E = h.numel()
         if in2sol is not None and in2mean is not None:
@@ -468,14 +480,7 @@ class Net:
         for t, cnt, name in ((in2out, E * m * m, "in2out"), (vol, E * rows * m, "in2sol/in2mean")):
             if t is not None and (_op_dtype(t) != dt or t.numel() != cnt):
                 raise ValueError(f"{name}: expected {cnt} elements of the common dtype")
-        nfb = ctypes.c_int64()
-        self.ctx._check(lib().el_infer(self.ctx.h, self.h, d, E, _ptr(h, torch.float64, E, "h"),
-                                       _ptr(kappa, torch.float64, E * nn, "kappa"),
-                                       _ptr(sigma, torch.float64, E * nn, "sigma"),
-                                       _ptr(in2out, name="in2out"), _ptr(vol, name="in2vol"), int(dt),
-                                       _ptr(in_range, torch.uint8, E, "in_range"), int(bool(fallback)),
-                                       int(precision), ctypes.byref(nfb)))
-        return nfb.value
+        return E, dt, vol
 
 
 def el_make_pairs(ctx, d, h, kappa, sigma, y, form=None):

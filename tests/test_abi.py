@@ -90,19 +90,26 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
 
 
-def test_recorded_matvec_traffic_is_tied_to_the_source():
+def test_recorded_matvec_traffic_is_tied_to_the_source(tmp_path, monkeypatch):
     """The roofline's measured traffic comes from the committed counter
-    summary only while the skeleton-product sources keep its hash; other
-    operator types have no recorded traffic."""
+    summary only while the skeleton-product sources keep its hash: a summary
+    carrying the current hash gives its figure, one with any other hash gives
+    None; other operator types have no recorded traffic."""
     import importlib.util
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
+    assert "paper_2308_02467_amd/csrc/el_internal.h" in bench.MATVEC_SOURCES   # the DiscDev layout
     text = open(os.path.join(ROOT, bench.TRAFFIC_SUMMARY["float16"])).read()
-    m = re.search(r"traffic_bytes_per_launch k_matvec<_Float16> = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
-    assert m is not None
-    if m.group(2) == bench.matvec_source_hash():
-        assert bench.recorded_traffic("float16") == float(m.group(1))
-    else:
-        assert bench.recorded_traffic("float16") is None
+    assert re.search(r"traffic_bytes_per_launch k_matvec<_Float16> = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
+    cur = bench.matvec_source_hash()
+    for sha, expect in ((cur, 1.5e9), ("0" * 64, None)):
+        os.makedirs(tmp_path / "profiles", exist_ok=True)
+        (tmp_path / bench.TRAFFIC_SUMMARY["float16"]).write_text(
+            f"traffic_bytes_per_launch k_matvec<_Float16> = 1.5e9 source_sha256 = {sha}\n")
+        for f in bench.MATVEC_SOURCES:
+            os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
+            (tmp_path / f).write_bytes(open(os.path.join(ROOT, f), "rb").read())
+        monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+        assert bench.recorded_traffic("float16") == expect
     assert bench.recorded_traffic("float32") is None

@@ -116,6 +116,15 @@ def test_bad_inputs_name_the_element(ctx):
     with pytest.raises(el.ElError) as ei:
         _gpu_local(ctx, 3, 8, 0.0, h, kap, sig)
     assert ei.value.code == el.EL_ERR_NONFINITE and "element 6" in str(ei.value)
+    sig[6, 0] = 1.0
+    # finite coefficients whose reference-element values overflow FP32 (the
+    # FP32 factorization meets an infinite entry and then NaN columns): the
+    # pivot search finds no usable pivot and the element is reported singular
+    sig[2, :] = 1e300
+    with pytest.raises(el.ElError) as ei:
+        _gpu_local(ctx, 3, 8, 0.0, h, kap, sig, precision=1)
+    print(f"[local solve] {ei.value}", flush=True)
+    assert ei.value.code == el.EL_ERR_SINGULAR and "element 2" in str(ei.value)
     with pytest.raises(ValueError):
         ctx.el_local_solve(el.disc(3, 8), torch.ones(2, dtype=torch.float64, device="cuda"),
                            torch.ones(5, dtype=torch.float64, device="cuda"),

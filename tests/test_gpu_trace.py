@@ -322,14 +322,41 @@ def test_conserve_energy_balance(ctx, dtype):
     assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= CONSERVE_KEEP[dtype]
     rng = np.random.default_rng(0)
     Op = T(i2o * (1 + 0.02 * rng.standard_normal(i2o.shape))).to(dtype)
+    before = Op.clone()
     mask = torch.ones(20, dtype=torch.uint8, device=DEV)
     mask[5] = 0
     ctx.el_conserve(d, T(h), T(kap), Op, S, mask)
     got = Op.to(torch.float64).cpu().numpy()
-    bal = balance(got, S.to(torch.float64).cpu().numpy())
+    Sd = S.to(torch.float64).cpu().numpy()
+    bal = balance(got, Sd)
     keep = np.arange(20) != 5
     assert np.abs(bal[keep]).max() <= tol * np.abs(win).max()
-    assert np.abs(bal[5]).max() > 1e-4            # masked element untouched
+    assert torch.equal(Op[5], before[5])          # masked element left bit-identical
+    # the documented rule: column c of in2out is scaled by one factor
+    # s_c = (w_c - absorption_c) / sum_o w_o in2out[o][c], computed here on
+    # the host from the operators the kernel received
+    P = before.to(torch.float64).cpu().numpy()
+    ab = balance(np.zeros_like(P), Sd) + win[None, :]
+    s_host = _column_factors(win[None, :] - ab, np.einsum("o,eom->em", wout, P))
+    _check_column_scaling(got[keep], P[keep], s_host[keep], dtype)
+
+
+def _column_factors(target, colsum):
+    """One factor per column: target / colsum, or 1 where either is not
+    positive (the column is then left as it is)."""
+    ok = (target > 0) & (colsum > 0)
+    return np.where(ok, target / np.where(ok, colsum, 1.0), 1.0)
+
+
+def _check_column_scaling(got, P, s_host, dtype):
+    """got == P * s_host per column, up to one rounding to dtype."""
+    exp = P * s_host[:, None, :]
+    rel, tiny = {torch.float64: (1e-14, 0.0), torch.float32: (2.0 ** -23, 1e-38),
+                 torch.float16: (2.0 ** -10, 2.0 ** -24)}[dtype]
+    err = np.abs(got - exp) - rel * np.abs(exp) - tiny
+    print(f"[el_conserve] column scaling: worst excess {err.max():.3e}, "
+          f"factors in [{s_host.min():.4f}, {s_host.max():.4f}]", flush=True)
+    assert np.all(err <= 0)
 
 
 @pytest.mark.parametrize("odt", [torch.float16, torch.bfloat16])
@@ -548,6 +575,36 @@ def test_batched_single_mesh_converged_and_empty_rhs(ctx):
     assert rep[1]["restarts"] >= 1
 
 
+def test_gmres_max_iter_reports_not_converged(ctx):
+    """Failure handling: with max_iter = 1 the solve stops after one Arnoldi
+    step and returns EL_WARN_NOT_CONVERGED; the report says so, and its
+    relative residual is the true residual of the trace it returned
+    (recomputed here with the oracle's product)."""
+    from paper_2308_02467_amd import el
+    p, n_a = 3, 8
+    d = el.disc(p, n_a)
+    nn, n, m = el.disc_sizes(d)
+    od, oms, hh, kap, sig = mesh_problem(p, n_a, 4, 4, field="const")
+    i2o_np, _, _ = local_solve_batch(od, hh, kap, sig)
+    i2o = T(i2o_np)
+    ms = el.mesh(4, 4, oms.h)
+    nt = el.trace_size(d, ms)
+    b = torch.empty(nt, dtype=torch.float64, device=DEV)
+    ctx.el_trace_rhs(d, ms, inputs.left_inflow(n_a), b)
+    for basis in (torch.float64, torch.float32):
+        t = torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV)
+        print(f"[gmres max_iter=1] basis {basis}", flush=True)
+        st, rep = ctx.el_trace_solve(d, [ms], [i2o], [b], [t], tol=1e-12, restart=10, max_iter=1, basis=basis)
+        assert st == el.EL_WARN_NOT_CONVERGED
+        assert rep[0]["iters"] == 1 and not rep[0]["converged"]
+        ind, outd = oms.element_dofs(od)
+        bn = b.cpu().numpy()
+        res = np.linalg.norm(bn - otrace.matvec(i2o_np, ind, outd, t.cpu().numpy())) / np.linalg.norm(bn)
+        print(f"[gmres max_iter=1] reported {rep[0]['relres']:.6e}, recomputed {res:.6e}", flush=True)
+        assert 1e-12 < res < 1.0
+        assert abs(rep[0]["relres"] - res) <= 1e-12 * res + 1e-15
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
 def test_conserve_in2mean_form(ctx, dtype):
     """The balance with the ordinate-averaged operator: exact (in2out, in2mean)
@@ -568,14 +625,17 @@ def test_conserve_in2mean_form(ctx, dtype):
     assert rel_err(O.to(torch.float64).cpu().numpy(), i2o) <= CONSERVE_KEEP[dtype]
     rng = np.random.default_rng(2)
     Op = T(i2o * (1 + 0.02 * rng.standard_normal(i2o.shape))).to(dtype)
+    P = Op.to(torch.float64).cpu().numpy()
     ctx.el_conserve(d, T(h), T(kap), Op, in2mean=Mn)
     got = Op.to(torch.float64).cpu().numpy()
     ab = n_a * np.einsum("n,enm->em", o.W, (0.5 * h[:, None, None] * kap[:, :, None]) * Mn.to(torch.float64).cpu().numpy())
     bal = np.einsum("o,eom->em", wout, got) + ab - win[None, :]
     assert np.abs(bal).max() <= tol * np.abs(win).max()
+    _check_column_scaling(got, P, _column_factors(win[None, :] - ab, np.einsum("o,eom->em", wout, P)), dtype)
 
 
-def test_batched_full_size_sampled_and_energy(ctx):
+@pytest.mark.parametrize("basis", [torch.float64, torch.float32])
+def test_batched_full_size_sampled_and_energy(ctx, basis):
     """The batched workload at its real sizes (meshes of 16^2 ... 128^2
     elements, p = 6, N_a = 16, sharp cloud edge): one local solve over all
     53,760 elements and one GMRES over the eight skeleton systems.  Checked
@@ -609,8 +669,9 @@ def test_batched_full_size_sampled_and_energy(ctx):
         ctx.el_trace_rhs(d, ms, gs, b)
         meshes.append(ms); bs.append(b); ts.append(torch.empty_like(b))
     ops = [i2o[offs[i]:offs[i + 1]] for i in range(len(sides))]
-    print("[batched full] one GMRES over 8 meshes", flush=True)
-    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=1e-11, restart=50, max_iter=20000)
+    print(f"[batched full] one GMRES over 8 meshes, basis {basis}", flush=True)
+    st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=1e-11, restart=50, max_iter=20000, basis=basis)
+    print(f"[batched full] iterations {[r['iters'] for r in rep]}", flush=True)
     assert st == 0 and all(r["converged"] and r["relres"] <= 1e-11 for r in rep), rep
     rng = np.random.default_rng(5)
     sel = np.sort(rng.choice(E, 6, replace=False))

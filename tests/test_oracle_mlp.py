@@ -145,3 +145,33 @@ def test_linear_network_is_one_affine_map():
         c = W @ c + b
     out, _ = net.forward(X)
     assert np.abs(out - (X @ A.T + c)).max() < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["gelu", "elu", "linear"])
+def test_bf16_emulation_inside_fp64_definition_bounds(kind):
+    """The running error bounds used by the GPU tests (tests/_netbound.py)
+    hold for the oracle's own emulation of the kernels' bfloat16 rounding
+    points: forward outputs and (with targets far from the outputs, so the
+    MAE signs agree) every gradient in loss units."""
+    import _netbound as nb
+    rng = np.random.default_rng(7)
+    n_in, width, depth, n_out, B = 11, 48, 3, 40, 30
+    net = _rand_mlp(rng, 16, width, depth, n_out, kind)
+    net.Ws[0][:, n_in:] = 0.0
+    h = rng.uniform(0.005, 0.1, (B, 1))
+    x = np.concatenate([h, rng.uniform(0.01, 3, (B, 5)), rng.uniform(0.05, 30, (B, 5))], axis=1)
+    fm, fs = rng.uniform(-2, 0, n_in), rng.uniform(0.5, 2, n_in)
+    X0 = features(x, fm, fs, 16)
+    e0 = nb.feature_bound(x, fm, fs, 16)
+    assert np.all(np.abs(bf16_round(X0) - X0) <= e0)
+    out, Xs, Zs, e_out, e_xs, e_zs = nb.forward_bounds(net, X0, e0)
+    ob, _ = net.forward(X0, bf16=True)
+    assert np.all(np.abs(ob - out) <= e_out)
+    sgn = rng.choice([-1.0, 1.0], (B, n_out))
+    tgt = out + sgn * 50.0
+    _, gWb, gbb = net.mae_grad(X0, tgt, bf16=True)
+    count = B * n_out
+    gW, gb, eW, eb = nb.grad_bounds(net, Xs, Zs, e_xs, e_zs, -sgn)
+    for l in range(depth + 1):
+        assert np.all(np.abs(gWb[l] * count - gW[l]) <= eW[l]), l
+        assert np.all(np.abs(gbb[l] * count - gb[l]) <= eb[l] + 1e-12 * (np.abs(gb[l]) + B)), l
