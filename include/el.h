@@ -358,6 +358,29 @@ el_status el_infer(el_ctx* ctx, const el_net* net, el_disc d, int64_t E, const d
                    const double* kappa, const double* sigma, void* in2out, void* in2vol, int out_dtype,
                    uint8_t* in_range, int fallback, int precision, int64_t* n_fallback_host);
 
+/* ---- allocation-free inference ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  el_infer
+ * without the plain-solver fallback that allocates nothing (no hipMalloc or
+ * hipFree, no workspace growth, no autotuner timing) and does not
+ * synchronize the stream.  Its scratch is one static 64 MiB device array
+ * per GPU, resolved by el_create and held until the process ends.  The
+ * elements are processed in passes of as many elements as the array holds
+ * for this network (2 (k0 + depth width) bytes per element, rounded down to
+ * a multiple of 256, at most 16,384 per pass); EL_ERR_ARG when fewer than
+ * 256 fit (a network too wide or deep for the array).  The GEMM block tile
+ * is fixed (256 x 256 direct-to-LDS where the operands allow it, else
+ * 128 x 128), so outputs may differ from el_infer's in the last FP32 bits
+ * where el_infer's autotuner chose another tile.  Every call on one GPU
+ * shares that GPU's array and overwrites what the last call left there:
+ * calls that overlap on one GPU (several streams or contexts) race, so
+ * order them on one stream.  in2out, in2vol, out_dtype as in el_infer;
+ * in_range [E] (may be NULL) receives the training-box mask, and elements
+ * outside the box keep the network's output (no fallback). */
+el_status el_infer_noalloc(el_ctx* ctx, const el_net* net, el_disc d, int64_t E, const double* h,
+                           const double* kappa, const double* sigma, void* in2out, void* in2vol, int out_dtype,
+                           uint8_t* in_range);
+
 #ifdef __cplusplus
 }
 #endif

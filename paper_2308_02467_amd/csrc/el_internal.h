@@ -91,6 +91,9 @@ el_status set_error(el_ctx* ctx, el_status code, const std::string& msg);
 el_status hip_check(el_ctx* ctx, hipError_t e, const char* what);
 el_status get_disc(el_ctx* ctx, const el_disc& d, el_ctx::DiscEntry** out);
 el_status ensure_ws(el_ctx* ctx, Workspace& ws, size_t bytes);
+// resolves the device address of the allocation-free entry point's static
+// scratch on ctx's device (once per device; the device must be current)
+el_status noalloc_init(el_ctx* ctx);
 
 // launchers implemented in the .hip files
 el_status launch_local_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E,

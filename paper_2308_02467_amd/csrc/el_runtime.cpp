@@ -117,6 +117,8 @@ el_status el_create(el_ctx** ctx, int device, void* hip_stream) {
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+  el_status st = noalloc_init(c);
+  if (st) { delete c; return st; }
   *ctx = c;
   return EL_OK;
 }

@@ -934,21 +934,63 @@ Box make_box(const el_net* net) {
   return b;
 }
 
-// hidden layers: X0 -> H[depth-1]; Z saved when save_z
-el_status forward_hidden(el_ctx* ctx, el_net* net, int64_t B, const Scratch& s, bool save_z) {
+// Block tile of a k-contiguous GEMM without the autotuner (no timing, no
+// host-side state): the 256 x 256 direct-to-LDS tile where it applies, else
+// 128 x 128.
+inline int fixed_variant(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t K) {
+  return variant_applies<true, true>(3, A, lda, B, ldb, K, 1) ? 3 : 0;
+}
+
+// hidden layers: X0 -> H[depth-1]; Z saved when save_z; tiles autotuned, or
+// fixed by fixed_variant() when no_tune
+el_status forward_hidden(el_ctx* ctx, el_net* net, int64_t B, const Scratch& s, bool save_z, bool no_tune = false) {
   const int64_t W = net->desc.width;
   for (int l = 0; l < net->desc.depth; ++l) {
     const uint16_t* X = l == 0 ? s.X0 : s.H + (size_t)(l - 1) * B * W;
     const int64_t in = net->in_dim[l];
+    const uint16_t* Wl = net->wbf + net->w_off[l];
     EpiHidden epi{net->theta + net->b_off[l], save_z ? s.Z + (size_t)l * B * W : nullptr, s.H + (size_t)l * B * W, W,
                   net->desc.act};
-    el_status st = mm<true, true>(ctx, X, in, net->wbf + net->w_off[l], in, B, W, in, 1, epi);
+    el_status st = no_tune ? mm_variant<true, true>(ctx, fixed_variant(X, in, Wl, in, in), X, in, Wl, in, B, W, in, 1,
+                                                    epi, false)
+                           : mm<true, true>(ctx, X, in, Wl, in, B, W, in, 1, epi);
     if (st) return st;
   }
   return EL_OK;
 }
 
 }  // namespace
+
+// ---- allocation-free inference: the static scratch array ----------------------
+// One array per GPU the library runs on, held until the process ends.  Host
+// code never uses its name as an address: noalloc_init() resolves the
+// device address once per device and the entry point passes that pointer
+// to the kernels.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+
+}  // namespace el
+
+static __device__ __align__(256) unsigned char scratch[el::kNoAllocBytes];
+
+namespace el {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+el_status noalloc_init(el_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return set_error(ctx, EL_ERR_ARG, "el_create: device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[ctx->device]) return EL_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return hip_check(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+  g_noalloc_ptr[ctx->device] = p;
+  return EL_OK;
+}
 
 el_status launch_local_solve_ex(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
                                 const double* kappa, const double* sigma, const int32_t* emap, void* o_i2o,
@@ -1305,6 +1347,76 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
   }
   if (n_fallback_host) *n_fallback_host = nfb;
   return st;
+}
+
+el_status el_infer_noalloc(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const double* h,
+                           const double* kappa, const double* sigma, void* in2out, void* in2vol, int out_dtype,
+                           uint8_t* in_range) {
+  if (!ctx || !cnet) return EL_ERR_ARG;
+  if (E <= 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: bad argument");
+  if (out_dtype != EL_BF16 && out_dtype != EL_F32 && out_dtype != EL_F16)
+    return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: out_dtype");
+  int64_t nn = 0, n = 0, m = 0;
+  if (el_disc_sizes(d, &nn, &n, &m) != EL_OK) return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: bad el_disc");
+  el_net* net = const_cast<el_net*>(cnet);
+  const int64_t mm_ = m * m;
+  if (net->desc.n_out != mm_ + n * m && net->desc.n_out != mm_ + nn * m)
+    return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: network output size does not match the discretization");
+  if (net->desc.n_in != 1 + 2 * nn)
+    return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: network input size does not match the discretization");
+  if (!net->fitted) return set_error(ctx, EL_ERR_STATE, "el_infer_noalloc: network has no training statistics");
+  hipSetDevice(ctx->device);
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    base = reinterpret_cast<char*>(g_noalloc_ptr[ctx->device]);
+  }
+  if (!base) return set_error(ctx, EL_ERR_STATE, "el_infer_noalloc: static scratch not initialized on this device");
+  const int D = net->desc.depth;
+  const int64_t W = net->desc.width, k0 = net->k0, nm = net->desc.n_out - mm_;
+  // rows per pass: features [rows][k0] and hidden activations [D][rows][W]
+  // (bfloat16) in the static array, a multiple of 256 rows
+  const int64_t row_bytes = 2 * (k0 + (int64_t)D * W);
+  const int64_t fit = (int64_t)(kNoAllocBytes / (size_t)row_bytes) / 256 * 256;
+  if (fit < 256) {
+    std::ostringstream os;
+    os << "el_infer_noalloc: the network needs " << row_bytes << " B of scratch per element; the "
+       << (kNoAllocBytes >> 20) << " MiB static scratch holds fewer than 256 elements";
+    return set_error(ctx, EL_ERR_ARG, os.str());
+  }
+  const int64_t rows = std::min<int64_t>(fit, 16384);
+  const size_t osz = out_dtype == EL_F32 ? 4 : 2;
+  for (int64_t e0 = 0; e0 < E; e0 += rows) {
+    const int64_t B = std::min(rows, E - e0);
+    Scratch s{};
+    s.X0 = reinterpret_cast<uint16_t*>(base);
+    s.H = reinterpret_cast<uint16_t*>(base + (size_t)rows * k0 * 2);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)B), dim3(128), 0, ctx->stream, nullptr, h + e0,
+                       kappa + e0 * nn, sigma + e0 * nn, B, net->desc.n_in, net->k0, net->feat_mean,
+                       net->feat_std, s.X0, make_box(net), in_range ? in_range + e0 : nullptr);
+    el_status st = forward_hidden(ctx, net, B, s, false, true);
+    if (st) return st;
+    char* po = in2out ? reinterpret_cast<char*>(in2out) + (size_t)e0 * mm_ * osz : nullptr;
+    char* ps = in2vol ? reinterpret_cast<char*>(in2vol) + (size_t)e0 * nm * osz : nullptr;
+    const uint16_t* Hl = s.H + (size_t)(D - 1) * B * W;
+    const uint16_t* WD = net->wbf + net->w_off[D];
+    const int v = fixed_variant(Hl, W, WD, W, W);
+    if (out_dtype == EL_F32) {
+      EpiOutOps<float> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<float*>(po),
+                           reinterpret_cast<float*>(ps), mm_, nm};
+      st = mm_variant<true, true>(ctx, v, Hl, W, WD, W, B, net->desc.n_out, W, 1, epi, true);
+    } else if (out_dtype == EL_F16) {
+      EpiOutOps<_Float16> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<_Float16*>(po),
+                              reinterpret_cast<_Float16*>(ps), mm_, nm};
+      st = mm_variant<true, true>(ctx, v, Hl, W, WD, W, B, net->desc.n_out, W, 1, epi, true);
+    } else {
+      EpiOutOps<uint16_t> epi{net->theta + net->b_off[D], net->y_mean, net->y_std, reinterpret_cast<uint16_t*>(po),
+                              reinterpret_cast<uint16_t*>(ps), mm_, nm};
+      st = mm_variant<true, true>(ctx, v, Hl, W, WD, W, B, net->desc.n_out, W, 1, epi, true);
+    }
+    if (st) return st;
+  }
+  return hip_check(ctx, hipGetLastError(), "el_infer_noalloc");
 }
 
 el_status el_gemm_tile(int variant) {

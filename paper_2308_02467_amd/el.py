@@ -124,6 +124,9 @@ _SIGS = {
     "el_infer": [ctypes.c_void_p, ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                  ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
+    "el_infer_noalloc": [ctypes.c_void_p, ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                         ctypes.c_void_p],
 }
 
 
@@ -465,6 +468,16 @@ class Net:
                                        _ptr(in_range, torch.uint8, E, "in_range"), int(bool(fallback)),
                                        int(precision), ctypes.byref(nfb)))
         return nfb.value
+
+    def infer_noalloc(self, d, h, kappa, sigma, in2out=None, in2sol=None, in_range=None, in2mean=None):
+        """el_infer_noalloc: no fallback, no allocation, no synchronization."""
+        E, dt, vol = self._infer_args(d, h, in2out, in2sol, in2mean)
+        nn, _, _ = disc_sizes(d)
+        self.ctx._check(lib().el_infer_noalloc(self.ctx.h, self.h, d, E, _ptr(h, torch.float64, E, "h"),
+                                               _ptr(kappa, torch.float64, E * nn, "kappa"),
+                                               _ptr(sigma, torch.float64, E * nn, "sigma"),
+                                               _ptr(in2out, name="in2out"), _ptr(vol, name="in2vol"), int(dt),
+                                               _ptr(in_range, torch.uint8, E, "in_range")))
 
     def _infer_args(self, d, h, in2out, in2sol, in2mean):
         nn, n, m = disc_sizes(d)
