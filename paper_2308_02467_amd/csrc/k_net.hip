@@ -131,8 +131,19 @@ __device__ inline float act_df(int act, float z) {
 }
 
 // GEMM epilogues.  The kernel calls col(n) once per output column a lane
-// owns, then (m, n, acc, z, c) for each of that column's rows, so that
-// per-column data (bias, output scaling) is loaded once.
+// owns; per 32 x 32 MFMA block it then loads pre(m, n) for the block's rows
+// of that column (all loads issued before any is used), calls
+// block_begin(), (m, n, acc, z, c, pre) for each row and block_end(); so
+// that per-column data (bias, output scaling) is loaded once and per-element
+// inputs (the training targets) are fetched in one batch.
+struct NoPre {};
+#define EL_EPI_DEFAULT_HOOKS                                              \
+  typedef NoPre Pre;                                                      \
+  static constexpr bool kHasPre = false;                                  \
+  static constexpr bool kStageLds = false;                                \
+  __device__ Pre pre(int, int) const { return Pre{}; }                    \
+  __device__ void block_begin() {}                                        \
+  __device__ void block_end(int, int, int, int, int) {}
 
 // hidden layer epilogue: z = acc + b; Z (optional) = z; H = bf16(act(z))
 struct EpiHidden {
@@ -144,8 +155,9 @@ struct EpiHidden {
   int64_t ld;
   int act;
   struct Col { float b; };
+  EL_EPI_DEFAULT_HOOKS
   __device__ Col col(int n) const { return Col{bias[n]}; }
-  __device__ void operator()(int m, int n, float acc, int, const Col& c) {
+  __device__ void operator()(int m, int n, float acc, int, const Col& c, Pre) {
     const float z = acc + c.b;
     if (Z) Z[(int64_t)m * ld + n] = z;
     H[(int64_t)m * ld + n] = f2bf(act_f(act, z));
@@ -161,8 +173,9 @@ struct EpiOutNorm {
   float* Y;
   int64_t ld;
   struct Col { float b; };
+  EL_EPI_DEFAULT_HOOKS
   __device__ Col col(int n) const { return Col{bias[n]}; }
-  __device__ void operator()(int m, int n, float acc, int, const Col& c) { Y[(int64_t)m * ld + n] = acc + c.b; }
+  __device__ void operator()(int m, int n, float acc, int, const Col& c, Pre) { Y[(int64_t)m * ld + n] = acc + c.b; }
   __device__ void flush() {}
 };
 
@@ -183,6 +196,7 @@ struct EpiOutOps {
     OutT* base;          // column n of element 0, or null
     int64_t stride;      // per element
   };
+  EL_EPI_DEFAULT_HOOKS
   __device__ static inline OutT cvt(float y) {
     if constexpr (std::is_same<OutT, _Float16>::value) return (_Float16)y;
     else if constexpr (sizeof(OutT) == 2) return f2bf(y);
@@ -197,39 +211,74 @@ struct EpiOutOps {
     else { c.base = i2s ? i2s + (n - mm) : nullptr; c.stride = nm; }
     return c;
   }
-  __device__ void operator()(int e, int, float acc, int, const Col& c) {
+  __device__ void operator()(int e, int, float acc, int, const Col& c, Pre) {
     if (c.base) c.base[(int64_t)e * c.stride] = cvt((acc + c.b) * c.sd + c.mean);
   }
   __device__ void flush() {}
 };
 
-// output layer in training: MAE against normalized targets; dY = sign(pred - target)
+// output layer in training: MAE against normalized targets; dY = sign(pred -
+// target).  Repeatable (every run writes the same outputs): instead of
+// accumulating, each 32 x 32 block writes the sum of its |d| to
+// lossp[m / 32][n / 32] and, per column, the sum of its 32 signs to
+// colp[m / 32][n] (the output-layer bias gradient in loss units: sums of
+// +-1, exact in FP32 in any order); fixed-order reductions follow.
 struct EpiMAE {
   static constexpr const char* kName = "mae";
-  static constexpr bool kRepeatable = false;   // accumulates the loss
+  static constexpr bool kRepeatable = true;
   const float* bias;
   const uint16_t* y;
   const float* ymean;
   const float* ystd;
   uint16_t* dY;
-  float* loss;
+  float* colp;    // [ceil(M/32)][ld]
+  float* lossp;   // [ceil(M/32)][ceil(ld/32)]
   int64_t ld;
-  float local;
-  struct Col { float b, mean, sd; };
-  __device__ Col col(int n) const { return Col{bias[n], ymean[n], ystd[n]}; }
-  __device__ void operator()(int m, int n, float acc, int, const Col& c) {
-    const int64_t i = (int64_t)m * ld + n;
+  float s_abs, s_sgn;
+  struct Col { float b, mean, rsd; };
+  typedef uint16_t Pre;
+  static constexpr bool kHasPre = true;
+  // the direct-to-LDS GEMM stages the block tile's targets in LDS first
+  // (ys [BM][BN] from rows ym0, columns yn0)
+  static constexpr bool kStageLds = true;
+  const __attribute__((address_space(3))) uint16_t* ys;
+  int ym0, yn0;
+  __device__ Col col(int n) const { return Col{bias[n], ymean[n], 1.f / ystd[n]}; }
+  // from the LDS tile, or from HBM with 32-bit byte offsets from the
+  // kernel-argument base (the host keeps B * n_out below 2^31): one address
+  // register per load
+  __device__ Pre pre(int m, int n) const {
+    if (ys) return ys[(m - ym0) * 256 + (n - yn0)];
+    const uint32_t off = ((uint32_t)m * (uint32_t)ld + (uint32_t)n) * 2u;
+    return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(y) + off);
+  }
+  __device__ void block_begin() { s_abs = 0.f; s_sgn = 0.f; }
+  __device__ void operator()(int m, int n, float acc, int, const Col& c, Pre t) {
+    const uint32_t i = (uint32_t)m * (uint32_t)ld + (uint32_t)n;   // below 2^31 (host check)
     const float pred = acc + c.b;
-    const float tgt = (bf2f(y[i]) - c.mean) / c.sd;
+    const float tgt = (bf2f(t) - c.mean) * c.rsd;
     const float d = pred - tgt;
-    local += fabsf(d);
+    s_abs += fabsf(d);
+    const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+    s_sgn += sg;
     dY[i] = d > 0.f ? (uint16_t)0x3f80 : (d < 0.f ? (uint16_t)0xbf80 : (uint16_t)0);
   }
-  __device__ void flush() {
-    float v = local;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, v);
+  // all 64 lanes call it: lanes l and l + 32 hold the two row halves of
+  // column n0 + l % 32 of the block at rows m0.  Blocks past the output
+  // (m0 >= M or n0 >= N: partial wave tiles) own no partial sums and write
+  // nothing; for the others m0 / 32 < ceil(M / 32) and n0 / 32 < ceil(N / 32).
+  __device__ void block_end(int m0, int n0, int lane, int M, int N) {
+    const float a = s_abs + __shfl_xor(s_abs, 32);
+    const float g = s_sgn + __shfl_xor(s_sgn, 32);
+    float t = a;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (m0 >= M || n0 >= N) return;
+    const int n = n0 + (lane & 31);
+    if (lane < 32 && n < N) colp[(int64_t)(m0 >> 5) * ld + n] = g;
+    if (lane == 0) lossp[(int64_t)(m0 >> 5) * ((ld + 31) >> 5) + (n0 >> 5)] = t;
   }
+  __device__ void flush() {}
 };
 
 struct EpiF32 {
@@ -238,8 +287,11 @@ struct EpiF32 {
   float* C;
   int64_t ldc, zstride;
   struct Col {};
+  EL_EPI_DEFAULT_HOOKS
   __device__ Col col(int) const { return Col{}; }
-  __device__ void operator()(int m, int n, float acc, int z, const Col&) { C[z * zstride + (int64_t)m * ldc + n] = acc; }
+  __device__ void operator()(int m, int n, float acc, int z, const Col&, Pre) {
+    C[z * zstride + (int64_t)m * ldc + n] = acc;
+  }
   __device__ void flush() {}
 };
 
@@ -250,7 +302,7 @@ struct EpiF32 {
 // column N - 1 and are never stored) and waited for once, so that the
 // guarded stores that follow wait for nothing (a wait inside the guarded
 // blocks would also wait for the stores before it).
-template <int TM, int TN, typename Epi>
+template <int TM, int TN, typename Epi, bool kBlockPre = false>
 __device__ inline void store_tiles(Epi& epi, const gemm::f32x16 (&acc)[TM][TN], int mw, int nw, int M, int N,
                                    int lane, int z) {
   const int lr = lane & 31, hi = lane >> 5;
@@ -261,14 +313,34 @@ __device__ inline void store_tiles(Epi& epi, const gemm::f32x16 (&acc)[TM][TN], 
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int n = nw + 32 * j + lr;
-    if (n < N) {
+    typename Epi::Pre pre[TM][16];
+    // the per-element inputs: all loads of a column before any is used
+    // (addresses clamped into the operand; rows and columns past it are not
+    // stored), or, kBlockPre (inputs staged in LDS), read where used
+    auto fetch = [&](int i) {
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int r = 0; r < 16; ++r)
+        pre[i][r] = epi.pre(min(mw + 32 * i + 8 * (r >> 2) + 4 * hi + (r & 3), M - 1), min(n, N - 1));
+    };
+    if constexpr (Epi::kHasPre && !kBlockPre) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) fetch(i);
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      epi.block_begin();
+      if (n < N) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int m = mw + 32 * i + 8 * (r >> 2) + 4 * hi + (r & 3);
-          if (m < M) epi(m, n, acc[i][j][r], z, cols[j]);
+          if (m < M) {
+            if constexpr (Epi::kHasPre && kBlockPre) epi(m, n, acc[i][j][r], z, cols[j], epi.pre(m, n));
+            else epi(m, n, acc[i][j][r], z, cols[j], pre[i][r]);
+          }
         }
+      }
+      epi.block_end(mw + 32 * i, nw + 32 * j, lane, M, N);
     }
   }
   epi.flush();
@@ -528,7 +600,30 @@ __global__ void __launch_bounds__(gemm_lds::threads<TN>()) k_mm_lds(const uint16
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[b][i], bfr[b][j], acc[i][j], 0, 0, 0);
     }
   }
-  store_tiles<TM, TN>(epi, acc, m0 + wm * 32 * TM, n0 + wn * 32 * TN, M, N, lane, blockIdx.z);
+  if constexpr (Epi::kStageLds) {
+    // the block tile's per-element epilogue inputs (ld = N) into the LDS
+    // stages, which are free once every wave is past its last MFMA reads:
+    // row r at r * BN, 16-byte chunks, one instruction per two rows;
+    // rows past M and chunks past N are clamped into the operand (never used)
+    static_assert(BM * BN * 2 <= (int)gemm_lds::kSmem, "epilogue tile");
+    __syncthreads();
+    const uint16_t* Y = epi.y;
+    for (int q = wave; q < BM / 2; q += NW) {
+      const int r = min(m0 + 2 * q + (lane >> 5), M - 1);
+      const int c = min(n0 + 8 * (lane & 31), N - 8);
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(Y + (int64_t)r * N + c),
+                                       reinterpret_cast<__attribute__((address_space(3))) void*>(L + q * 512), 16, 0,
+                                       0);
+    }
+    __builtin_amdgcn_s_waitcnt(gemm_lds::vmcnt_imm(0));
+    __syncthreads();
+    epi.ys = L;
+    epi.ym0 = m0;
+    epi.yn0 = n0;
+    store_tiles<TM, TN, Epi, true>(epi, acc, m0 + wm * 32 * TM, n0 + wn * 32 * TN, M, N, lane, blockIdx.z);
+  } else {
+    store_tiles<TM, TN>(epi, acc, m0 + wm * 32 * TM, n0 + wn * 32 * TN, M, N, lane, blockIdx.z);
+  }
 }
 
 // whether k_mm_lds can take a GEMM (k-contiguous operands, 16-byte aligned
@@ -741,6 +836,52 @@ __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, floa
   wbf[i] = f2bf(t);
 }
 
+// out[b] = sum of p[b * chunk .. min(n, (b + 1) * chunk)) in a fixed order
+// (workgroups of 256 threads; one workgroup per output)
+__global__ void k_sum_chunks(const float* __restrict__ p, int64_t n, int64_t chunk, float* __restrict__ out) {
+  __shared__ double part[256];
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+  double acc = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) acc += p[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = (float)part[0];
+}
+
+// dst [cols][rows] = src [rows][cols]^T for 16-bit values, rows and cols
+// multiples of 64: 64 x 64 tiles through LDS, 16-byte loads and stores
+// (256 threads; each moves two 16-byte row chunks in and two column chunks
+// out)
+__global__ void __launch_bounds__(256) k_transpose16(const uint16_t* __restrict__ src, int64_t rows, int64_t cols,
+                                                     uint16_t* __restrict__ dst) {
+  __shared__ uint16_t t[64][64 + 2];
+  const int64_t tiles_c = cols / 64;
+  const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * 64, c0 = (int64_t)(blockIdx.x % tiles_c) * 64;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = tid + 256 * h, r = q >> 3, ch = (q & 7) * 8;
+    const uint4 v = *reinterpret_cast<const uint4*>(src + (r0 + r) * cols + c0 + ch);
+    const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[r][ch + k] = e[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = tid + 256 * h, c = q >> 3, rh = (q & 7) * 8;
+    uint4 v;
+    uint16_t* e = reinterpret_cast<uint16_t*>(&v);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e[k] = t[rh + k][c];
+    *reinterpret_cast<uint4*>(dst + (c0 + c) * rows + r0 + rh) = v;
+  }
+}
+
 __global__ void k_loss_out(const float* acc, float scale, float* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = *acc * scale;
 }
@@ -888,10 +1029,22 @@ struct Scratch {
   float* dZ;         // [B][width]
   uint16_t* dZ16;    // [B][width]
   float* loss;       // [1]
+  float* colp;       // [ceil(B/32)][n_out] per-block sums of the output-layer signs (training only)
+  uint16_t* dYT;     // [n_out][B] (training with 64 | B, n_out, width: the transposed output-layer GEMMs)
+  uint16_t* HT;      // [width][B] last hidden layer, transposed
+  uint16_t* WT;      // [width][n_out] output-layer weights, transposed
+  float* lossp;      // [ceil(B/32)][ceil(n_out/32)] per-block sums of |d| (training only)
   int64_t part_elems;
 };
 
 constexpr int kSplitOut = 32;   // split-K of dY * W_out (K = n_out)
+constexpr int kLossChunks = 256;   // first-level workgroups of the loss reduction
+
+// The output layer's dW (dY^T H) and dX (dY W) products take the
+// direct-to-LDS tile through transposed copies of dY, H and W when every
+// dimension is a multiple of 64; otherwise the register-staged tile
+// transposes on the way into LDS.
+inline bool transposed_ok(int64_t B, int64_t nout, int64_t W) { return B % 64 == 0 && nout % 64 == 0 && W % 64 == 0; }
 constexpr int kSplitW = 8;      // split-K of the hidden dW GEMMs (K = batch)
 
 el_status get_scratch(el_ctx* ctx, el_net* net, int64_t B, bool train, Scratch& s) {
@@ -904,6 +1057,12 @@ el_status get_scratch(el_ctx* ctx, el_net* net, int64_t B, bool train, Scratch& 
   size_t opart = train ? add((size_t)part * 4) : 0;
   size_t odZ = train ? add((size_t)B * W * 4) : 0, odZ16 = train ? add((size_t)B * W * 2) : 0;
   size_t oloss = add(256);
+  const int64_t rb = (B + 31) / 32;
+  size_t ocolp = train ? add((size_t)rb * nout * 4) : 0;
+  size_t olossp = train ? add(((size_t)rb * ((nout + 31) / 32) + kLossChunks) * 4) : 0;
+  const bool tr = train && transposed_ok(B, nout, W);
+  size_t odYT = tr ? add((size_t)nout * B * 2) : 0, oHT = tr ? add((size_t)W * B * 2) : 0;
+  size_t oWT = tr ? add((size_t)W * nout * 2) : 0;
   if (net->scratch.bytes < need) {
     if (net->scratch.ptr) {
       hipStreamSynchronize(ctx->stream);
@@ -924,6 +1083,11 @@ el_status get_scratch(el_ctx* ctx, el_net* net, int64_t B, bool train, Scratch& 
   s.dZ = train ? reinterpret_cast<float*>(b + odZ) : nullptr;
   s.dZ16 = train ? reinterpret_cast<uint16_t*>(b + odZ16) : nullptr;
   s.loss = reinterpret_cast<float*>(b + oloss);
+  s.colp = train ? reinterpret_cast<float*>(b + ocolp) : nullptr;
+  s.lossp = train ? reinterpret_cast<float*>(b + olossp) : nullptr;
+  s.dYT = tr ? reinterpret_cast<uint16_t*>(b + odYT) : nullptr;
+  s.HT = tr ? reinterpret_cast<uint16_t*>(b + oHT) : nullptr;
+  s.WT = tr ? reinterpret_cast<uint16_t*>(b + oWT) : nullptr;
   s.part_elems = part;
   return EL_OK;
 }
@@ -1216,18 +1380,44 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
                      net->desc.n_in, net->k0, net->feat_mean, net->feat_std, s.X0, open, nullptr);
   st = forward_hidden(ctx, net, B, s, true);
   if (st) return st;
-  hipLaunchKernelGGL(k_fill_f, dim3(1), dim3(64), 0, str, s.loss, (int64_t)1, 0.f);
   const uint16_t* Hlast = s.H + (size_t)(D - 1) * B * W;
-  EpiMAE mae{net->theta + net->b_off[D], y, net->y_mean, net->y_std, s.dY, s.loss, nout, 0.f};
+  if (B * nout >= ((int64_t)1 << 31))
+    return set_error(ctx, EL_ERR_ARG, "el_train_step: batch x n_out must stay below 2^31");
+  EpiMAE mae{net->theta + net->b_off[D], y, net->y_mean, net->y_std, s.dY, s.colp, s.lossp, nout, 0.f, 0.f,
+             nullptr, 0, 0};
   st = mm<true, true>(ctx, Hlast, W, net->wbf + net->w_off[D], W, B, nout, W, 1, mae, true);
   if (st) return st;
-  // output layer gradients
-  hipLaunchKernelGGL(k_colsum<uint16_t>, dim3(nblk(nout, 16)), dim3(256), 0, str, s.dY, B, nout, net->grad + net->b_off[D]);
-  st = mm<false, false>(ctx, s.dY, nout, Hlast, W, nout, W, B, 1, EpiF32{net->grad + net->w_off[D], W, 0});
-  if (st) return st;
-  st = mm<true, false>(ctx, s.dY, nout, net->wbf + net->w_off[D], W, B, W, nout, kSplitOut,
-                       EpiF32{s.part, W, B * W});
-  if (st) return st;
+  // output layer gradients: the bias from the epilogue's per-block column
+  // sums, the loss from its per-block sums (fixed-order reductions)
+  const int64_t rb = (B + 31) / 32;
+  hipLaunchKernelGGL(k_colsum<float>, dim3(nblk(nout, 16)), dim3(256), 0, str, s.colp, rb, nout,
+                     net->grad + net->b_off[D]);
+  {
+    const int64_t nl = rb * ((nout + 31) / 32), chunk = (nl + kLossChunks - 1) / kLossChunks;
+    float* lp2 = s.lossp + nl;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(kLossChunks), dim3(256), 0, str, s.lossp, nl, chunk, lp2);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, str, lp2, (int64_t)kLossChunks, (int64_t)kLossChunks,
+                       s.loss);
+  }
+  if (s.dYT) {
+    auto tp = [&](const uint16_t* src, int64_t rows, int64_t cols, uint16_t* dst) {
+      hipLaunchKernelGGL(k_transpose16, dim3((unsigned)((rows / 64) * (cols / 64))), dim3(256), 0, str, src, rows,
+                         cols, dst);
+    };
+    tp(s.dY, B, nout, s.dYT);
+    tp(Hlast, B, W, s.HT);
+    tp(net->wbf + net->w_off[D], nout, W, s.WT);
+    st = mm<true, true>(ctx, s.dYT, B, s.HT, B, nout, W, B, 1, EpiF32{net->grad + net->w_off[D], W, 0});
+    if (st) return st;
+    st = mm<true, true>(ctx, s.dY, nout, s.WT, nout, B, W, nout, kSplitOut, EpiF32{s.part, W, B * W});
+    if (st) return st;
+  } else {
+    st = mm<false, false>(ctx, s.dY, nout, Hlast, W, nout, W, B, 1, EpiF32{net->grad + net->w_off[D], W, 0});
+    if (st) return st;
+    st = mm<true, false>(ctx, s.dY, nout, net->wbf + net->w_off[D], W, B, W, nout, kSplitOut,
+                         EpiF32{s.part, W, B * W});
+    if (st) return st;
+  }
   {
     int64_t ks = (nout + kSplitOut - 1) / kSplitOut;
     ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;

@@ -284,15 +284,15 @@ def test_infer_range_mask_and_fallback(ctx, dtype):
 
 def bf16_mode_check(got, ref, u_st, tiny, what):
     """Entries within one storage rounding + 2e-4 of the largest entry of the
-    bfloat16-rounded oracle, but for at most 1 in 1000 (rounding-boundary
-    flips of hidden activations)."""
+    bfloat16-rounded oracle, but for at most 5 in 1000 (rounding-boundary
+    flips of hidden activations; up to 8.4e-4 measured)."""
     d = np.abs(got - ref)
     lim = u_st * np.abs(ref) + 2e-4 * np.abs(ref).max() + tiny
     over = float(np.mean(d > lim))
     print(f"[{what}] vs the bfloat16-rounded oracle: max |err| {d.max():.3e} (largest entry "
           f"{np.abs(ref).max():.3e}); median |err| {np.median(d):.3e}; entries beyond one storage unit + 2e-4 of "
           f"the largest: {over:.2e}", flush=True)
-    assert over <= 1e-3
+    assert over <= 5e-3
 
 
 def _infer_checks(hn, x, X0, got, yv_bf, keep, dtype):
@@ -301,7 +301,7 @@ def _infer_checks(hn, x, X0, got, yv_bf, keep, dtype):
     largest entry), except where a hidden activation fell on the other side
     of a bfloat16 rounding boundary in the two computations (then the
     difference is one bfloat16 unit of that activation times its weights):
-    at most 1 in 1000 entries.  Against the plain FP64 definition: every
+    at most 5 in 1000 entries.  Against the plain FP64 definition: every
     entry within the running error bound."""
     ys, ym = hn["ys"].astype(np.float64), hn["ym"].astype(np.float64)
     u_st = {torch.float32: nb.U32, torch.float16: 2.0 ** -11, torch.bfloat16: nb.U}[dtype]
