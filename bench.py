@@ -93,6 +93,10 @@ def parse():
                          "(P0 cells, N_a=28, g=0.8, albedo 1, 800 training / 200 test fields, batch 50, "
                          "networks of 1-4 layers)")
     ap.add_argument("--pg-time-limit", type=float, default=60.0, help="training seconds per network")
+    ap.add_argument("--pg-schedule", choices=("time", "paper"), default="time",
+                    help="time: --pg-time-limit seconds per network (lr / 10 after 70 %%); paper: 3000 epochs each "
+                         "at lr 1e-3, 1e-4 and 1e-5 (Sec. 3.1)")
+    ap.add_argument("--pg-layers", default="1,2,3,4", help="network depths (layers) of the generator study")
     ap.add_argument("--pg-train", type=int, default=800, help="training fields of the generator study")
     ap.add_argument("--pg-floor", type=float, default=0.0,
                     help="constant added to every generated field (0: the generator as printed)")
@@ -468,14 +472,23 @@ def paper_generator_main(args):
     n_in = 1 + 2 * nn
     width = (2 * n_in + 7) // 8 * 8
     n_out = m * m + nn * m
+    # the floor set by the bfloat16 storage of the targets: the exact
+    # operators of the test fields rounded to bfloat16
+    fo = ((ref_o.to(torch.bfloat16).double() - ref_o).flatten(1).norm(dim=1) / ref_o.flatten(1).norm(dim=1))
+    fm = ((ref_m.to(torch.bfloat16).double() - ref_m).flatten(1).norm(dim=1) / ref_m.flatten(1).norm(dim=1))
+    floor = {"in2out_rel_l2_mean": float(fo.mean()), "in2mean_rel_l2_mean": float(fm.mean())}
     rows = []
-    for layers in (1, 2, 3, 4):
+    for layers in [int(v) for v in args.pg_layers.split(",")]:
         act = el.EL_ACT_LINEAR if layers == 1 else el.EL_ACT_ELU
         net = el.Net.create(ctx, n_in, width, max(1, layers - 1), n_out, act=act, seed=0)
         net.fit_normalization(x_tr, y_tr)
         t0 = time.perf_counter()
-        hist = learned.train(net, x_tr, y_tr, 100000, batch=50, lr=1e-3, time_limit=args.pg_time_limit,
-                             decay_at=0.7, log=False)
+        if args.pg_schedule == "paper":
+            hist = learned.train(net, x_tr, y_tr, 0, batch=50, schedule=[(3000, 1e-3), (3000, 1e-4), (3000, 1e-5)],
+                                 log=True, log_every=500)
+        else:
+            hist = learned.train(net, x_tr, y_tr, 100000, batch=50, lr=1e-3, time_limit=args.pg_time_limit,
+                                 decay_at=0.7, log=False)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         po = torch.empty((n_te, m, m), dtype=torch.float32, device=dev)
@@ -487,6 +500,8 @@ def paper_generator_main(args):
         rows.append({"layers": layers, "network": f"{n_in}-{width}x{max(1, layers - 1)}-{n_out} "
                      + ("linear" if layers == 1 else "ELU"), "epochs": len(hist),
                      "final_train_loss": hist[-1] if hist else None, "training_s": t_train,
+                     "train_loss_at_epochs": {str(e): hist[e - 1] for e in (1, 10, 100, 1000, 3000, 6000, 9000)
+                                              if e <= len(hist)},
                      "test_in2out_rel_l2_mean": float(eo.mean()), "test_in2out_rel_l2_median": float(np.median(eo)),
                      "test_in2mean_rel_l2_mean": float(em.mean())})
         log(f"paper generator: {layers} layers, test in2out error {eo.mean():.3e}")
@@ -494,7 +509,8 @@ def paper_generator_main(args):
     ctx.close()
     return {"study": "element training with the paper's coefficient generator", "p": p, "n_a": n_a,
             "angular": "p0", "g": 0.8, "albedo": 1.0, "train": n_tr, "test": n_te, "batch": 50,
-            "a_sigma": 10.0, "c_sm": 2.0, "floor": args.pg_floor, "networks": rows}
+            "a_sigma": 10.0, "c_sm": 2.0, "floor": args.pg_floor, "schedule": args.pg_schedule,
+            "bf16_target_rounding_floor": floor, "networks": rows}
 
 
 def cloud_main(args):

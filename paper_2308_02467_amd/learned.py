@@ -42,10 +42,14 @@ def training_set(ctx, d, N, seed=1234, chunk=8192, log=True, form=el.EL_FORM_IN2
     return x, y
 
 
-def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=None, decay_at=0.0):
+def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=None, decay_at=0.0,
+          schedule=None, log_every=1):
     """Adam on the MAE loss; returns the per-epoch mean loss (normalized units).
     decay_at in (0, 1): lr is divided by 10 after that fraction of the epochs
-    (or of the time limit), as in the paper's stepwise schedule (Sec. 3.1)."""
+    (or of the time limit), as in the paper's stepwise schedule (Sec. 3.1).
+    schedule: a list of (epochs, lr) segments run one after the other (it
+    replaces epochs, lr and decay_at), e.g. the paper's 3000 epochs each at
+    1e-3, 1e-4 and 1e-5."""
     N = x.shape[0]
     nb = N // batch
     rng = np.random.default_rng(seed)
@@ -53,17 +57,21 @@ def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=N
     acc = torch.zeros(1, dtype=torch.float32, device=x.device)
     hist = []
     t0 = time.perf_counter()
+    lrs = None
+    if schedule is not None:
+        lrs = [l for (n_ep, l) in schedule for _ in range(n_ep)]
+        epochs = len(lrs)
     for ep in range(epochs):
         acc.zero_()
         elapsed = time.perf_counter() - t0
         late = decay_at > 0 and (ep >= decay_at * epochs or (time_limit and elapsed >= decay_at * time_limit))
-        lr_ep = lr * 0.1 if late else lr
+        lr_ep = lrs[ep] if lrs is not None else (lr * 0.1 if late else lr)
         for b in rng.permutation(nb):
             b0 = int(b) * batch
             net.train_step(x[b0:b0 + batch], y[b0:b0 + batch], lr_ep, loss)
             acc += loss
         hist.append(acc.item() / nb)
-        if log:
+        if log and ((ep + 1) % log_every == 0 or ep + 1 == epochs):
             print(f"[learned] epoch {ep + 1}/{epochs} loss {hist[-1]:.4e} ({time.perf_counter() - t0:.1f} s)",
                   file=sys.stderr, flush=True)
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
