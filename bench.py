@@ -107,6 +107,9 @@ def parse():
                     help="angular discretization of the cloud leg (p0: the paper's piecewise-constant cells)")
     ap.add_argument("--cloud-train-samples", type=int, default=65536)
     ap.add_argument("--cloud-epochs", type=int, default=60)
+    ap.add_argument("--local-solve-only", action="store_true",
+                    help="time only el_local_solve (FP64, then FP32 + refinement) on the --n mesh of the cloud "
+                         "and print one JSON line (the command the local-solve counter profiles use)")
     return ap.parse_args()
 
 
@@ -153,6 +156,39 @@ def recorded_traffic(op_dtype):
     return float(m.group(1))
 
 
+def local_solve_main(args, ctx, d, hh, kap, sig, i2o, i2s, i2m):
+    """The plain local solve alone (a1-a4 and a5): W untimed and K timed
+    launches of el_local_solve per precision on the cloud mesh; median launch
+    time by HIP events on the current stream."""
+    import torch
+    from paper_2308_02467_amd import el
+    nn, n, m = el.disc_sizes(d)
+    E = hh.shape[0]
+    rr = torch.empty(E, dtype=torch.float64, device=hh.device)
+    stream = torch.cuda.current_stream()
+    flop_el = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * m          # LU + solves for m columns
+    out = {"workload": f"el_local_solve, {int(round(E ** 0.5))}^2 elements of the Gaussian cloud, p={d.p}, "
+                       f"N_a={d.n_a} (n={n}, m={m})", "elements": E, "steps": args.steps, "warmup": args.warmup}
+    for prec, name in ((el.EL_FP64, "fp64"), (el.EL_FP32_IR, "fp32_ir")):
+        ts = []
+        for it in range(args.warmup + args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.el_local_solve(d, hh, kap, sig, precision=prec, in2out=i2o, in2sol=i2s, in2mean=i2m,
+                               rel_resid=rr if prec == el.EL_FP32_IR else None)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                ts.append(e0.elapsed_time(e1))
+        t = float(np.median(ts))
+        out[name] = {"ms": t, "el_per_s": E / (t * 1e-3), "tflops": flop_el * E / (t * 1e-3) / 1e12}
+        if prec == el.EL_FP32_IR:
+            out[name]["max_rel_resid"] = float(rr.max())
+        log(f"local solve {name}: {t:.1f} ms")
+    out["flop_per_element"] = flop_el
+    return out
+
+
 def main():
     args = parse()
     if args.cpu_worker_json:
@@ -196,6 +232,9 @@ def main():
     i2o = torch.empty((E, m, m), dtype=torch.float64, device=dev)
     i2s = torch.empty((E, n, m), dtype=torch.float64, device=dev)
     i2m = torch.empty((E, nn, m), dtype=torch.float64, device=dev)
+    if args.local_solve_only:
+        print(json.dumps(local_solve_main(args, ctx, d, hh, kap, sig, i2o, i2s, i2m)))
+        return
     nt = el.trace_size(d, ms)
     b = torch.empty(nt, dtype=torch.float64, device=dev)
     t = torch.empty(nt, dtype=torch.float64, device=dev)

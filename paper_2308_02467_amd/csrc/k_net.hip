@@ -239,16 +239,16 @@ struct EpiMAE {
   typedef uint16_t Pre;
   static constexpr bool kHasPre = true;
   // the direct-to-LDS GEMM stages the block tile's targets in LDS first
-  // (ys [BM][BN] from rows ym0, columns yn0)
+  // (ys [BM][ypitch = BN] from rows ym0, columns yn0)
   static constexpr bool kStageLds = true;
   const __attribute__((address_space(3))) uint16_t* ys;
-  int ym0, yn0;
+  int ypitch, ym0, yn0;
   __device__ Col col(int n) const { return Col{bias[n], ymean[n], 1.f / ystd[n]}; }
   // from the LDS tile, or from HBM with 32-bit byte offsets from the
   // kernel-argument base (the host keeps B * n_out below 2^31): one address
   // register per load
   __device__ Pre pre(int m, int n) const {
-    if (ys) return ys[(m - ym0) * 256 + (n - yn0)];
+    if (ys) return ys[(m - ym0) * ypitch + (n - yn0)];
     const uint32_t off = ((uint32_t)m * (uint32_t)ld + (uint32_t)n) * 2u;
     return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(y) + off);
   }
@@ -446,12 +446,13 @@ __global__ void __launch_bounds__(gemm::kThreads) __attribute__((amdgpu_waves_pe
   store_tiles<TM, TN>(epi, acc, m0 + wm * 32 * TM, n0 + wn * 32 * TN, M, N, lane, blockIdx.z);
 }
 
-// Large-tile variants for k-contiguous operands with K a multiple of 64: a
-// 256 x 256 block tile, 8 waves of 128 x 64 (4 x 2 MFMA tiles of 32 x 32),
-// operand tiles moved from HBM straight into LDS by global_load_lds_dwordx4
-// (no register staging, so the accumulators of the larger wave tile fit),
-// NS LDS stages of BK k (128 KB in all), loads NS - 1 tiles ahead, one
-// barrier per k tile.  A row of an operand tile is BK / 8 chunks of 16 bytes
+// Large-tile variant for k-contiguous operands with K a multiple of BK: a
+// BM x BN block tile of WM x WN waves, each (BM / WM) x (BN / WN) in MFMA
+// tiles of 32 x 32 (in use: 256 x 256 with 8 waves of 128 x 64), operand
+// tiles moved from HBM straight into LDS by global_load_lds_dwordx4 (no
+// register staging, so the accumulators of the larger wave tile fit), NS LDS
+// stages of BK k (128 KB for 256 x 256 in two stages of 64), loads NS - 1
+// tiles ahead, one barrier per k tile.  A row of an operand tile is BK / 8 chunks of 16 bytes
 // (8 k); chunk c of row r sits at position c ^ f(r) of the row (gemm_lds::swz),
 // so the 16-byte fragment reads of consecutive rows at one chunk spread over
 // all banks.  One load instruction
@@ -460,13 +461,9 @@ __global__ void __launch_bounds__(gemm::kThreads) __attribute__((amdgpu_waves_pe
 // there.  Per k16 step a wave reads 6 fragments for 8 MFMAs (the 64 x 64
 // wave tile of k_mm reads 4 for 4).
 namespace gemm_lds {
-constexpr int BM = 256, BN = 256;
-constexpr int TM = 4;                               // MFMA tiles per wave along M (2 waves of 128 rows)
-// TN MFMA tiles per wave along N: 2 (8 waves of 128 x 64) or 4 (4 waves of
-// 128 x 128, accumulators in the AGPRs)
-template <int TN>
-constexpr int threads() { return 64 * 2 * (BN / (32 * TN)); }
-constexpr size_t kSmem = 128 * 1024;                // NS x BK x (BM + BN) x 2 bytes
+// LDS bytes of NS stages of BK k for a BM x BN block tile
+template <int BK, int NS, int BM, int BN>
+constexpr size_t smem() { return (size_t)NS * BK * (BM + BN) * 2; }
 // chunk position of row r: conflict-free 16-byte fragment reads of 32
 // consecutive rows whether a read is served 8 lanes at a time over 32 banks
 // or 16 lanes at a time over 64 banks (rows r and r + 8 must differ too)
@@ -489,6 +486,7 @@ __device__ inline void lds_tile_load(const uint16_t* __restrict__ G, int64_t ld,
   constexpr int CPR = BK / 8;                        // 16-byte chunks per row
   constexpr int RPI = 64 / CPR;                      // rows per load instruction
   constexpr int NI = R / RPI / NW;                   // instructions per wave
+  static_assert(NI * NW * RPI == R, "whole row groups per wave");
   const int sub = lane / CPR;
 #pragma unroll
   for (int t = 0; t < NI; ++t) {
@@ -502,19 +500,18 @@ __device__ inline void lds_tile_load(const uint16_t* __restrict__ G, int64_t ld,
   }
 }
 
-template <int BK, int NS, int TN, typename Epi>
-__global__ void __launch_bounds__(gemm_lds::threads<TN>()) k_mm_lds(const uint16_t* __restrict__ A, int64_t lda,
-                                                                     const uint16_t* __restrict__ B, int64_t ldb,
-                                                                     int M, int N, int K, int k_split, Epi epi) {
+template <int BK, int NS, int BM, int BN, int WM, int WN, typename Epi>
+__global__ void __launch_bounds__(64 * WM * WN) k_mm_lds(const uint16_t* __restrict__ A, int64_t lda,
+                                                          const uint16_t* __restrict__ B, int64_t ldb, int M, int N,
+                                                          int K, int k_split, Epi epi) {
   using namespace gemm;
-  using gemm_lds::BM;
-  using gemm_lds::BN;
-  using gemm_lds::TM;
-  static_assert(NS * BK * (BM + BN) * 2 <= (int)gemm_lds::kSmem, "LDS stages");
-  constexpr int NW = gemm_lds::threads<TN>() / 64;   // waves
-  constexpr int WN = NW / 2;                         // waves along N
-  constexpr int kTile = BM * BK;                     // bf16 per operand tile
+  constexpr int NW = WM * WN;                        // waves
+  constexpr int TM = BM / (32 * WM), TN = BN / (32 * WN);   // MFMA tiles per wave
+  static_assert(TM * 32 * WM == BM && TN * 32 * WN == BN, "wave tiles");
+  static_assert(gemm_lds::smem<BK, NS, BM, BN>() <= 160 * 1024, "LDS stages");
+  constexpr int kTileA = BM * BK, kTileB = BN * BK;   // bf16 per operand tile
   constexpr int LW = (BM + BN) * BK / 8 / 64 / NW;   // load instructions per wave per k tile
+  static_assert(LW * 64 * NW * 8 == (BM + BN) * BK, "whole load instructions per wave");
   extern __shared__ __align__(16) uint16_t lds_mm_big[];
   lds_u16* L = (lds_u16*)lds_mm_big;   // the dynamic LDS array, as an LDS-space pointer
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -544,8 +541,8 @@ __global__ void __launch_bounds__(gemm_lds::threads<TN>()) k_mm_lds(const uint16
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-  auto stage_a = [&](int st) { return L + st * 2 * kTile; };
-  auto stage_b = [&](int st) { return L + st * 2 * kTile + kTile; };
+  auto stage_a = [&](int st) { return L + st * (kTileA + kTileB); };
+  auto stage_b = [&](int st) { return L + st * (kTileA + kTileB) + kTileA; };
   auto load_tile = [&](int t) {
     const int k = kb + t * BK;
     lds_tile_load<BK, BM, NW>(A, lda, M, m0, k, stage_a(t % NS), wave, lane);
@@ -599,18 +596,37 @@ __global__ void __launch_bounds__(gemm_lds::threads<TN>()) k_mm_lds(const uint16
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[b][i], bfr[b][j], acc[i][j], 0, 0, 0);
     }
+    // issue order of the k tile (left to itself the scheduler groups each
+    // step's reads and waits for all of them before the MFMAs that need the
+    // first): the first step's fragment reads, then each step's MFMAs with
+    // the next step's reads placed between them, one wait per step
+    static_assert(TM * TN >= TM + TN, "a read between MFMAs");
+    __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);   // 0x100: LDS reads
+#pragma unroll
+    for (int ks = 0; ks < BK - 16; ks += 16) {
+#pragma unroll
+      for (int q = 0; q < TM + TN; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // 0x008: MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, TM * TN - TM - TN, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
   }
   if constexpr (Epi::kStageLds) {
     // the block tile's per-element epilogue inputs (ld = N) into the LDS
     // stages, which are free once every wave is past its last MFMA reads:
-    // row r at r * BN, 16-byte chunks, one instruction per two rows;
-    // rows past M and chunks past N are clamped into the operand (never used)
-    static_assert(BM * BN * 2 <= (int)gemm_lds::kSmem, "epilogue tile");
+    // row r at r * BN, 16-byte chunks (chunk i of the tile: row i / (BN / 8),
+    // 16 bytes at i * 16; one instruction fills 64 chunks); rows past M and
+    // chunks past N are clamped into the operand (never used)
+    static_assert(BM * BN * 2 <= gemm_lds::smem<BK, NS, BM, BN>(), "epilogue tile");
+    static_assert((BM * BN / 8) % 64 == 0, "whole instructions");
     __syncthreads();
     const uint16_t* Y = epi.y;
-    for (int q = wave; q < BM / 2; q += NW) {
-      const int r = min(m0 + 2 * q + (lane >> 5), M - 1);
-      const int c = min(n0 + 8 * (lane & 31), N - 8);
+    for (int q = wave; q < BM * BN / 8 / 64; q += NW) {
+      const int ci = q * 64 + lane;
+      const int r = min(m0 + ci / (BN / 8), M - 1);
+      const int c = min(n0 + 8 * (ci % (BN / 8)), N - 8);
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(Y + (int64_t)r * N + c),
                                        reinterpret_cast<__attribute__((address_space(3))) void*>(L + q * 512), 16, 0,
                                        0);
@@ -618,6 +634,7 @@ __global__ void __launch_bounds__(gemm_lds::threads<TN>()) k_mm_lds(const uint16
     __builtin_amdgcn_s_waitcnt(gemm_lds::vmcnt_imm(0));
     __syncthreads();
     epi.ys = L;
+    epi.ypitch = BN;
     epi.ym0 = m0;
     epi.yn0 = n0;
     store_tiles<TM, TN, Epi, true>(epi, acc, m0 + wm * 32 * TM, n0 + wn * 32 * TN, M, N, lane, blockIdx.z);
@@ -627,7 +644,8 @@ __global__ void __launch_bounds__(gemm_lds::threads<TN>()) k_mm_lds(const uint16
 }
 
 // whether k_mm_lds can take a GEMM (k-contiguous operands, 16-byte aligned
-// rows, K and the split-K chunk multiples of 64)
+// rows, K and the split-K chunk multiples of 64, the k tile of every
+// direct-to-LDS variant)
 inline bool mm_lds_ok(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t K, int splits) {
   int64_t ks = (K + splits - 1) / splits;
   ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
@@ -635,25 +653,27 @@ inline bool mm_lds_ok(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t
          reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
 }
 
-template <int BK, int NS, int TN, typename Epi>
+template <int BK, int NS, int BM, int BN, int WM, int WN, typename Epi>
 el_status mm_lds(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M, int64_t N,
                  int64_t K, int splits, Epi epi) {
-  if (!mm_lds_ok(A, lda, B, ldb, K, splits))
+  static_assert(BK == 64, "mm_lds_ok checks k tiles of 64");
+  if (!mm_lds_ok(A, lda, B, ldb, K, splits) || !epi_lds_ok(epi, N))
     return set_error(ctx, EL_ERR_ARG, "internal GEMM: the direct-to-LDS tile needs K % 64 == 0 and aligned rows");
+  constexpr size_t smem = gemm_lds::smem<BK, NS, BM, BN>();
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mm_lds<BK, NS, TN, Epi>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds::kSmem);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mm_lds<BK, NS, BM, BN, WM, WN, Epi>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return hip_check(ctx, e, "hipFuncSetAttribute(k_mm_lds)");
     attr_set = true;
   }
   int64_t ks = (K + splits - 1) / splits;
   ks = (ks + gemm::BK - 1) / gemm::BK * gemm::BK;
   const int nz = (int)((K + ks - 1) / ks);
-  const int64_t tiles = ((M + gemm_lds::BM - 1) / gemm_lds::BM) * ((N + gemm_lds::BN - 1) / gemm_lds::BN);
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   if (tiles > INT_MAX / 2) return set_error(ctx, EL_ERR_ARG, "internal GEMM: too many tiles");
-  hipLaunchKernelGGL((k_mm_lds<BK, NS, TN, Epi>), dim3((unsigned)tiles, 1, (unsigned)nz), dim3(gemm_lds::threads<TN>()),
-                     gemm_lds::kSmem, ctx->stream, A, lda, B, ldb, (int)M, (int)N, (int)K, (int)ks, epi);
+  hipLaunchKernelGGL((k_mm_lds<BK, NS, BM, BN, WM, WN, Epi>), dim3((unsigned)tiles, 1, (unsigned)nz),
+                     dim3(64 * WM * WN), smem, ctx->stream, A, lda, B, ldb, (int)M, (int)N, (int)K, (int)ks, epi);
   return hip_check(ctx, hipGetLastError(), "launch k_mm_lds");
 }
 
@@ -701,9 +721,23 @@ std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, std::vector<float>>> g_tune;   // key -> (choice, ms per variant)
 std::atomic<int> g_force_tile{-1};   // >= 0: this variant wherever it applies (el_gemm_tile)
 
-template <bool A_KC, bool B_KC>
-bool variant_applies(int v, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t K, int splits) {
-  return !kVariants[v].lds || (A_KC && B_KC && mm_lds_ok(A, lda, B, ldb, K, splits));
+// an epilogue that stages per-element inputs (ld = N) in LDS needs 16-byte
+// aligned rows of them
+template <typename Epi>
+bool epi_lds_ok(const Epi& epi, int64_t N) {
+  if constexpr (Epi::kStageLds) {
+    return N % 8 == 0 && reinterpret_cast<uintptr_t>(epi.y) % 16 == 0;
+  } else {
+    (void)epi;
+    (void)N;
+    return true;
+  }
+}
+
+template <bool A_KC, bool B_KC, typename Epi>
+bool variant_applies(int v, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t N, int64_t K,
+                     int splits, const Epi& epi) {
+  return !kVariants[v].lds || (A_KC && B_KC && mm_lds_ok(A, lda, B, ldb, K, splits) && epi_lds_ok(epi, N));
 }
 
 template <bool A_KC, bool B_KC, typename Epi>
@@ -713,11 +747,13 @@ el_status mm_variant(el_ctx* ctx, int v, const uint16_t* A, int64_t lda, const u
     case 1: return mm_t<A_KC, B_KC, 1, 2, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
     case 2: return mm_t<A_KC, B_KC, 2, 1, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
     case 3:
-      // 8 waves of 128 x 64, k tiles of 64 in two stages (on the 128^2, p = 6
-      // output layer faster than k tiles of 32 in four stages or 4 waves of
-      // 128 x 128)
+      // 256 x 256, 8 waves of 128 x 64, k tiles of 64 in two stages.  Slower
+      // on every network GEMM of the 128^2, p = 6 workload: k tiles of 32 in
+      // four or five stages, 4 waves of 128 x 128, 192 x 192 in three stages
+      // (6 waves: two SIMDs carry two waves, two carry one), 256 x 128 and
+      // 128 x 256 in three stages (4 waves, one per SIMD)
       if constexpr (A_KC && B_KC) {
-        return mm_lds<64, 2, 2, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi);
+        return mm_lds<64, 2, 256, 256, 2, 4, Epi>(ctx, A, lda, B, ldb, M, N, K, splits, epi);
       } else {
         return set_error(ctx, EL_ERR_ARG, "internal GEMM: the direct-to-LDS tile needs k-contiguous operands");
       }
@@ -730,7 +766,7 @@ el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int
              int64_t K, int splits, Epi epi, bool m_fast = false) {
   if (M <= 0 || N <= 0) return EL_OK;
   const int forced = g_force_tile.load();
-  if (forced >= 0 && variant_applies<A_KC, B_KC>(forced, A, lda, B, ldb, K, splits))
+  if (forced >= 0 && variant_applies<A_KC, B_KC>(forced, A, lda, B, ldb, N, K, splits, epi))
     return mm_variant<A_KC, B_KC, Epi>(ctx, forced, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
   if constexpr (!Epi::kRepeatable) {
     return mm_variant<A_KC, B_KC, Epi>(ctx, 0, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
@@ -752,7 +788,7 @@ el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int
         return hip_check(ctx, hipGetLastError(), "autotune events");
       int best = 0;
       for (int v = 0; v < kNumVariants; ++v) {
-        if (!variant_applies<A_KC, B_KC>(v, A, lda, B, ldb, K, splits)) {
+        if (!variant_applies<A_KC, B_KC>(v, A, lda, B, ldb, N, K, splits, epi)) {
           ms[v] = INFINITY;   // not a candidate for this GEMM
           continue;
         }
@@ -1102,7 +1138,7 @@ Box make_box(const el_net* net) {
 // host-side state): the 256 x 256 direct-to-LDS tile where it applies, else
 // 128 x 128.
 inline int fixed_variant(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t K) {
-  return variant_applies<true, true>(3, A, lda, B, ldb, K, 1) ? 3 : 0;
+  return mm_lds_ok(A, lda, B, ldb, K, 1) ? 3 : 0;
 }
 
 // hidden layers: X0 -> H[depth-1]; Z saved when save_z; tiles autotuned, or
@@ -1384,7 +1420,7 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
   if (B * nout >= ((int64_t)1 << 31))
     return set_error(ctx, EL_ERR_ARG, "el_train_step: batch x n_out must stay below 2^31");
   EpiMAE mae{net->theta + net->b_off[D], y, net->y_mean, net->y_std, s.dY, s.colp, s.lossp, nout, 0.f, 0.f,
-             nullptr, 0, 0};
+             nullptr, 0, 0, 0};
   st = mm<true, true>(ctx, Hlast, W, net->wbf + net->w_off[D], W, B, nout, W, 1, mae, true);
   if (st) return st;
   // output layer gradients: the bias from the epilogue's per-block column

@@ -79,7 +79,10 @@ def gemm_tile():
 
 # tile -1: the autotuner's choice; 3: the 256 x 256 direct-to-LDS tile for
 # every GEMM that can take it (k-contiguous operands, K % 64 == 0)
-@pytest.mark.parametrize("tile", [-1, 3])
+LDS_TILES = [3]
+
+
+@pytest.mark.parametrize("tile", [-1] + LDS_TILES)
 @pytest.mark.parametrize("n_in,width,depth,n_out,act,B", [(9, 64, 2, 96, 0, 6), (19, 128, 3, 200, 1, 6),
                                                            (99, 1024, 4, 1024, 0, 6), (99, 256, 1, 225792, 0, 6),
                                                            (99, 256, 2, 1000, 0, 700), (19, 128, 3, 200, 2, 6)])
@@ -104,7 +107,7 @@ def test_forward_parity(ctx, gemm_tile, tile, n_in, width, depth, n_out, act, B)
     net.close()
 
 
-@pytest.mark.parametrize("tile", [-1, 3])
+@pytest.mark.parametrize("tile", [-1] + LDS_TILES)
 def test_gradients_and_adam(ctx, gemm_tile, tile):
     from paper_2308_02467_amd import el
     n_in, width, depth, n_out, B = 9, 64, 3, 128, 48
