@@ -107,6 +107,8 @@ def parse():
                     help="angular discretization of the cloud leg (p0: the paper's piecewise-constant cells)")
     ap.add_argument("--cloud-train-samples", type=int, default=65536)
     ap.add_argument("--cloud-epochs", type=int, default=60)
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner choices: loaded from this file when it exists, saved to it at the end")
     ap.add_argument("--local-solve-only", action="store_true",
                     help="time only el_local_solve (FP64, then FP32 + refinement) on the --n mesh of the cloud "
                          "and print one JSON line (the command the local-solve counter profiles use)")
@@ -221,6 +223,8 @@ def main():
 
     ctx = el.Context(0)
     stream = torch.cuda.current_stream()
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        log(f"autotuner: {el.tuning_load(args.tune_cache)} choices from {args.tune_cache}")
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)      # 1 GiB
         dst = torch.empty_like(src)
@@ -383,6 +387,8 @@ def main():
         "gemm_tiles": el.tuning_report().strip().split("\n") if el.tuning_report().strip() else [],
         "accuracy": acc,
     }
+    if args.tune_cache:
+        el.tuning_save(args.tune_cache)
     print(json.dumps(out))
     ctx.close()
 

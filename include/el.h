@@ -320,6 +320,23 @@ el_status el_net_num_params(const el_net* net, int64_t* n_params);
  * receives the size needed including the NUL.  Never fails. */
 el_status el_tuning_report(char* buf, size_t cap, size_t* len);
 
+/* The autotuner's choices across processes.  el_tuning_save writes every
+ * choice made or loaded so far in this process to the text file at host
+ * string path (created or replaced): a header line, then one line per GEMM
+ * shape, "<key>\t<tile index>\t<tile name>", where the key begins with the
+ * device architecture (e.g. gfx950).  el_tuning_load reads such a file; its
+ * choices are used from then on instead of timing the candidates (a key is
+ * only ever looked up on a device of its architecture); lines whose tile
+ * index and name do not match a tile of this library are skipped.  *loaded
+ * (may be NULL) receives the number of choices taken.  Both: EL_ERR_ARG for
+ * a NULL path or a file that cannot be written / opened; el_tuning_load
+ * also for a missing header or a malformed line, and then takes nothing.
+ * el_tuning_reset forgets every choice of this process.  Host only; calls
+ * that overlap with GEMMs on other threads are safe (one lock). */
+el_status el_tuning_save(const char* path);
+el_status el_tuning_load(const char* path, int64_t* loaded);
+el_status el_tuning_reset(void);
+
 /* Block tile of the network GEMMs in this process: -1 (default) = chosen
  * per shape by the autotuner; 0 = 128x128, 1 = 64x128, 2 = 128x64,
  * 3 = 256x256 with operand tiles loaded straight into LDS (only GEMMs

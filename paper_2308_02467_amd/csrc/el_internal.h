@@ -80,6 +80,7 @@ struct el_ctx {
   el::Workspace ws_small;    // flags, reductions
   el::Workspace ws_infer;    // el_infer: range mask (when the caller passes none) and fallback index
   int num_cus = 256;
+  std::string arch = "unknown";   // the device's architecture name (e.g. gfx950), part of every autotuner key
   // captured GMRES restart cycle (rebuilt when the batch shape changes)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gm_exec = nullptr;

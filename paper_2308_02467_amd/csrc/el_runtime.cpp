@@ -116,7 +116,13 @@ el_status el_create(el_ctx** ctx, int device, void* hip_stream) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->num_cus = prop.multiProcessorCount;
+    // "gfx950:sramecc+:xnack-" -> "gfx950"
+    std::string a(prop.gcnArchName);
+    a = a.substr(0, a.find(':'));
+    if (!a.empty()) c->arch = a;
+  }
   el_status st = noalloc_init(c);
   if (st) { delete c; return st; }
   *ctx = c;

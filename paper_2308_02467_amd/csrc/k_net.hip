@@ -8,6 +8,7 @@
 #include <cmath>
 #include <type_traits>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -706,19 +707,28 @@ el_status mm_t(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, i
 }
 
 // ---- GEMM autotuner --------------------------------------------------------
-// The block tile is chosen per GEMM shape, on first use, by timing the
-// candidates below on the call's own operands (outputs are overwritten by
-// the chosen run); epilogues with side effects other than their outputs
-// (the loss accumulation) use the default.  Choices are kept per process.
+// The block tile is chosen per GEMM shape and device architecture, on first
+// use, by timing the candidates below on the call's own operands (outputs are
+// overwritten by the chosen run); epilogues whose runs are not repeatable use
+// the default.  Choices are kept per process and can be saved to and loaded
+// from a text file (el_tuning_save / el_tuning_load), which then replaces the
+// timing.
 struct TileVariant {
   int tm, tn;
   bool lds;   // k_mm_lds (k-contiguous operands only)
 };
+// the tile's name in reports and cache files
+inline std::string tile_name(const TileVariant& v) {
+  std::ostringstream os;
+  os << 64 * v.tm << "x" << 64 * v.tn << (v.lds ? " direct-to-LDS" : "");
+  return os.str();
+}
 constexpr TileVariant kVariants[] = {{2, 2, false}, {1, 2, false}, {2, 1, false}, {4, 4, true}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, std::vector<float>>> g_tune;   // key -> (choice, ms per variant)
+// key ("<arch> gemm ...") -> (choice, ms per variant; empty when loaded from a file)
+std::map<std::string, std::pair<int, std::vector<float>>> g_tune;
 std::atomic<int> g_force_tile{-1};   // >= 0: this variant wherever it applies (el_gemm_tile)
 
 // an epilogue that stages per-element inputs (ld = N) in LDS needs 16-byte
@@ -772,7 +782,7 @@ el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int
     return mm_variant<A_KC, B_KC, Epi>(ctx, 0, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
   } else {
     std::ostringstream ks;
-    ks << "gemm " << (A_KC ? "A" : "At") << (B_KC ? "B" : "Bt") << ' ' << Epi::kName << " M=" << M << " N=" << N
+    ks << ctx->arch << " gemm " << (A_KC ? "A" : "At") << (B_KC ? "B" : "Bt") << ' ' << Epi::kName << " M=" << M << " N=" << N
        << " K=" << K << " splits=" << splits;
     const std::string key = ks.str();
     int choice = -1;
@@ -1645,6 +1655,58 @@ el_status el_infer_noalloc(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E
   return hip_check(ctx, hipGetLastError(), "el_infer_noalloc");
 }
 
+// Cache file: a first line naming the format, then one line per choice:
+// "<key>\t<tile index>\t<tile name>".
+static const char kTuneHeader[] = "# el GEMM autotuner choices v1";
+
+el_status el_tuning_save(const char* path) {
+  if (!path) return EL_ERR_ARG;
+  std::ofstream f(path, std::ios::out | std::ios::trunc);
+  if (!f) return EL_ERR_ARG;
+  f << kTuneHeader << '\n';
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tune)
+      f << kv.first << '\t' << kv.second.first << '\t' << tile_name(kVariants[kv.second.first]) << '\n';
+  }
+  f.flush();
+  return f ? EL_OK : EL_ERR_ARG;
+}
+
+el_status el_tuning_load(const char* path, int64_t* loaded) {
+  if (loaded) *loaded = 0;
+  if (!path) return EL_ERR_ARG;
+  std::ifstream f(path);
+  if (!f) return EL_ERR_ARG;
+  std::string line;
+  if (!std::getline(f, line) || line != kTuneHeader) return EL_ERR_ARG;
+  // parse everything first: a malformed line leaves the choices unchanged
+  std::vector<std::pair<std::string, int>> take;
+  while (std::getline(f, line)) {
+    if (line.empty()) continue;
+    const size_t t1 = line.find('\t');
+    const size_t t2 = t1 == std::string::npos ? t1 : line.find('\t', t1 + 1);
+    if (t1 == 0 || t2 == std::string::npos || line.find('\t', t2 + 1) != std::string::npos) return EL_ERR_ARG;
+    const std::string key = line.substr(0, t1), idx = line.substr(t1 + 1, t2 - t1 - 1), name = line.substr(t2 + 1);
+    if (idx.empty() || idx.size() > 3 || idx.find_first_not_of("0123456789") != std::string::npos)
+      return EL_ERR_ARG;
+    const int v = std::stoi(idx);
+    // a tile this library numbers differently (or does not have) is skipped
+    if (v >= kNumVariants || tile_name(kVariants[v]) != name) continue;
+    take.emplace_back(key, v);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : take) g_tune[kv.first] = {kv.second, {}};
+  if (loaded) *loaded = (int64_t)take.size();
+  return EL_OK;
+}
+
+el_status el_tuning_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return EL_OK;
+}
+
 el_status el_gemm_tile(int variant) {
   if (variant < -1 || variant >= kNumVariants) return EL_ERR_ARG;
   g_force_tile.store(variant);
@@ -1656,10 +1718,12 @@ el_status el_tuning_report(char* buf, size_t cap, size_t* len) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& kv : g_tune) {
-      const TileVariant v = kVariants[kv.second.first];
-      os << kv.first << " -> tile " << 64 * v.tm << "x" << 64 * v.tn
-         << (v.lds ? " direct-to-LDS" : "")
-         << " (ms:";
+      os << kv.first << " -> tile " << tile_name(kVariants[kv.second.first]);
+      if (kv.second.second.empty()) {
+        os << " (from a cache file)\n";
+        continue;
+      }
+      os << " (ms:";
       for (float t : kv.second.second) os << ' ' << t;
       os << ")\n";
     }

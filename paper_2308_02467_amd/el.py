@@ -96,6 +96,9 @@ _SIGS = {
                         ctypes.c_void_p],
     "el_gemm_tile": [ctypes.c_int],
     "el_tuning_report": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "el_tuning_save": [ctypes.c_char_p],
+    "el_tuning_load": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
+    "el_tuning_reset": [],
     "el_trace_solve": [ctypes.c_void_p, el_disc, ctypes.c_int, ctypes.POINTER(el_mesh),
                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(el_gmres_opts),
@@ -571,6 +574,26 @@ def tuning_report():
     buf = ctypes.create_string_buffer(max(n.value, 1))
     lib().el_tuning_report(buf, n.value, None)
     return buf.value.decode()
+
+
+def tuning_save(path):
+    """Write the autotuner's choices to a text file (el_tuning_save)."""
+    if lib().el_tuning_save(os.fsencode(path)) != EL_OK:
+        raise ElError(EL_ERR_ARG, f"el_tuning_save: cannot write {path}")
+
+
+def tuning_load(path):
+    """Take the autotuner's choices from a file written by tuning_save
+    (el_tuning_load); returns the number of choices taken."""
+    n = ctypes.c_int64()
+    if lib().el_tuning_load(os.fsencode(path), ctypes.byref(n)) != EL_OK:
+        raise ElError(EL_ERR_ARG, f"el_tuning_load: cannot read {path} as an autotuner file")
+    return n.value
+
+
+def tuning_reset():
+    """Forget every autotuner choice of this process (el_tuning_reset)."""
+    lib().el_tuning_reset()
 
 
 def gemm_tile(variant):

@@ -181,6 +181,38 @@ def test_gradients_fp64_definition(ctx, n_in, width, depth, n_out, act, B):
     net.close()
 
 
+def test_tuning_cache_replaces_timing(ctx, tmp_path):
+    """Choices saved by one process and loaded into a fresh autotuner give
+    the same tiles without timing: bit-identical forward outputs, and the
+    report marks every choice as taken from the file."""
+    from paper_2308_02467_amd import el
+    n_in, width, depth, n_out, B = 99, 256, 2, 1000, 700
+    rng = np.random.default_rng(31)
+    hn = _host_net(rng, n_in, width, depth, n_out)
+    net = _load(ctx, hn, n_in, width, depth, n_out)
+    x = torch.from_numpy(_raw_inputs(rng, B, (n_in - 1) // 2).astype(np.float32)).to(DEV)
+    y1 = torch.empty((B, n_out), dtype=torch.float32, device=DEV)
+    y2 = torch.empty_like(y1)
+    el.tuning_reset()
+    net.forward(x, y1)
+    timed = el.tuning_report()
+    print("[tuning] timed:\n" + timed, flush=True)
+    keys = [l.split(" -> ")[0] for l in timed.splitlines()]
+    arch = torch.cuda.get_device_properties(DEV).gcnArchName.split(":")[0]
+    assert keys and all(k.split()[0] == arch for k in keys)
+    f = tmp_path / "tune.txt"
+    el.tuning_save(f)
+    el.tuning_reset()
+    assert el.tuning_load(f) == len(keys)
+    net.forward(x, y2)
+    loaded = el.tuning_report()
+    assert [l.split(" (")[0] for l in loaded.splitlines()] == [l.split(" (")[0] for l in timed.splitlines()]
+    assert all(l.endswith("(from a cache file)") for l in loaded.splitlines())
+    assert torch.equal(y1, y2)
+    el.tuning_reset()
+    net.close()
+
+
 def test_save_load_and_bitwise_resume(ctx):
     from paper_2308_02467_amd import el
     n_in, width, depth, n_out, B = 9, 64, 2, 64, 32
