@@ -240,16 +240,21 @@ struct EpiMAE {
   typedef uint16_t Pre;
   static constexpr bool kHasPre = true;
   // the direct-to-LDS GEMM stages the block tile's targets in LDS first
-  // (ys [BM][ypitch = BN] from rows ym0, columns yn0)
+  // (rows ym0.., columns yn0..; pitch ypitch; tile rows below ysplit from ys,
+  // the others from ys2)
   static constexpr bool kStageLds = true;
   const __attribute__((address_space(3))) uint16_t* ys;
-  int ypitch, ym0, yn0;
+  const __attribute__((address_space(3))) uint16_t* ys2;
+  int ypitch, ysplit, ym0, yn0;
   __device__ Col col(int n) const { return Col{bias[n], ymean[n], 1.f / ystd[n]}; }
   // from the LDS tile, or from HBM with 32-bit byte offsets from the
   // kernel-argument base (the host keeps B * n_out below 2^31): one address
   // register per load
   __device__ Pre pre(int m, int n) const {
-    if (ys) return ys[(m - ym0) * ypitch + (n - yn0)];
+    if (ys) {
+      const int r = m - ym0;
+      return r < ysplit ? ys[r * ypitch + (n - yn0)] : ys2[(r - ysplit) * ypitch + (n - yn0)];
+    }
     const uint32_t off = ((uint32_t)m * (uint32_t)ld + (uint32_t)n) * 2u;
     return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(y) + off);
   }
@@ -453,7 +458,10 @@ __global__ void __launch_bounds__(gemm::kThreads) __attribute__((amdgpu_waves_pe
 // tiles moved from HBM straight into LDS by global_load_lds_dwordx4 (no
 // register staging, so the accumulators of the larger wave tile fit), NS LDS
 // stages of BK k (128 KB for 256 x 256 in two stages of 64), loads NS - 1
-// tiles ahead, one barrier per k tile.  A row of an operand tile is BK / 8 chunks of 16 bytes
+// tiles ahead, one barrier per k tile.  An epilogue with per-element inputs
+// (the training targets) has them staged in LDS, the first three quarters of
+// the rows fetched while the last k tile multiplies (into the stage it leaves
+// free and the 32 KB beyond the stages).  A row of an operand tile is BK / 8 chunks of 16 bytes
 // (8 k); chunk c of row r sits at position c ^ f(r) of the row (gemm_lds::swz),
 // so the 16-byte fragment reads of consecutive rows at one chunk spread over
 // all banks.  One load instruction
@@ -465,6 +473,14 @@ namespace gemm_lds {
 // LDS bytes of NS stages of BK k for a BM x BN block tile
 template <int BK, int NS, int BM, int BN>
 constexpr size_t smem() { return (size_t)NS * BK * (BM + BN) * 2; }
+constexpr size_t kMaxLds = 160 * 1024;
+// two stages and an epilogue that stages its inputs: the inputs' first rows
+// are fetched into the stage the last k tile leaves free and the LDS beyond
+// the stages while that tile multiplies
+template <typename Epi, int NS>
+constexpr bool prefetch_epi() { return Epi::kStageLds && NS == 2; }
+template <typename Epi, int BK, int NS, int BM, int BN>
+constexpr size_t lds_bytes() { return prefetch_epi<Epi, NS>() ? kMaxLds : smem<BK, NS, BM, BN>(); }
 // chunk position of row r: conflict-free 16-byte fragment reads of 32
 // consecutive rows whether a read is served 8 lanes at a time over 32 banks
 // or 16 lanes at a time over 64 banks (rows r and r + 8 must differ too)
@@ -509,7 +525,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_mm_lds(const uint16_t* __restr
   constexpr int NW = WM * WN;                        // waves
   constexpr int TM = BM / (32 * WM), TN = BN / (32 * WN);   // MFMA tiles per wave
   static_assert(TM * 32 * WM == BM && TN * 32 * WN == BN, "wave tiles");
-  static_assert(gemm_lds::smem<BK, NS, BM, BN>() <= 160 * 1024, "LDS stages");
+  static_assert(gemm_lds::lds_bytes<Epi, BK, NS, BM, BN>() <= gemm_lds::kMaxLds, "LDS stages");
   constexpr int kTileA = BM * BK, kTileB = BN * BK;   // bf16 per operand tile
   constexpr int LW = (BM + BN) * BK / 8 / 64 / NW;   // load instructions per wave per k tile
   static_assert(LW * 64 * NW * 8 == (BM + BN) * BK, "whole load instructions per wave");
@@ -544,11 +560,39 @@ __global__ void __launch_bounds__(64 * WM * WN) k_mm_lds(const uint16_t* __restr
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
   auto stage_a = [&](int st) { return L + st * (kTileA + kTileB); };
   auto stage_b = [&](int st) { return L + st * (kTileA + kTileB) + kTileA; };
+  // k tile t goes to stage (t + sh) % NS; with the epilogue prefetch the last
+  // tile lands in stage 0 and leaves stage 1 free, which is contiguous with
+  // the LDS beyond the stages
+  constexpr bool kPre = gemm_lds::prefetch_epi<Epi, NS>();
+  const int sh = kPre ? nsteps + 1 : 0;
   auto load_tile = [&](int t) {
     const int k = kb + t * BK;
-    lds_tile_load<BK, BM, NW>(A, lda, M, m0, k, stage_a(t % NS), wave, lane);
-    lds_tile_load<BK, BN, NW>(B, ldb, N, n0, k, stage_b(t % NS), wave, lane);
+    lds_tile_load<BK, BM, NW>(A, lda, M, m0, k, stage_a((t + sh) % NS), wave, lane);
+    lds_tile_load<BK, BN, NW>(B, ldb, N, n0, k, stage_b((t + sh) % NS), wave, lane);
   };
+  // rows [r0, r1) of the block tile's epilogue inputs (ld = N) into LDS at D
+  // (pitch BN): 16-byte chunks, chunk i of the range at i * 16 bytes, one
+  // instruction per 64 chunks; rows past M and chunks past N are clamped into
+  // the operand (never used)
+  auto stage_inputs = [&](int r0, int r1, lds_u16* D) {
+    if constexpr (Epi::kStageLds) {
+      static_assert((BN / 8) % 64 == 0 || 64 % (BN / 8) == 0, "whole rows per instruction group");
+      const uint16_t* Y = epi.y;
+      const int nq = (r1 - r0) * (BN / 8) / 64;
+      for (int q = wave; q < nq; q += NW) {
+        const int ci = q * 64 + lane;
+        const int r = min(m0 + r0 + ci / (BN / 8), M - 1);
+        const int c = min(n0 + 8 * (ci % (BN / 8)), N - 8);
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(Y + (int64_t)r * N + c),
+                                         reinterpret_cast<__attribute__((address_space(3))) void*>(D + q * 512), 16,
+                                         0, 0);
+      }
+    }
+  };
+  constexpr int kStageElems = BK * (BM + BN);
+  constexpr int kPreRows = kPre ? (int)((gemm_lds::kMaxLds / 2 - kStageElems) / BN) : 0;   // rows fetched early
+  static_assert(!kPre || (kPreRows < BM && (BM - kPreRows) * BN <= kStageElems && kPreRows % 8 == 0),
+                "epilogue prefetch layout");
 #pragma unroll
   for (int t = 0; t < NS - 1; ++t)
     if (t < nsteps) load_tile(t);
@@ -573,8 +617,9 @@ __global__ void __launch_bounds__(64 * WM * WN) k_mm_lds(const uint16_t* __restr
     // in flight, the later tiles' included
     asm volatile("s_barrier" ::: "memory");
     if (s + NS - 1 < nsteps) load_tile(s + NS - 1);
-    const lds_u16* as = stage_a(s % NS) + (wm * 32 * TM + lr) * BK;
-    const lds_u16* bs = stage_b(s % NS) + (wn * 32 * TN + lr) * BK;
+    else if (kPre && s == nsteps - 1) stage_inputs(0, kPreRows, L + kStageElems);
+    const lds_u16* as = stage_a((s + sh) % NS) + (wm * 32 * TM + lr) * BK;
+    const lds_u16* bs = stage_b((s + sh) % NS) + (wn * 32 * TN + lr) * BK;
     // fragments of the next k16 step are read while this one multiplies
     bf16x8 af[2][TM], bfr[2][TN];
     auto frags = [&](int ks, int b) {
@@ -615,26 +660,27 @@ __global__ void __launch_bounds__(64 * WM * WN) k_mm_lds(const uint16_t* __restr
     __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
   }
   if constexpr (Epi::kStageLds) {
-    // the block tile's per-element epilogue inputs (ld = N) into the LDS
-    // stages, which are free once every wave is past its last MFMA reads:
-    // row r at r * BN, 16-byte chunks (chunk i of the tile: row i / (BN / 8),
-    // 16 bytes at i * 16; one instruction fills 64 chunks); rows past M and
-    // chunks past N are clamped into the operand (never used)
-    static_assert(BM * BN * 2 <= gemm_lds::smem<BK, NS, BM, BN>(), "epilogue tile");
+    // the block tile's per-element epilogue inputs in LDS: with the prefetch,
+    // rows below kPreRows are already on their way (into stage 1 and the LDS
+    // beyond the stages) and the rest go to stage 0 once every wave is past
+    // its last MFMA reads; without it (or without k tiles) all rows go to the
+    // stages from 0
+    static_assert(BM * BN * 2 <= gemm_lds::lds_bytes<Epi, BK, NS, BM, BN>(), "epilogue tile");
     static_assert((BM * BN / 8) % 64 == 0, "whole instructions");
     __syncthreads();
-    const uint16_t* Y = epi.y;
-    for (int q = wave; q < BM * BN / 8 / 64; q += NW) {
-      const int ci = q * 64 + lane;
-      const int r = min(m0 + ci / (BN / 8), M - 1);
-      const int c = min(n0 + 8 * (ci % (BN / 8)), N - 8);
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(Y + (int64_t)r * N + c),
-                                       reinterpret_cast<__attribute__((address_space(3))) void*>(L + q * 512), 16, 0,
-                                       0);
+    if (kPre && nsteps > 0) {
+      stage_inputs(kPreRows, BM, L);
+      epi.ys = L + kStageElems;
+      epi.ys2 = L;
+      epi.ysplit = kPreRows;
+    } else {
+      stage_inputs(0, BM, L);
+      epi.ys = L;
+      epi.ys2 = L;
+      epi.ysplit = BM;
     }
     __builtin_amdgcn_s_waitcnt(gemm_lds::vmcnt_imm(0));
     __syncthreads();
-    epi.ys = L;
     epi.ypitch = BN;
     epi.ym0 = m0;
     epi.yn0 = n0;
@@ -660,7 +706,7 @@ el_status mm_lds(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B,
   static_assert(BK == 64, "mm_lds_ok checks k tiles of 64");
   if (!mm_lds_ok(A, lda, B, ldb, K, splits) || !epi_lds_ok(epi, N))
     return set_error(ctx, EL_ERR_ARG, "internal GEMM: the direct-to-LDS tile needs K % 64 == 0 and aligned rows");
-  constexpr size_t smem = gemm_lds::smem<BK, NS, BM, BN>();
+  constexpr size_t smem = gemm_lds::lds_bytes<Epi, BK, NS, BM, BN>();
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mm_lds<BK, NS, BM, BN, WM, WN, Epi>),
@@ -1430,7 +1476,7 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
   if (B * nout >= ((int64_t)1 << 31))
     return set_error(ctx, EL_ERR_ARG, "el_train_step: batch x n_out must stay below 2^31");
   EpiMAE mae{net->theta + net->b_off[D], y, net->y_mean, net->y_std, s.dY, s.colp, s.lossp, nout, 0.f, 0.f,
-             nullptr, 0, 0, 0};
+             nullptr, nullptr, 0, 0, 0, 0};
   st = mm<true, true>(ctx, Hlast, W, net->wbf + net->w_off[D], W, B, nout, W, 1, mae, true);
   if (st) return st;
   // output layer gradients: the bias from the epilogue's per-block column
