@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--cloud-epochs", type=int, default=60)
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner choices: loaded from this file when it exists, saved to it at the end")
+    ap.add_argument("--vendor-gemm-reference", action="store_true",
+                    help="time torch.matmul (the vendor BLAS) in bfloat16 at the network's output-layer shapes "
+                         "and print one JSON line (context for the network GEMMs; not part of the path)")
     ap.add_argument("--local-solve-only", action="store_true",
                     help="time only el_local_solve (FP64, then FP32 + refinement) on the --n mesh of the cloud "
                          "and print one JSON line (the command the local-solve counter profiles use)")
@@ -158,6 +161,35 @@ def recorded_traffic(op_dtype):
     return float(m.group(1))
 
 
+def vendor_gemm_reference():
+    """torch.matmul (hipBLASLt) in bfloat16, bfloat16 output, no epilogue, at
+    the output layer's shapes (inference of 16,384 elements, training batch
+    4,096, the dW shape) and a square 8192^3: the vendor library's rate on
+    the same box, as context for the network GEMMs' roofline fractions."""
+    import torch
+    dev = torch.device("cuda:0")
+    out = {"what": "torch.matmul bf16 x bf16 -> bf16, operands resident, 5 timed calls after one warm-up",
+           "peak_tflops": 2500.0, "shapes": []}
+    for M, N, K in ((16384, 225792, 1024), (4096, 225792, 1024), (225792, 1024, 4096), (8192, 8192, 8192)):
+        a = torch.randn(M, K, device=dev, dtype=torch.bfloat16)
+        b = torch.randn(N, K, device=dev, dtype=torch.bfloat16)
+        c = torch.matmul(a, b.t())
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            c = torch.matmul(a, b.t())
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        tf = 2.0 * M * N * K / (ms * 1e-3) / 1e12
+        out["shapes"].append({"M": M, "N": N, "K": K, "ms": ms, "tflops": tf, "frac": tf / 2500.0})
+        log(f"vendor GEMM M={M} N={N} K={K}: {ms:.3f} ms = {tf:.0f} TFLOP/s")
+        del a, b, c
+        torch.cuda.empty_cache()
+    return out
+
+
 def local_solve_main(args, ctx, d, hh, kap, sig, i2o, i2s, i2m):
     """The plain local solve alone (a1-a4 and a5): W untimed and K timed
     launches of el_local_solve per precision on the cloud mesh; median launch
@@ -202,6 +234,9 @@ def main():
     import torch
     from paper_2308_02467_amd import el, inputs
 
+    if args.vendor_gemm_reference:
+        print(json.dumps(vendor_gemm_reference()))
+        return
     if args.cloud:
         print(json.dumps(cloud_main(args)))
         return
