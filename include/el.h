@@ -37,6 +37,14 @@
  * stream; calls that report on the host (status flags, GMRES reports)
  * synchronize that stream before returning.
  *
+ * Empty batches: a call with E = 0 elements (B = 0 rows for el_net_forward)
+ * checks its enumerated arguments, launches nothing, leaves every output
+ * untouched (el_mean_l2: both sums 0; el_infer: *n_fallback_host = 0) and
+ * returns EL_OK; its pointers may then be NULL.  el_train_step and
+ * el_net_fit_normalization need at least one pair, el_trace_solve at least
+ * one mesh (EL_ERR_ARG); a mesh has n_x, n_y >= 1, and a 1 x 1 mesh is
+ * valid: all of its faces are domain boundary.
+ *
  * Errors: EL_OK = 0; negative values are errors (outputs undefined);
  * EL_WARN_NOT_CONVERGED = +1 means outputs are valid to the reported
  * residual.  el_last_error() returns text naming the failing element or mesh.

@@ -320,9 +320,10 @@ el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const 
                       const void* in2vol, int form, int op_dtype, const uint8_t* mask, void* out, int out_dtype) {
   if (!ctx) return EL_ERR_ARG;
   if (!out) { out = in2out; out_dtype = op_dtype; }
-  if (E <= 0 || !h || !kappa || !in2out || !in2vol || !op_dtype_ok(op_dtype) || !op_dtype_ok(out_dtype) ||
-      (form != EL_FORM_IN2SOL && form != EL_FORM_IN2MEAN))
-    return set_error(ctx, EL_ERR_ARG, "el_conserve: bad argument");
+  if (!op_dtype_ok(op_dtype) || !op_dtype_ok(out_dtype) || (form != EL_FORM_IN2SOL && form != EL_FORM_IN2MEAN))
+    return set_error(ctx, EL_ERR_ARG, "el_conserve: bad dtype or form");
+  if (E == 0) return EL_OK;
+  if (E < 0 || !h || !kappa || !in2out || !in2vol) return set_error(ctx, EL_ERR_ARG, "el_conserve: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
@@ -340,7 +341,12 @@ el_status el_conserve(el_ctx* ctx, el_disc d, int64_t E, const double* h, const 
 el_status el_mean_l2(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* a,
                      const double* ref, double* out_host) {
   if (!ctx) return EL_ERR_ARG;
-  if (E <= 0 || !h || !a || !ref || !out_host) return set_error(ctx, EL_ERR_ARG, "el_mean_l2: bad argument");
+  if (!out_host) return set_error(ctx, EL_ERR_ARG, "el_mean_l2: null out_host");
+  if (E == 0) {
+    out_host[0] = out_host[1] = 0.0;   // empty sums
+    return EL_OK;
+  }
+  if (E < 0 || !h || !a || !ref) return set_error(ctx, EL_ERR_ARG, "el_mean_l2: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);

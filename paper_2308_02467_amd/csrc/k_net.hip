@@ -1427,8 +1427,9 @@ el_status el_net_fit_normalization(el_ctx* ctx, el_net* net, int64_t N, const fl
 el_status el_make_pairs(el_ctx* ctx, el_disc d, int64_t E, const double* h, const double* kappa,
                         const double* sigma, int form, uint16_t* y) {
   if (!ctx) return EL_ERR_ARG;
-  if (E <= 0 || !h || !kappa || !sigma || !y || (form != EL_FORM_IN2SOL && form != EL_FORM_IN2MEAN))
-    return set_error(ctx, EL_ERR_ARG, "el_make_pairs: bad argument");
+  if (form != EL_FORM_IN2SOL && form != EL_FORM_IN2MEAN) return set_error(ctx, EL_ERR_ARG, "el_make_pairs: form");
+  if (E == 0) return EL_OK;
+  if (E < 0 || !h || !kappa || !sigma || !y) return set_error(ctx, EL_ERR_ARG, "el_make_pairs: bad argument");
   hipSetDevice(ctx->device);
   el_ctx::DiscEntry* de;
   el_status st = get_disc(ctx, d, &de);
@@ -1438,7 +1439,9 @@ el_status el_make_pairs(el_ctx* ctx, el_disc d, int64_t E, const double* h, cons
 }
 
 el_status el_net_forward(el_ctx* ctx, const el_net* cnet, int64_t B, const float* x, float* y_norm) {
-  if (!ctx || !cnet || B <= 0 || !x || !y_norm) return set_error(ctx, EL_ERR_ARG, "el_net_forward: bad argument");
+  if (!ctx || !cnet) return EL_ERR_ARG;
+  if (B == 0) return EL_OK;
+  if (B < 0 || !x || !y_norm) return set_error(ctx, EL_ERR_ARG, "el_net_forward: bad argument");
   el_net* net = const_cast<el_net*>(cnet);
   hipSetDevice(ctx->device);
   Scratch s;
@@ -1551,9 +1554,13 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
                    const double* sigma, void* in2out, void* in2vol, int out_dtype, uint8_t* in_range, int fallback,
                    int precision, int64_t* n_fallback_host) {
   if (!ctx || !cnet) return EL_ERR_ARG;
-  if (E <= 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer: bad argument");
   if (out_dtype != EL_BF16 && out_dtype != EL_F32 && out_dtype != EL_F16)
     return set_error(ctx, EL_ERR_ARG, "el_infer: out_dtype");
+  if (E == 0) {
+    if (n_fallback_host) *n_fallback_host = 0;
+    return EL_OK;
+  }
+  if (E < 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer: bad argument");
   const size_t osz = out_dtype == EL_F32 ? 4 : 2;
   el_net* net = const_cast<el_net*>(cnet);
   hipSetDevice(ctx->device);
@@ -1635,9 +1642,10 @@ el_status el_infer_noalloc(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E
                            const double* kappa, const double* sigma, void* in2out, void* in2vol, int out_dtype,
                            uint8_t* in_range) {
   if (!ctx || !cnet) return EL_ERR_ARG;
-  if (E <= 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: bad argument");
   if (out_dtype != EL_BF16 && out_dtype != EL_F32 && out_dtype != EL_F16)
     return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: out_dtype");
+  if (E == 0) return EL_OK;
+  if (E < 0 || !h || !kappa || !sigma) return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: bad argument");
   int64_t nn = 0, n = 0, m = 0;
   if (el_disc_sizes(d, &nn, &n, &m) != EL_OK) return set_error(ctx, EL_ERR_ARG, "el_infer_noalloc: bad el_disc");
   el_net* net = const_cast<el_net*>(cnet);
