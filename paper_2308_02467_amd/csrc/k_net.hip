@@ -869,27 +869,41 @@ el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int
   }
 }
 
-// out[n] = sum_b X[b][n] (X bfloat16 or float).  256 threads = 16 columns x
-// 16 row groups; fixed summation order (deterministic).
-template <typename T>
-__global__ void k_colsum(const T* __restrict__ X, int64_t B, int64_t N, float* __restrict__ out) {
-  __shared__ float part[16][17];
-  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
-  const int64_t n = (int64_t)blockIdx.x * 16 + c;
+// Column sums of a float matrix X [B][N] over the row range of chunk
+// blockIdx.y (rows rows each): out[blockIdx.y][n].  256 threads = 4 waves of
+// 64 consecutive columns (each load instruction of a wave reads 256
+// contiguous bytes of one row); wave w adds rows w, w + 4, ... of the chunk
+// in order and the four wave sums are added in wave order (deterministic).
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ X, int64_t B, int64_t N, int64_t rows,
+                                                 float* __restrict__ out) {
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t r0 = (int64_t)blockIdx.y * rows, r1 = min(B, r0 + rows);
   float acc = 0.f;
   if (n < N) {
-    for (int64_t b = g; b < B; b += 16) {
-      if constexpr (sizeof(T) == 2) acc += bf2f(X[b * N + n]);
-      else acc += X[b * N + n];
-    }
+#pragma unroll 8
+    for (int64_t b = r0 + w; b < r1; b += 4) acc += X[b * N + n];
   }
-  part[g][c] = acc;
+  part[w][lane] = acc;
   __syncthreads();
-  if (g == 0 && n < N) {
-    float t = 0.f;
-    for (int i = 0; i < 16; ++i) t += part[i][c];
-    out[n] = t;
+  if (w == 0 && n < N) out[(int64_t)blockIdx.y * N + n] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+// out[n] = sum_b X[b][n] for X [B][N] float: row chunks of at most rows_max
+// rows summed into tmp [ceil(B / rows_max)][N] and the chunk sums reduced in
+// chunk order (one launch when B <= rows_max; tmp may be null then)
+el_status colsum(el_ctx* ctx, const float* X, int64_t B, int64_t N, int64_t rows_max, float* tmp, float* out) {
+  const unsigned cb = (unsigned)((N + 63) / 64);
+  if (B <= rows_max) {
+    hipLaunchKernelGGL(k_colsum, dim3(cb, 1), dim3(256), 0, ctx->stream, X, B, N, B, out);
+  } else {
+    const int64_t chunks = (B + rows_max - 1) / rows_max;
+    if (!tmp || chunks > 65535) return set_error(ctx, EL_ERR_ARG, "internal column sum: bad chunking");
+    hipLaunchKernelGGL(k_colsum, dim3(cb, (unsigned)chunks), dim3(256), 0, ctx->stream, X, B, N, rows_max, tmp);
+    hipLaunchKernelGGL(k_colsum, dim3(cb, 1), dim3(256), 0, ctx->stream, tmp, chunks, N, chunks, out);
   }
+  return hip_check(ctx, hipGetLastError(), "launch k_colsum");
 }
 
 // dZ = (sum_s P[s]) * act'(Z); writes FP32 and bfloat16
@@ -1126,10 +1140,12 @@ struct Scratch {
   uint16_t* HT;      // [width][B] last hidden layer, transposed
   uint16_t* WT;      // [width][n_out] output-layer weights, transposed
   float* lossp;      // [ceil(B/32)][ceil(n_out/32)] per-block sums of |d| (training only)
+  float* cst;        // [ceil(B/128)][width] row-chunk sums of the hidden bias gradients (training only)
   int64_t part_elems;
 };
 
 constexpr int kSplitOut = 32;   // split-K of dY * W_out (K = n_out)
+constexpr int64_t kColsumRows = 128;   // rows per chunk of the column sums
 constexpr int kLossChunks = 256;   // first-level workgroups of the loss reduction
 
 // The output layer's dW (dY^T H) and dX (dY W) products take the
@@ -1152,6 +1168,7 @@ el_status get_scratch(el_ctx* ctx, el_net* net, int64_t B, bool train, Scratch& 
   const int64_t rb = (B + 31) / 32;
   size_t ocolp = train ? add((size_t)rb * nout * 4) : 0;
   size_t olossp = train ? add(((size_t)rb * ((nout + 31) / 32) + kLossChunks) * 4) : 0;
+  size_t ocst = train ? add((size_t)((B + kColsumRows - 1) / kColsumRows) * W * 4) : 0;
   const bool tr = train && transposed_ok(B, nout, W);
   size_t odYT = tr ? add((size_t)nout * B * 2) : 0, oHT = tr ? add((size_t)W * B * 2) : 0;
   size_t oWT = tr ? add((size_t)W * nout * 2) : 0;
@@ -1177,6 +1194,7 @@ el_status get_scratch(el_ctx* ctx, el_net* net, int64_t B, bool train, Scratch& 
   s.loss = reinterpret_cast<float*>(b + oloss);
   s.colp = train ? reinterpret_cast<float*>(b + ocolp) : nullptr;
   s.lossp = train ? reinterpret_cast<float*>(b + olossp) : nullptr;
+  s.cst = train ? reinterpret_cast<float*>(b + ocst) : nullptr;
   s.dYT = tr ? reinterpret_cast<uint16_t*>(b + odYT) : nullptr;
   s.HT = tr ? reinterpret_cast<uint16_t*>(b + oHT) : nullptr;
   s.WT = tr ? reinterpret_cast<uint16_t*>(b + oWT) : nullptr;
@@ -1485,8 +1503,8 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
   // output layer gradients: the bias from the epilogue's per-block column
   // sums, the loss from its per-block sums (fixed-order reductions)
   const int64_t rb = (B + 31) / 32;
-  hipLaunchKernelGGL(k_colsum<float>, dim3(nblk(nout, 16)), dim3(256), 0, str, s.colp, rb, nout,
-                     net->grad + net->b_off[D]);
+  st = colsum(ctx, s.colp, rb, nout, rb, nullptr, net->grad + net->b_off[D]);
+  if (st) return st;
   {
     const int64_t nl = rb * ((nout + 31) / 32), chunk = (nl + kLossChunks - 1) / kLossChunks;
     float* lp2 = s.lossp + nl;
@@ -1523,7 +1541,8 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
   for (int l = D - 1; l >= 0; --l) {
     const int64_t in = net->in_dim[l];
     const uint16_t* X = l == 0 ? s.X0 : s.H + (size_t)(l - 1) * B * W;
-    hipLaunchKernelGGL(k_colsum<float>, dim3(nblk(W, 16)), dim3(256), 0, str, s.dZ, B, W, net->grad + net->b_off[l]);
+    st = colsum(ctx, s.dZ, B, W, kColsumRows, s.cst, net->grad + net->b_off[l]);
+    if (st) return st;
     st = mm<false, false>(ctx, s.dZ16, W, X, in, W, in, B, kSplitW, EpiF32{s.part, in, W * in});
     if (st) return st;
     {
