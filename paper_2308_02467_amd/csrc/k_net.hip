@@ -1575,6 +1575,8 @@ el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const 
   if (!ctx || !cnet) return EL_ERR_ARG;
   if (out_dtype != EL_BF16 && out_dtype != EL_F32 && out_dtype != EL_F16)
     return set_error(ctx, EL_ERR_ARG, "el_infer: out_dtype");
+  if (precision != EL_FP64 && precision != EL_FP32_IR)
+    return set_error(ctx, EL_ERR_ARG, "el_infer: unknown fallback precision");
   if (E == 0) {
     if (n_fallback_host) *n_fallback_host = 0;
     return EL_OK;

@@ -65,6 +65,9 @@ def test_empty_batches(ctx):
     # an unknown enumerated argument is still an error with no elements
     with pytest.raises(el.ElError):
         ctx.el_local_solve(d, h, kap, sig, precision=7, in2out=f64(0, m, m))
+    with pytest.raises(el.ElError):
+        net.infer(d, h, kap, sig, torch.empty((0, m, m), dtype=torch.float32, device=DEV),
+                  torch.empty((0, n, m), dtype=torch.float32, device=DEV), None, fallback=True, precision=7)
     net.close()
 
 
