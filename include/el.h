@@ -320,27 +320,30 @@ el_status el_net_fit_normalization(el_ctx* ctx, el_net* net, int64_t N, const fl
 el_status el_net_params(el_ctx* ctx, const el_net* net, int which, float* dst);
 el_status el_net_num_params(const el_net* net, int64_t* n_params);
 
-/* Text report of the block tiles the GEMM autotuner chose so far in this
- * process, one line per GEMM shape (shape, chosen tile, timing of each
- * candidate in ms).  The autotuner times each candidate tile once, on the
- * first call of a shape, on that call's own operands.  Writes at most cap
+/* Text report of the autotuners' choices so far in this process, one line
+ * per key (key, chosen candidate, timing of each candidate in ms): the GEMM
+ * block tile per GEMM shape, timed once on the first call of a shape on that
+ * call's own operands, and the skeleton product's row shape per operator
+ * type and m, timed on the first product (el_trace_matvec) or before the
+ * first GMRES cycle (el_trace_solve) with such operators.  Writes at most cap
  * bytes (NUL-terminated) into host buf (may be NULL); *len (may be NULL)
  * receives the size needed including the NUL.  Never fails. */
 el_status el_tuning_report(char* buf, size_t cap, size_t* len);
 
-/* The autotuner's choices across processes.  el_tuning_save writes every
+/* The autotuners' choices across processes.  el_tuning_save writes every
  * choice made or loaded so far in this process to the text file at host
- * string path (created or replaced): a header line, then one line per GEMM
- * shape, "<key>\t<tile index>\t<tile name>", where the key begins with the
- * device architecture (e.g. gfx950).  el_tuning_load reads such a file; its
- * choices are used from then on instead of timing the candidates (a key is
- * only ever looked up on a device of its architecture); lines whose tile
- * index and name do not match a tile of this library are skipped.  *loaded
- * (may be NULL) receives the number of choices taken.  Both: EL_ERR_ARG for
- * a NULL path or a file that cannot be written / opened; el_tuning_load
- * also for a missing header or a malformed line, and then takes nothing.
- * el_tuning_reset forgets every choice of this process.  Host only; calls
- * that overlap with GEMMs on other threads are safe (one lock). */
+ * string path (created or replaced): a header line, then one line per key,
+ * "<key>\t<candidate index>\t<candidate name>", where the key begins with
+ * the device architecture (e.g. gfx950) and names the tuner (gemm or
+ * matvec).  el_tuning_load reads such a file; its choices are used from then
+ * on instead of timing the candidates (a key is only ever looked up on a
+ * device of its architecture); lines whose index and name do not match a
+ * candidate of this library are skipped.  *loaded (may be NULL) receives the
+ * number of choices taken.  Both: EL_ERR_ARG for a NULL path or a file that
+ * cannot be written / opened; el_tuning_load also for a missing header or a
+ * malformed line, and then takes nothing.  el_tuning_reset forgets every
+ * choice of this process.  Host only; calls that overlap with tuned launches
+ * on other threads are safe (one lock). */
 el_status el_tuning_save(const char* path);
 el_status el_tuning_load(const char* path, int64_t* loaded);
 el_status el_tuning_reset(void);
@@ -352,6 +355,13 @@ el_status el_tuning_reset(void);
  * autotuned tile).  For tests that pin one tile.  EL_ERR_ARG for another
  * value. */
 el_status el_gemm_tile(int variant);
+
+/* Row shape of the skeleton product in this process: -1 (default) = chosen
+ * per operator type and m by the autotuner; 0 = 4 rows x 4 chunks, 1 = 2 rows
+ * x 8 chunks, 2 = 8 rows x 2 chunks per 8-lane group (16 loads of 16 bytes in
+ * flight per lane).  For tests that pin one shape.  EL_ERR_ARG for another
+ * value. */
+el_status el_matvec_shape(int shape);
 
 /* Training pairs from the local solver (FP64 LU; FP32 LU with FP64
  * refinement when the FP64 factorization does not fit one workgroup, as at

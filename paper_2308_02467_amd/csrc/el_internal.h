@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -125,6 +126,23 @@ el_status launch_conserve(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const d
                           void* out, int out_dtype);
 el_status launch_mean_l2(el_ctx* ctx, el_ctx::DiscEntry* de, int64_t E, const double* h,
                          const double* a, const double* ref, double* out_host);
+
+// ---- autotuner registry ----------------------------------------------------------
+// Choices of the autotuners (GEMM block tile, skeleton-product row shape),
+// kept per process: key "<arch> <kind> <shape>" (kind "gemm" or "matvec") ->
+// the chosen candidate's index, the candidates' timings in ms (empty when the
+// choice was loaded from a file) and the candidates' names.  Thread-safe.
+bool tune_find(const std::string& key, int* choice);
+void tune_store(const std::string& key, int choice, const std::vector<float>& ms);
+// candidate names of each tuner, in index order (for reports and for checking
+// loaded choices against this library's candidates)
+std::vector<std::string> gemm_tile_names();
+std::vector<std::string> matvec_shape_names();
+// the skeleton product's row shape (index into matvec_shape_names()) for
+// in2out of op_dtype on this discretization: pinned, tuned, or timed now on
+// the product x -> y over mesh (y overwritten)
+el_status matvec_shape(el_ctx* ctx, el_ctx::DiscEntry* de, const el_mesh& mesh, const void* in2out, int op_dtype,
+                       const double* x, double* y, int* shape);
 
 inline int64_t mesh_faces(const el_mesh& m) {
   return (int64_t)(m.n_x + 1) * m.n_y + (int64_t)m.n_x * (m.n_y + 1);

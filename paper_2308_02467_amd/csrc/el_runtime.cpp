@@ -1,9 +1,11 @@
 // Host runtime of the C ABI: context, error text, cached discretization
 // tables on the device, workspace growth, argument checks and dispatch to
 // the kernel launchers.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <sstream>
 
 #include "el_internal.h"
@@ -102,9 +104,133 @@ static bool mesh_ok(const el_mesh& m) {
 
 }  // namespace el
 
+namespace el {
+
+namespace {
+struct TuneEntry {
+  int choice;
+  std::vector<float> ms;   // per candidate; empty when loaded from a file
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+
+// the tuner kind of a key "<arch> <kind> ..." and its candidates' names
+std::vector<std::string> names_of(const std::string& key) {
+  const size_t a = key.find(' ');
+  if (a == std::string::npos) return {};
+  const size_t b = key.find(' ', a + 1);
+  const std::string kind = key.substr(a + 1, b == std::string::npos ? std::string::npos : b - a - 1);
+  if (kind == "gemm") return gemm_tile_names();
+  if (kind == "matvec") return matvec_shape_names();
+  return {};
+}
+}  // namespace
+
+bool tune_find(const std::string& key, int* choice) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *choice = it->second.choice;
+  return true;
+}
+
+void tune_store(const std::string& key, int choice, const std::vector<float>& ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = TuneEntry{choice, ms};
+}
+
+}  // namespace el
+
 using namespace el;
 
 extern "C" {
+
+el_status el_tuning_report(char* buf, size_t cap, size_t* len) {
+  std::ostringstream os;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tune) {
+      const std::vector<std::string> names = names_of(kv.first);
+      const int c = kv.second.choice;
+      os << kv.first << " -> " << (kv.first.find(" gemm ") != std::string::npos ? "tile " : "shape ")
+         << (c >= 0 && c < (int)names.size() ? names[c] : std::string("?"));
+      if (kv.second.ms.empty()) {
+        os << " (from a cache file)\n";
+        continue;
+      }
+      os << " (ms:";
+      for (float t : kv.second.ms) os << ' ' << t;
+      os << ")\n";
+    }
+  }
+  const std::string s = os.str();
+  if (len) *len = s.size() + 1;
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return EL_OK;
+}
+
+// Cache file: a first line naming the format, then one line per choice:
+// "<key>\t<candidate index>\t<candidate name>".
+static const char kTuneHeader[] = "# el autotuner choices v2";
+
+el_status el_tuning_save(const char* path) {
+  if (!path) return EL_ERR_ARG;
+  std::ofstream f(path, std::ios::out | std::ios::trunc);
+  if (!f) return EL_ERR_ARG;
+  f << kTuneHeader << '\n';
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tune) {
+      const std::vector<std::string> names = names_of(kv.first);
+      const int c = kv.second.choice;
+      if (c < 0 || c >= (int)names.size()) continue;
+      f << kv.first << '\t' << c << '\t' << names[c] << '\n';
+    }
+  }
+  f.flush();
+  return f ? EL_OK : EL_ERR_ARG;
+}
+
+el_status el_tuning_load(const char* path, int64_t* loaded) {
+  if (loaded) *loaded = 0;
+  if (!path) return EL_ERR_ARG;
+  std::ifstream f(path);
+  if (!f) return EL_ERR_ARG;
+  std::string line;
+  if (!std::getline(f, line) || line != kTuneHeader) return EL_ERR_ARG;
+  // parse everything first: a malformed line leaves the choices unchanged
+  std::vector<std::pair<std::string, int>> take;
+  while (std::getline(f, line)) {
+    if (line.empty()) continue;
+    const size_t t1 = line.find('\t');
+    const size_t t2 = t1 == std::string::npos ? t1 : line.find('\t', t1 + 1);
+    if (t1 == 0 || t2 == std::string::npos || line.find('\t', t2 + 1) != std::string::npos) return EL_ERR_ARG;
+    const std::string key = line.substr(0, t1), idx = line.substr(t1 + 1, t2 - t1 - 1), name = line.substr(t2 + 1);
+    if (idx.empty() || idx.size() > 3 || idx.find_first_not_of("0123456789") != std::string::npos)
+      return EL_ERR_ARG;
+    const int v = std::stoi(idx);
+    // a kind or candidate this library numbers differently (or does not
+    // have) is skipped
+    const std::vector<std::string> names = names_of(key);
+    if (v >= (int)names.size() || names[v] != name) continue;
+    take.emplace_back(key, v);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : take) g_tune[kv.first] = TuneEntry{kv.second, {}};
+  if (loaded) *loaded = (int64_t)take.size();
+  return EL_OK;
+}
+
+el_status el_tuning_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return EL_OK;
+}
+
 
 el_status el_create(el_ctx** ctx, int device, void* hip_stream) {
   if (!ctx) return EL_ERR_ARG;

@@ -131,7 +131,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---- products -----------------------------------------------------------------
-template <typename OpT, bool IMP>
+template <typename OpT, bool IMP, int R>
 __global__ void __launch_bounds__(kMVThreads) k_bmatvec(DiscDev dv, const BMesh* __restrict__ ms, int n_mesh,
                                                          const BState* __restrict__ st, int pred,
                                                          const double* __restrict__ x, double* __restrict__ y) {
@@ -141,8 +141,8 @@ __global__ void __launch_bounds__(kMVThreads) k_bmatvec(DiscDev dv, const BMesh*
   const BMesh M = ms[mi];
   const int e = (int)((int64_t)blockIdx.x - M.e0);
   const MeshDev md{M.n_x, M.n_y, M.n_vf};
-  matvec_element<OpT, IMP>(dv, md, e, reinterpret_cast<const OpT*>(M.op) + (size_t)e * dv.m * dv.m, x + M.d0,
-                           y + M.d0, sm);
+  matvec_element<OpT, IMP, R>(dv, md, e, reinterpret_cast<const OpT*>(M.op) + (size_t)e * dv.m * dv.m, x + M.d0,
+                              y + M.d0, sm);
 }
 
 // ---- vector kernels (one block = kChunk DOFs of one mesh) ---------------------
@@ -529,6 +529,7 @@ struct Batch {
   DiscDev dv;
   int m;
   int op_dtype;
+  int mv_shape;      // row shape of the product (index into matvec_shape_names())
   int n_mesh;
   int64_t E, Np;
   int nblk;
@@ -554,8 +555,19 @@ struct Batch {
     const size_t smem = matvec_smem_bytes(m);
     with_op_type(op_dtype, [&](auto tag) {
       using T = decltype(tag);
-      hipLaunchKernelGGL((k_bmatvec<T, IMP>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st, pred,
-                         x, y);
+      switch (mv_shape) {
+        case 1:
+          hipLaunchKernelGGL((k_bmatvec<T, IMP, 2>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
+                             pred, x, y);
+          break;
+        case 2:
+          hipLaunchKernelGGL((k_bmatvec<T, IMP, 8>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
+                             pred, x, y);
+          break;
+        default:
+          hipLaunchKernelGGL((k_bmatvec<T, IMP, 4>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
+                             pred, x, y);
+      }
     });
   }
   void matvec(hipStream_t s, int pred, const double* x, double* y, bool imp) const {
@@ -687,6 +699,10 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   for (int i = 0; i < n_mesh && he == hipSuccess; ++i)
     he = hipMemcpyAsync(bt.bcat + hm[i].d0, b[i], sizeof(double) * hm[i].N, hipMemcpyDeviceToDevice, s);
   if (he != hipSuccess) return hip_check(ctx, he, "el_trace_solve: staging");
+  // the product's row shape (timed on the first mesh's product b -> tmp when
+  // this operator type and size are new), fixed before the cycle is captured
+  stt = matvec_shape(ctx, de, meshes[0], in2out[0], op_dtype, bt.bcat, bt.tmp, &bt.mv_shape);
+  if (stt) return stt;
   hipLaunchKernelGGL(k_bzero, dim3(nblocks(Np, 256)), dim3(256), 0, s, bt.xcat, Np);
   if (opts.x0)   // starting guess (the padding between segments stays zero)
     for (int i = 0; i < n_mesh && he == hipSuccess; ++i)
@@ -704,7 +720,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   // graph of one restart cycle, cached on the context
   std::ostringstream key;
   key << base << ':' << R << ':' << n_mesh << ':' << E << ':' << Np << ':' << nblk << ':' << op_dtype << ':'
-      << (const void*)de << ':' << opts.tol << ':' << opts.max_iter << ':' << f32;
+      << (const void*)de << ':' << opts.tol << ':' << opts.max_iter << ':' << f32 << ':' << bt.mv_shape;
   bool use_graph = opts.graph != 0;
   if (use_graph && (ctx->gm_key != key.str() || !ctx->gm_exec)) {
     if (ctx->gm_exec) {

@@ -772,9 +772,6 @@ inline std::string tile_name(const TileVariant& v) {
 constexpr TileVariant kVariants[] = {{2, 2, false}, {1, 2, false}, {2, 1, false}, {4, 4, true}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-std::mutex g_tune_mu;
-// key ("<arch> gemm ...") -> (choice, ms per variant; empty when loaded from a file)
-std::map<std::string, std::pair<int, std::vector<float>>> g_tune;
 std::atomic<int> g_force_tile{-1};   // >= 0: this variant wherever it applies (el_gemm_tile)
 
 // an epilogue that stages per-element inputs (ld = N) in LDS needs 16-byte
@@ -832,12 +829,7 @@ el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int
        << " K=" << K << " splits=" << splits;
     const std::string key = ks.str();
     int choice = -1;
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      auto it = g_tune.find(key);
-      if (it != g_tune.end()) choice = it->second.first;
-    }
-    if (choice < 0) {
+    if (!tune_find(key, &choice) || choice < 0 || choice >= kNumVariants) {
       std::vector<float> ms(kNumVariants, 0.f);
       hipEvent_t e0, e1;
       if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -862,8 +854,7 @@ el_status mm(el_ctx* ctx, const uint16_t* A, int64_t lda, const uint16_t* B, int
       hipEventDestroy(e0);
       hipEventDestroy(e1);
       choice = best;
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune[key] = {choice, ms};
+      tune_store(key, choice, ms);
     }
     return mm_variant<A_KC, B_KC, Epi>(ctx, choice, A, lda, B, ldb, M, N, K, splits, epi, m_fast);
   }
@@ -1269,6 +1260,12 @@ el_status noalloc_init(el_ctx* ctx) {
 el_status launch_local_solve_ex(el_ctx* ctx, el_ctx::DiscEntry* de, int precision, int64_t E, const double* h,
                                 const double* kappa, const double* sigma, const int32_t* emap, void* o_i2o,
                                 void* o_i2v, int form, int out_dtype, uint16_t* pairs);
+
+std::vector<std::string> gemm_tile_names() {
+  std::vector<std::string> v;
+  for (int i = 0; i < kNumVariants; ++i) v.push_back(tile_name(kVariants[i]));
+  return v;
+}
 
 }  // namespace el
 
@@ -1730,86 +1727,9 @@ el_status el_infer_noalloc(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E
   return hip_check(ctx, hipGetLastError(), "el_infer_noalloc");
 }
 
-// Cache file: a first line naming the format, then one line per choice:
-// "<key>\t<tile index>\t<tile name>".
-static const char kTuneHeader[] = "# el GEMM autotuner choices v1";
-
-el_status el_tuning_save(const char* path) {
-  if (!path) return EL_ERR_ARG;
-  std::ofstream f(path, std::ios::out | std::ios::trunc);
-  if (!f) return EL_ERR_ARG;
-  f << kTuneHeader << '\n';
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (auto& kv : g_tune)
-      f << kv.first << '\t' << kv.second.first << '\t' << tile_name(kVariants[kv.second.first]) << '\n';
-  }
-  f.flush();
-  return f ? EL_OK : EL_ERR_ARG;
-}
-
-el_status el_tuning_load(const char* path, int64_t* loaded) {
-  if (loaded) *loaded = 0;
-  if (!path) return EL_ERR_ARG;
-  std::ifstream f(path);
-  if (!f) return EL_ERR_ARG;
-  std::string line;
-  if (!std::getline(f, line) || line != kTuneHeader) return EL_ERR_ARG;
-  // parse everything first: a malformed line leaves the choices unchanged
-  std::vector<std::pair<std::string, int>> take;
-  while (std::getline(f, line)) {
-    if (line.empty()) continue;
-    const size_t t1 = line.find('\t');
-    const size_t t2 = t1 == std::string::npos ? t1 : line.find('\t', t1 + 1);
-    if (t1 == 0 || t2 == std::string::npos || line.find('\t', t2 + 1) != std::string::npos) return EL_ERR_ARG;
-    const std::string key = line.substr(0, t1), idx = line.substr(t1 + 1, t2 - t1 - 1), name = line.substr(t2 + 1);
-    if (idx.empty() || idx.size() > 3 || idx.find_first_not_of("0123456789") != std::string::npos)
-      return EL_ERR_ARG;
-    const int v = std::stoi(idx);
-    // a tile this library numbers differently (or does not have) is skipped
-    if (v >= kNumVariants || tile_name(kVariants[v]) != name) continue;
-    take.emplace_back(key, v);
-  }
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  for (auto& kv : take) g_tune[kv.first] = {kv.second, {}};
-  if (loaded) *loaded = (int64_t)take.size();
-  return EL_OK;
-}
-
-el_status el_tuning_reset(void) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune.clear();
-  return EL_OK;
-}
-
 el_status el_gemm_tile(int variant) {
   if (variant < -1 || variant >= kNumVariants) return EL_ERR_ARG;
   g_force_tile.store(variant);
-  return EL_OK;
-}
-
-el_status el_tuning_report(char* buf, size_t cap, size_t* len) {
-  std::ostringstream os;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (auto& kv : g_tune) {
-      os << kv.first << " -> tile " << tile_name(kVariants[kv.second.first]);
-      if (kv.second.second.empty()) {
-        os << " (from a cache file)\n";
-        continue;
-      }
-      os << " (ms:";
-      for (float t : kv.second.second) os << ' ' << t;
-      os << ")\n";
-    }
-  }
-  const std::string s = os.str();
-  if (len) *len = s.size() + 1;
-  if (buf && cap > 0) {
-    const size_t n = std::min(cap - 1, s.size());
-    std::memcpy(buf, s.data(), n);
-    buf[n] = 0;
-  }
   return EL_OK;
 }
 

@@ -131,18 +131,20 @@ __device__ inline double row_dot<_Float16>(const _Float16* __restrict__ row, con
 // once: groups of 8 lanes, 16-byte loads.  The loads of a batch of KB chunks
 // per lane and row are all issued before any product (R KB = 16 loads in
 // flight per lane; m is a multiple of 8, so chunks never straddle the row
-// end).  rows[r]: start of row r; a[r]: its partial sum of this lane.
-template <typename OpT>
+// end).  rows[r]: start of row r; a[r]: its partial sum of this lane.  The
+// row shape R (2, 4 or 8 rows per group and pass) is chosen per operator
+// type and m by the skeleton-product tuner.
+template <typename OpT, int R_>
 struct RowShape {
   static constexpr int V = 16 / sizeof(OpT);          // entries per 16-byte chunk
-  static constexpr int R = sizeof(OpT) == 2 ? 4 : 2;  // rows per group and pass
+  static constexpr int R = R_;                        // rows per group and pass
   static constexpr int KB = 16 / R;                   // chunks per lane and row in a batch
+  static_assert(R * KB == 16, "16 loads in flight per lane");
 };
 
-template <typename OpT>
-__device__ inline void row_dots(const OpT* const (&rows)[RowShape<OpT>::R], const double* tin, int m, int gl,
-                                double (&a)[RowShape<OpT>::R]) {
-  constexpr int V = RowShape<OpT>::V, R = RowShape<OpT>::R, KB = RowShape<OpT>::KB;
+template <typename OpT, int R_>
+__device__ inline void row_dots(const OpT* const (&rows)[R_], const double* tin, int m, int gl, double (&a)[R_]) {
+  constexpr int V = RowShape<OpT, R_>::V, R = R_, KB = RowShape<OpT, R_>::KB;
   typedef OpT vec __attribute__((ext_vector_type(V)));
 #pragma unroll
   for (int r = 0; r < R; ++r) a[r] = 0.0;
@@ -187,7 +189,7 @@ __host__ __device__ inline size_t matvec_smem_bytes(int m) { return (2 * sizeof(
 // vectors; sm: matvec_smem_bytes(m) of LDS.  Every index and x value the
 // element needs is fetched up front, one per thread, so the row loop waits
 // only on the operator stream.
-template <typename OpT, bool IMP = true>
+template <typename OpT, bool IMP, int R>
 __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int e, const OpT* __restrict__ op_e,
                                       const double* __restrict__ x, double* __restrict__ y, double* sm) {
   const int i = e % ms.n_x, j = e / ms.n_x;
@@ -219,13 +221,12 @@ __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int 
   };
   // R rows per group at a time (rows past the end repeat the group's first
   // row: loaded, not stored)
-  constexpr int R = RowShape<OpT>::R;
   for (int o = wave * 8 + g; o < m; o += R * kRowStep) {
     const OpT* rows[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) rows[r] = op_e + (size_t)(o + r * kRowStep < m ? o + r * kRowStep : o) * m;
     double a[R];
-    row_dots<OpT>(rows, tin, m, gl, a);
+    row_dots<OpT, R>(rows, tin, m, gl, a);
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (o + r * kRowStep < m) finish(o + r * kRowStep, a[r]);

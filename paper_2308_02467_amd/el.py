@@ -95,6 +95,7 @@ _SIGS = {
     "el_trace_matvec": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_void_p],
     "el_gemm_tile": [ctypes.c_int],
+    "el_matvec_shape": [ctypes.c_int],
     "el_tuning_report": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "el_tuning_save": [ctypes.c_char_p],
     "el_tuning_load": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
@@ -594,6 +595,14 @@ def tuning_load(path):
 def tuning_reset():
     """Forget every autotuner choice of this process (el_tuning_reset)."""
     lib().el_tuning_reset()
+
+
+def matvec_shape(shape):
+    """Pin the skeleton product's row shape (el_matvec_shape); -1 restores
+    the autotuner."""
+    st = lib().el_matvec_shape(int(shape))
+    if st != 0:
+        raise ValueError(f"el_matvec_shape: bad shape {shape}")
 
 
 def gemm_tile(variant):

@@ -65,6 +65,20 @@ def test_bad_disc_rejected():
         el.disc_sizes(el.disc(0, 8))
 
 
+def test_matvec_shape_pin_validates_its_argument():
+    """el_matvec_shape is host-only: -1 (autotuner) and the three row shapes
+    are accepted, anything else is EL_ERR_ARG."""
+    from paper_2308_02467_amd import el
+    L = el.lib()
+    for v in (-1, 0, 1, 2, -1):
+        assert L.el_matvec_shape(v) == 0, v
+    for v in (-2, 3, 1 << 20):
+        assert L.el_matvec_shape(v) != 0, v
+    with pytest.raises(ValueError):
+        el.matvec_shape(5)
+    el.matvec_shape(-1)
+
+
 def test_gemm_tile_pin_validates_its_argument():
     """el_gemm_tile is host-only: -1 (autotuner) and the four tiles are
     accepted, anything else is EL_ERR_ARG and leaves the setting alone."""

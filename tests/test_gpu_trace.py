@@ -67,9 +67,24 @@ def test_trace_rhs_bit_exact(ctx):
     assert np.array_equal(b.cpu().numpy(), ref)
 
 
-@pytest.mark.parametrize("p,n_a,nx,ny", [(3, 8, 4, 4), (6, 16, 3, 2)])
-def test_matvec_f64_and_bf16(ctx, p, n_a, nx, ny):
+@pytest.fixture
+def matvec_shape():
+    """Pins the skeleton product's row shape for one test and restores the
+    autotuner."""
     from paper_2308_02467_amd import el
+    yield el.matvec_shape
+    el.matvec_shape(-1)
+
+
+# shape -1: the autotuner's choice; 0-2: the three row shapes pinned
+MV_SHAPES = [-1, 0, 1, 2]
+
+
+@pytest.mark.parametrize("shape", MV_SHAPES)
+@pytest.mark.parametrize("p,n_a,nx,ny", [(3, 8, 4, 4), (6, 16, 3, 2)])
+def test_matvec_f64_and_bf16(ctx, matvec_shape, shape, p, n_a, nx, ny):
+    from paper_2308_02467_amd import el
+    matvec_shape(shape)
     od, oms, hh, kap, sig = mesh_problem(p, n_a, nx, ny)
     i2o, _, _ = local_solve_batch(od, hh, kap, sig)
     ind, outd = oms.element_dofs(od)
@@ -77,7 +92,7 @@ def test_matvec_f64_and_bf16(ctx, p, n_a, nx, ny):
     nt = el.trace_size(d, ms)
     x = np.random.default_rng(1).standard_normal(nt)
     y = torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV)
-    print(f"[el_trace_matvec] p={p} n_a={n_a} {nx}x{ny} f64", flush=True)
+    print(f"[el_trace_matvec] p={p} n_a={n_a} {nx}x{ny} shape={shape} f64", flush=True)
     ctx.el_trace_matvec(d, ms, T(i2o), T(x), y)
     ref = otrace.matvec(i2o, ind, outd, x)
     assert rel_err(y.cpu().numpy(), ref) <= 1e-13
@@ -98,6 +113,12 @@ def test_matvec_f64_and_bf16(ctx, p, n_a, nx, ny):
     ctx.el_trace_matvec(d, ms, oph, T(x), y)
     refh = otrace.matvec(oph.to(torch.float64).cpu().numpy(), ind, outd, x)
     assert rel_err(y.cpu().numpy(), refh) <= 1e-13
+    if shape < 0:
+        # the autotuner timed the row shapes for each operator type of this m
+        m = el.disc_sizes(d)[2]
+        rep = el.tuning_report()
+        for name in ("f64", "bf16", "f32", "f16"):
+            assert f" matvec {name} m={m} -> shape " in rep, rep
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.bfloat16])
@@ -459,14 +480,16 @@ def test_batched_uneven_meshes_parity(ctx, basis):
         assert rel_err(t, ref["t"]) <= 1e-10, (oms.n_x, oms.n_y, rel_err(t, ref["t"]))
 
 
+@pytest.mark.parametrize("shape", MV_SHAPES)
 @pytest.mark.parametrize("basis", [torch.float64, torch.float32])
 @pytest.mark.parametrize("dtype", [torch.float16, torch.float32])
-def test_batched_rounded_operators_parity(ctx, dtype, basis):
+def test_batched_rounded_operators_parity(ctx, matvec_shape, shape, dtype, basis):
     """GMRES over several meshes with FP16 / FP32 operators (the storage of
     the learned step), with either Krylov basis: the solution of
     (I - P~) t = b with the rounded operators P~, against the oracle's direct
     solve with the same rounded operators."""
     from paper_2308_02467_amd import el
+    matvec_shape(shape)
     p, n_a = 3, 8
     probs = _batched_problem(p, n_a)[:4]
     d = el.disc(p, n_a)
@@ -487,7 +510,7 @@ def test_batched_rounded_operators_parity(ctx, dtype, basis):
         ops.append(op)
         bs.append(b)
         ts.append(torch.full((nt,), float("nan"), dtype=torch.float64, device=DEV))
-    print(f"[batched] el_trace_solve {dtype} basis={basis} n_mesh={len(meshes)}", flush=True)
+    print(f"[batched] el_trace_solve {dtype} basis={basis} shape={shape} n_mesh={len(meshes)}", flush=True)
     st, rep = ctx.el_trace_solve(d, meshes, ops, bs, ts, tol=1e-12, restart=20, max_iter=3000, basis=basis)
     assert st == 0
     for r, t, ref in zip(rep, ts, refs):

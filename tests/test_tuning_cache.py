@@ -4,7 +4,7 @@ import pytest
 
 from paper_2308_02467_amd import el
 
-HEADER = "# el GEMM autotuner choices v1"
+HEADER = "# el autotuner choices v2"
 
 
 @pytest.fixture(autouse=True)
@@ -24,27 +24,32 @@ def test_load_save_round_trip(tmp_path):
         HEADER,
         "gfx950 gemm AB hidden M=16384 N=1024 K=1024 splits=1\t3\t256x256 direct-to-LDS",
         "gfx942 gemm AtBt f32 M=1024 N=128 K=4096 splits=8\t2\t128x64",
+        "gfx950 matvec f16 m=224\t1\t2 rows x 8 chunks",
         "",
+        # a tuner kind this library does not have: skipped
+        "gfx950 lu f64 n=784\t0\t7 tiles",
         # a tile index this library names differently, and one it does not have: skipped
         "gfx950 gemm AB mae M=4096 N=225792 K=1024 splits=1\t1\t128x128",
         "gfx950 gemm AB f32 M=1 N=1 K=1 splits=1\t99\t64x64",
     ])
-    assert el.tuning_load(src) == 2
+    assert el.tuning_load(src) == 3
     rep = el.tuning_report()
     assert "gfx950 gemm AB hidden M=16384 N=1024 K=1024 splits=1 -> tile 256x256 direct-to-LDS (from a cache file)" in rep
     assert "gfx942 gemm AtBt f32 M=1024 N=128 K=4096 splits=8 -> tile 128x64 (from a cache file)" in rep
-    assert "mae" not in rep and "M=1 N=1" not in rep
+    assert "gfx950 matvec f16 m=224 -> shape 2 rows x 8 chunks (from a cache file)" in rep
+    assert "mae" not in rep and "M=1 N=1" not in rep and " lu " not in rep
     out = tmp_path / "out.txt"
     el.tuning_save(out)
     lines = out.read_text().splitlines()
     assert lines[0] == HEADER
     assert sorted(lines[1:]) == sorted([
         "gfx950 gemm AB hidden M=16384 N=1024 K=1024 splits=1\t3\t256x256 direct-to-LDS",
-        "gfx942 gemm AtBt f32 M=1024 N=128 K=4096 splits=8\t2\t128x64"])
+        "gfx942 gemm AtBt f32 M=1024 N=128 K=4096 splits=8\t2\t128x64",
+        "gfx950 matvec f16 m=224\t1\t2 rows x 8 chunks"])
     # a second load of the saved file takes the same choices
     el.tuning_reset()
     assert el.tuning_report() == ""
-    assert el.tuning_load(out) == 2
+    assert el.tuning_load(out) == 3
     assert el.tuning_report() == rep
 
 
