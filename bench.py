@@ -125,7 +125,16 @@ def log(msg):
 MATVEC_SOURCES = ("paper_2308_02467_amd/csrc/trace_dev.h", "paper_2308_02467_amd/csrc/k_trace.hip",
                   "paper_2308_02467_amd/csrc/el_internal.h")
 TRAFFIC_SUMMARY = {"float16": "profiles/k_matvec_f16_128x128_p6_na16_hbm_traffic.md"}
-MATVEC_KERNEL = {"float32": "k_matvec<float>", "float16": "k_matvec<_Float16>"}
+MATVEC_ELEM = {"float32": ("f32", "float"), "float16": ("f16", "_Float16")}
+
+
+def matvec_kernel(el, op_dtype, m):
+    """Name of the skeleton product kernel that runs for operators stored as
+    op_dtype with m trace unknowns per element: the row count in its name is
+    the shape the autotuner chose for that pair (its tuning report line)."""
+    short, elem = MATVEC_ELEM[op_dtype]
+    hit = re.search(r" matvec " + short + r" m=" + str(m) + r" -> shape (\d+) rows", el.tuning_report())
+    return f"k_matvec<{elem}, {hit.group(1)}>" if hit else f"k_matvec<{elem}, ?>"
 
 
 def act_code(el, args):
@@ -146,15 +155,16 @@ def matvec_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(op_dtype):
-    """HBM bytes per launch of the skeleton product with operators stored as
-    op_dtype, from the committed rocprofv3 counter summary, or None when the
+def recorded_traffic(op_dtype, kernel):
+    """HBM bytes per launch of the skeleton product kernel `kernel` with
+    operators stored as op_dtype, from the committed rocprofv3 counter
+    summary, or None when the summary holds no line for that kernel or the
     kernel's source changed since."""
     try:
         text = open(os.path.join(ROOT, TRAFFIC_SUMMARY[op_dtype])).read()
     except (OSError, KeyError):
         return None
-    kern = re.escape(MATVEC_KERNEL[op_dtype])
+    kern = re.escape(kernel)
     m = re.search(r"traffic_bytes_per_launch " + kern + r" = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
     if not m or m.group(2) != matvec_source_hash():
         return None
@@ -861,6 +871,7 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, i2m_pl
     mv_ms = e0.elapsed_time(e1) / reps
     mv_bytes = E * m * (m * esz + 3 * 8)        # operator + gathered inflow + outflow read/write
     mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+    mv_kernel = matvec_kernel(el, args.op_dtype, m)
 
     study = storage_study(args, ctx, net, d, ms, hh, kap, sig, g_side, b, mean_plain, E, n, m) \
         if args.storage_study else None
@@ -916,9 +927,9 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, i2m_pl
         "fp64_basis_gmres": rec64[-1][1],
         "mean_rel_l2_vs_converged": conv,
         "roofline_matvec": {"bound": "hbm",
-                            "kernel": f"{MATVEC_KERNEL[args.op_dtype]} (element body shared with the GMRES product)",
-                            "achieved": mv_gbs, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(args.op_dtype),
+                            "kernel": f"{mv_kernel} (element body shared with the GMRES product)",
+                            "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS,
+                            "traffic": recorded_traffic(args.op_dtype, mv_kernel),
                             "bytes_per_launch": mv_bytes, "avg_launch_ms": mv_ms},
     }
     net.close()

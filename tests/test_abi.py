@@ -106,24 +106,36 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_recorded_matvec_traffic_is_tied_to_the_source(tmp_path, monkeypatch):
     """The roofline's measured traffic comes from the committed counter
-    summary only while the skeleton-product sources keep its hash: a summary
-    carrying the current hash gives its figure, one with any other hash gives
-    None; other operator types have no recorded traffic."""
+    summary only while the skeleton-product sources keep its hash and only
+    for the row shape the autotuner chose: a summary line for that kernel with
+    the current hash gives its figure; another hash, another shape or another
+    operator type gives None."""
     import importlib.util
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
     assert "paper_2308_02467_amd/csrc/el_internal.h" in bench.MATVEC_SOURCES   # the DiscDev layout
     text = open(os.path.join(ROOT, bench.TRAFFIC_SUMMARY["float16"])).read()
-    assert re.search(r"traffic_bytes_per_launch k_matvec<_Float16> = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)", text)
+    assert re.search(r"traffic_bytes_per_launch k_matvec<_Float16, \d> = ([0-9.eE+]+) source_sha256 = ([0-9a-f]+)",
+                     text)
+
+    class FakeEl:
+        @staticmethod
+        def tuning_report():
+            return ("gfx950 gemm M=16384 N=225792 K=1024 -> tile 256x256 lds (ms: 8.5 9.1)\n"
+                    "gfx950 matvec f16 m=224 -> shape 4 rows x 4 chunks (ms: 0.317 0.320 0.345)\n")
+    k4 = bench.matvec_kernel(FakeEl, "float16", 224)
+    assert k4 == "k_matvec<_Float16, 4>"
+    assert bench.matvec_kernel(FakeEl, "float16", 120) == "k_matvec<_Float16, ?>"
     cur = bench.matvec_source_hash()
     for sha, expect in ((cur, 1.5e9), ("0" * 64, None)):
         os.makedirs(tmp_path / "profiles", exist_ok=True)
         (tmp_path / bench.TRAFFIC_SUMMARY["float16"]).write_text(
-            f"traffic_bytes_per_launch k_matvec<_Float16> = 1.5e9 source_sha256 = {sha}\n")
+            f"traffic_bytes_per_launch k_matvec<_Float16, 4> = 1.5e9 source_sha256 = {sha}\n")
         for f in bench.MATVEC_SOURCES:
             os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
             (tmp_path / f).write_bytes(open(os.path.join(ROOT, f), "rb").read())
         monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-        assert bench.recorded_traffic("float16") == expect
-    assert bench.recorded_traffic("float32") is None
+        assert bench.recorded_traffic("float16", k4) == expect
+        assert bench.recorded_traffic("float16", "k_matvec<_Float16, 2>") is None
+    assert bench.recorded_traffic("float32", "k_matvec<float, 4>") is None
