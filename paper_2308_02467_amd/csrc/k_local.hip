@@ -106,6 +106,7 @@ struct LuArgs {
   int ir_steps;
   double ir_tol;
   int ir_cols;          // solution columns staged in LDS per residual pass (8, 4 or 2)
+  const double* Tt;     // refinement: transport table transposed per ordinate [n_a][nn][nn]
 };
 
 // Entry (i, j) of the padded local matrix A (identity outside n x n).
@@ -536,6 +537,140 @@ __device__ inline void panel_solve2(T* pan, T* rs, T* bbuf, const T* fac, const 
   __syncthreads();
 }
 
+// Partial-pivoting factorization of the 16 columns of the LDS panel, rows
+// [J, npad) in logical order, with the rows held in registers: thread tid
+// owns the rows that sit at logical positions J + tid + kThreads k when the
+// panel starts (their "home"), R of them at most.  Rows never move while
+// the columns are eliminated; each thread tracks the current logical
+// position of its rows.  One barrier per column: every wave publishes its
+// best candidate (key, position, 16 values) to its slot in cand (two sets
+// of slots, alternating by column, so that a slot is rewritten only after
+// every thread has passed the barrier that follows its last read); after
+// the barrier all threads pick the same winner, which takes position J + c
+// (the row there takes the winner's old position), and every other live row
+// is eliminated by it.  The key orders candidates by |value| (the top 32
+// bits of its FP64 pattern, monotonic for non-negative values), then by the
+// lower home position; a NaN ranks below every number, so that a column
+// without a nonzero candidate still picks a row (and is reported singular).
+// On return the rows are back in pan at their final logical positions and
+// perm is permuted to match.  All threads call it; it ends on a barrier.
+// rows per thread of factor_panel for at most kWaves * MAXT row tiles
+template <int MAXT>
+constexpr int kMaxRows = (kWaves * MAXT * NB + kThreads - 1) / kThreads;
+
+template <typename T, int R>
+__device__ __attribute__((noinline)) void factor_panel(T* pan_g, int* perm_g, T* cand_g, int* sflag_g, int J,
+                                                       int npad, int tid) {
+  J = __builtin_amdgcn_readfirstlane(J);
+  npad = __builtin_amdgcn_readfirstlane(npad);
+  lptr<T> pan = (lptr<T>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<T>)pan_g);
+  lptr<int> perm = (lptr<int>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<int>)perm_g);
+  lptr<T> cval = (lptr<T>)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lptr<T>)cand_g);
+  lptr<unsigned long long> ckey = (lptr<unsigned long long>)(cval + 2 * kWaves * NB);
+  lptr<int> cpos = (lptr<int>)(ckey + 2 * kWaves);
+  const int wave = tid >> 6;
+  auto key_of = [](T v, int home) -> unsigned long long {
+    const double a = fabs((double)v);
+    const uint32_t hi = a == a ? (uint32_t)((unsigned long long)__double_as_longlong(a) >> 32) + 2u : 1u;
+    return ((unsigned long long)hi << 32) | (unsigned long long)(0xffffffffu - (uint32_t)home);
+  };
+  T row[R][NB];
+  int pos[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int r = J + tid + kThreads * k;
+    pos[k] = r < npad ? r : -1;   // -1: no row
+#pragma unroll
+    for (int j = 0; j < NB; ++j) row[k][j] = r < npad ? pan[r * LDP + j] : T(0);
+  }
+  unsigned long long best = 0ull;
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (pos[k] >= J) {
+      const unsigned long long kk = key_of(row[k][0], J + tid + kThreads * k);
+      best = kk > best ? kk : best;
+    }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int par = (c & 1) * kWaves;
+    unsigned long long wk = best;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(wk, off);
+      wk = o > wk ? o : wk;
+    }
+    if (wk == 0ull) {
+      if ((tid & 63) == 0) ckey[par + wave] = 0ull;
+    } else if (best == wk) {
+      // this lane holds the wave's best row
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+        if (pos[k] >= J + c && key_of(row[k][c], J + tid + kThreads * k) == wk) {
+#pragma unroll
+          for (int j = 0; j < NB; ++j) cval[(par + wave) * NB + j] = row[k][j];
+          cpos[par + wave] = pos[k];
+        }
+      ckey[par + wave] = wk;
+    }
+    __syncthreads();
+    unsigned long long gk = ckey[par];
+    int gw = 0;
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+      const unsigned long long o = ckey[par + w];
+      if (o > gk) { gk = o; gw = w; }
+    }
+    const int ghome = (int)(0xffffffffu - (uint32_t)gk);
+    const int gpos = cpos[par + gw];
+    // the pivot row (loops over all 16 columns with the column test inside,
+    // so that their trip counts are constant before the column loop is
+    // unrolled and the row arrays stay in registers)
+    T pr[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) pr[j] = j >= c ? cval[(par + gw) * NB + j] : T(0);
+    const T piv = pr[c];
+    if (tid == 0 && !(fabs((double)piv) > 0.0)) sflag_g[0] = 1;
+    const T rp = piv != T(0) ? T(1) / piv : T(0);
+    best = 0ull;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int home = J + tid + kThreads * k;
+      if (pos[k] >= J + c) {
+        if (home == ghome) {
+          pos[k] = J + c;
+        } else {
+          if (pos[k] == J + c) pos[k] = gpos;   // makes room for the pivot row
+          const T l = row[k][c] * rp;
+          row[k][c] = l;
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            if (j > c) row[k][j] -= l * pr[j];
+          if (c + 1 < NB) {
+            const unsigned long long kk = key_of(row[k][c + 1], home);
+            best = kk > best ? kk : best;
+          }
+        }
+      }
+    }
+  }
+  // rows and perm to their final logical positions
+  int pv[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int home = J + tid + kThreads * k;
+    pv[k] = pos[k] >= 0 ? perm[home] : 0;
+    if (pos[k] >= 0) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) pan[pos[k] * LDP + j] = row[k][j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (pos[k] >= 0) perm[pos[k]] = pv[k];
+  __syncthreads();
+}
+
 __device__ inline void argmax_combine(double& v, int& i, double v2, int i2) {
   if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
 }
@@ -549,76 +684,89 @@ __host__ __device__ inline size_t lds_base_bytes(int npad, int nn) {
   return (b + 15) / 16 * 16;
 }
 
-// FP64 residual of a solution panel for the refinement: for the rows of the
-// panel (logical order), pan[i][c] = (-B_hat - A x)[perm[i]][c], x the FP64
+// FP64 residual of a solution panel for the refinement: for every equation
+// q (natural order), pan[pinv[q]][c] = (-B_hat - A x)[q][c], x the FP64
 // solution panel xg [npad][NB] in HBM, using the structure of A (per-ordinate
 // transport blocks, node-diagonal M and S); colmax[c] = max |residual| of
-// column c.  x is staged through LDS (xs, npad x XC doubles) XC columns at a
-// time.  All threads call it; it ends on a barrier.
+// column c.  x is staged through LDS column by column (xs [XC][npad]
+// doubles), XC columns at a time.  Consecutive threads take consecutive
+// equations, so that the reads of x are conflict-free and those of the
+// transposed transport table Tt (Tt[k][j][i] = T[k][i][j]) are coalesced.
+// All threads call it; it ends on a barrier.
 template <typename T, int XC>
-__device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, const double* tau_e,
+__device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* pinv, const int* corder, const double* tau_e,
                                    const double* tau_s, const double* xg, double* xs, unsigned long long* colmax,
                                    int npad, int P0, int tid, int64_t e, double he) {
   const DiscDev& dv = a.dv;
-  const int n = dv.n, m = dv.m, nn = dv.nn;
+  const int n = dv.n, m = dv.m, nn = dv.nn, qd = dv.q, n_a = dv.n_a;
   for (int c0 = 0; c0 < NB; c0 += XC) {
     for (int idx = tid; idx < npad * XC; idx += kThreads) {
       const int r = idx / XC, c = idx % XC;
-      xs[idx] = xg[r * NB + c0 + c];
+      xs[c * npad + r] = xg[r * NB + c0 + c];
     }
+    // the right-hand side's nonzero of each column (one per inflow column)
+    int irow[XC];
+    double ival[XC];
+#pragma unroll
+    for (int c = 0; c < XC; ++c) {
+      const int slot = P0 + c0 + c;
+      irow[c] = slot < m ? dv.in_row[corder[slot]] : -1;
+      ival[c] = slot < m ? dv.in_val[corder[slot]] : 0.0;
+    }
+    const bool src_col = a.src && P0 + c0 <= m && m < P0 + c0 + XC;
     __syncthreads();
     // running max of |residual| per column as bit patterns (a NaN beats
     // every number), reduced over the wave before one atomic per column
     unsigned long long mb[XC];
 #pragma unroll
     for (int c = 0; c < XC; ++c) mb[c] = 0ull;
-    for (int i = tid; i < npad; i += kThreads) {
-      const int q = perm[i];
+    for (int q = tid; q < npad; q += kThreads) {
       double acc[XC];
       if (q >= n) {
 #pragma unroll
-        for (int c = 0; c < XC; ++c) acc[c] = -xs[q * XC + c];
+        for (int c = 0; c < XC; ++c) acc[c] = -xs[c * npad + q];
       } else {
         const int k = q / nn, nd = q - k * nn;
-        const int qd = dv.q, na = nd % qd, nb = nd / qd;
-        const double* Trow = dv.T + ((size_t)k * nn + nd) * nn;
-        const double* xk = xs + (size_t)k * nn * XC;
+        const int na = nd % qd, nb = nd / qd;
+        const double* Tk = a.Tt + (size_t)k * nn * nn;
+        const double* xk = xs + k * nn;
 #pragma unroll
         for (int c = 0; c < XC; ++c) acc[c] = 0.0;
         // the transport block row has nonzeros only at trial nodes in the
         // same node row (c', nb) or the same node column (na, d'): 2q - 1 of
         // the nn entries
+#pragma unroll 4
         for (int u = 0; u < qd; ++u) {
-          const double t1 = Trow[nb * qd + u];
-          const double* xr = xk + (nb * qd + u) * XC;
+          const int j1 = nb * qd + u;
+          const double t1 = Tk[j1 * nn + nd];
 #pragma unroll
-          for (int c = 0; c < XC; ++c) acc[c] += t1 * xr[c];
+          for (int c = 0; c < XC; ++c) acc[c] += t1 * xk[c * npad + j1];
           if (u != nb) {
-            const double t2 = Trow[u * qd + na];
-            const double* xq = xk + (u * qd + na) * XC;
+            const int j2 = u * qd + na;
+            const double t2 = Tk[j2 * nn + nd];
 #pragma unroll
-            for (int c = 0; c < XC; ++c) acc[c] += t2 * xq[c];
+            for (int c = 0; c < XC; ++c) acc[c] += t2 * xk[c * npad + j2];
           }
         }
         const double wd = dv.W[nd] * tau_e[nd], ws = dv.W[nd] * tau_s[nd];
-        const double* Qr = dv.Q + k * dv.n_a;
+        const double* Qr = dv.Q + k * n_a;
         double sc[XC];
 #pragma unroll
         for (int c = 0; c < XC; ++c) sc[c] = 0.0;
-        for (int kp = 0; kp < dv.n_a; ++kp) {
+#pragma unroll 8
+        for (int kp = 0; kp < n_a; ++kp) {
           const double qk = Qr[kp];
-          const double* xq = xs + (kp * nn + nd) * XC;
 #pragma unroll
-          for (int c = 0; c < XC; ++c) sc[c] += qk * xq[c];
+          for (int c = 0; c < XC; ++c) sc[c] += qk * xs[c * npad + kp * nn + nd];
         }
+        const double sv = src_col ? 0.5 * he * dv.W[nd] * a.src[e * n + q] : 0.0;
 #pragma unroll
         for (int c = 0; c < XC; ++c) {
-          const int col = P0 + c0 + c;
-          const double rv = col < m ? (q == dv.in_row[col] ? dv.in_val[col] : 0.0)
-                                    : (col == m && a.src ? 0.5 * he * dv.W[nd] * a.src[e * n + q] : 0.0);
-          acc[c] = rv - (acc[c] + wd * xs[q * XC + c] - ws * sc[c]);
+          const double rv = q == irow[c] ? ival[c] : (src_col && P0 + c0 + c == m ? sv : 0.0);
+          acc[c] = rv - (acc[c] + wd * xs[c * npad + q] - ws * sc[c]);
         }
       }
+      const int i = pinv[q];
 #pragma unroll
       for (int c = 0; c < XC; ++c) {
         pan[i * LDP + c0 + c] = (T)acc[c];
@@ -637,6 +785,17 @@ __device__ inline void ir_residual(const LuArgs<T>& a, T* pan, const int* perm, 
       if ((tid & 63) == 0) atomicMax(&colmax[c0 + c], v);
     }
     __syncthreads();
+  }
+}
+
+// Tt[k][j][i] = T[k][i][j]: the transport table transposed per ordinate
+__global__ void k_transpose_transport(const double* T, double* Tt, int n_a, int nn) {
+  const int64_t total = (int64_t)n_a * nn * nn;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = idx / ((int64_t)nn * nn);
+    const int rem = (int)(idx - k * nn * nn), i = rem / nn, j = rem - i * nn;
+    Tt[(k * nn + j) * nn + i] = T[idx];
   }
 }
 
@@ -760,58 +919,14 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         pending = false;
       }
       transform_blocks<T>(pan, inv, 0, 0, J / NB, wave, lane);
-      // factor rows [J, npad) of the panel with partial pivoting
-      double best = -1.0;
-      int bidx = INT_MAX;
-      for (int r = J + tid; r < npad; r += kThreads) {
-        double v = fabs((double)pan[r * LDP]);
-        if (v > best) { best = v; bidx = r; }
+      // factor rows [J, npad) of the panel with partial pivoting (the rows
+      // in registers; the candidate slots use bbuf, idle between sweeps)
+      switch ((npad + kThreads - 1) / kThreads) {
+        case 1: factor_panel<T, 1>(pan, perm, bbuf, sflag, J, npad, tid); break;
+        case 2: factor_panel<T, 2>(pan, perm, bbuf, sflag, J, npad, tid); break;
+        case 3: if constexpr (kMaxRows<MAXT> >= 3) factor_panel<T, 3>(pan, perm, bbuf, sflag, J, npad, tid); break;
+        default: if constexpr (kMaxRows<MAXT> >= 4) factor_panel<T, 4>(pan, perm, bbuf, sflag, J, npad, tid); break;
       }
-      // (unrolled: the column c is a constant in each copy of the body)
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const int col = J + c;
-        for (int off = 32; off > 0; off >>= 1) {
-          double v2 = __shfl_xor(best, off);
-          int i2 = __shfl_xor(bidx, off);
-          argmax_combine(best, bidx, v2, i2);
-        }
-        if (lane == 0) { redv[wave] = best; redi[wave] = bidx; }
-        __syncthreads();
-        double gv = redv[0];
-        int gi = redi[0];
-        for (int w = 1; w < kWaves; ++w) argmax_combine(gv, gi, redv[w], redi[w]);
-        if (gi < col || gi >= npad) { gi = col; gv = 0.0; }   // NaN column: no candidate
-        if (gi != col) {
-          if (tid < NB) {
-            T tmp = pan[col * LDP + tid];
-            pan[col * LDP + tid] = pan[gi * LDP + tid];
-            pan[gi * LDP + tid] = tmp;
-          }
-          if (tid == NB) { int tp = perm[col]; perm[col] = perm[gi]; perm[gi] = tp; }
-        }
-        if (tid == 0 && !(gv > 0.0)) sflag[0] = 1;
-        __syncthreads();
-        const T piv = pan[col * LDP + c];
-        const T rp = piv != T(0) ? T(1) / piv : T(0);
-        T pr[NB];   // pivot row right of the column
-#pragma unroll
-        for (int j = c + 1; j < NB; ++j) pr[j] = pan[col * LDP + j];
-        best = -1.0;
-        bidx = INT_MAX;
-        for (int r = col + 1 + tid; r < npad; r += kThreads) {
-          T* row = pan + r * LDP;
-          T l = row[c] * rp;
-          row[c] = l;
-#pragma unroll
-          for (int j = c + 1; j < NB; ++j) row[j] -= l * pr[j];
-          if (c + 1 < NB) {
-            double v = fabs((double)row[c + 1]);
-            if (v > best) { best = v; bidx = r; }
-          }
-        }
-      }
-      __syncthreads();
       // inverses of the unit-lower and upper diagonal blocks: lane j of wave
       // 0 computes column j of L^{-1}, lane j of wave 1 column j of U^{-1}.
       // The entries of a column above (L) or below (U) the diagonal are
@@ -884,6 +999,38 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     }
     for (int r = tid; r < npad; r += kThreads) pinv[perm[r]] = r;
     __syncthreads();
+    // The inflow columns are solved in the order of the logical row of their
+    // one nonzero (ties by column), so that the forward sweep of each panel
+    // starts at its first column's block and later panels skip more of it:
+    // slot s < m holds column corder[s] (perm_old is free after the
+    // factorization; m <= npad <= kThreads * kMaxRows).
+    int* corder = perm_old;
+    for (int t = tid; t < m; t += kThreads) corder[t] = pinv[dv.in_row[t]];
+    __syncthreads();
+    {
+      int rk[kMaxRows<MAXT>];
+#pragma unroll
+      for (int u = 0; u < kMaxRows<MAXT>; ++u) {
+        const int t = tid + u * kThreads;
+        rk[u] = -1;
+        if (t < m) {
+          const int key = corder[t];
+          int rank = 0;
+          for (int c2 = 0; c2 < m; ++c2) {
+            const int k2 = corder[c2];
+            rank += (k2 < key || (k2 == key && c2 < t)) ? 1 : 0;
+          }
+          rk[u] = rank;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kMaxRows<MAXT>; ++u)
+        if (rk[u] >= 0) corder[rk[u]] = tid + u * kThreads;
+      __syncthreads();
+    }
+    // column of slot s (the source column m and the padding keep theirs)
+    auto colof = [&](int slot) { return slot < m ? corder[slot] : slot; };
 
     // ---- right-hand side panels: X = U^{-1} L^{-1} P (-B_hat), two at a
     // time (the second in rs)
@@ -891,7 +1038,8 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     for (int P0 = 0; P0 < mpad;) {
       const bool two = P0 + NB < mpad;
       // column col < m: -B_hat (one nonzero); column m: the source (h/2) W f
-      auto rhs = [&](int r, int col) {
+      auto rhs = [&](int r, int slot) {
+        const int col = colof(slot);
         const int q = perm[r];
         if (col < m) return q == dv.in_row[col] ? (T)dv.in_val[col] : T(0);
         if (col == m && a.src && q < n) {
@@ -909,7 +1057,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
       if (tid == 0) {
         int mn = npad;
         for (int c = 0; c < (two ? 2 * NB : NB); ++c) {
-          if (P0 + c < m) mn = min(mn, pinv[dv.in_row[P0 + c]]);
+          if (P0 + c < m) mn = min(mn, pinv[dv.in_row[colof(P0 + c)]]);
           else if (P0 + c == m && a.src) mn = 0;   // dense column
         }
         sflag[1] = (mn / NB) * NB;
@@ -929,15 +1077,16 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
         __threadfence_block();
         __syncthreads();
         auto residual = [&](const double* x, unsigned long long* cm, int p0) {
-          if (a.ir_cols == 8) ir_residual<T, 8>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
-          else if (a.ir_cols == 4) ir_residual<T, 4>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
-          else ir_residual<T, 2>(a, pan, perm, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
+          if (a.ir_cols == 8) ir_residual<T, 8>(a, pan, pinv, corder, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
+          else if (a.ir_cols == 4)
+            ir_residual<T, 4>(a, pan, pinv, corder, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
+          else ir_residual<T, 2>(a, pan, pinv, corder, tau_e, tau_s, x, xs, cm, npad, p0, tid, e, he);
         };
         auto worst_of = [&](const unsigned long long* cm, int p0) {
           double w = 0.0;
           for (int c = 0; c < NB; ++c) {
             const double r = __longlong_as_double((long long)cm[c]);
-            if (p0 + c < m) w = fmax(w, r / dv.in_val[p0 + c]);
+            if (p0 + c < m) w = fmax(w, r / dv.in_val[colof(p0 + c)]);
             else if (p0 + c == m && a.src) w = fmax(w, r / fmax(__longlong_as_double((long long)src_max), 1e-300));
           }
           return w;
@@ -988,12 +1137,13 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
             int r = idx >> 4, c = idx & 15;
             if (P0 + c < m) {
               const double v = ir ? xsol[r * NB + c] : (double)pan[r * LDP + c];
-              const int64_t o = ((int64_t)e * n + r) * m + P0 + c;
+              const int col = colof(P0 + c);
+              const int64_t o = ((int64_t)e * n + r) * m + col;
               if (a.in2sol) a.in2sol[o] = v;
               if (a.b_i2s) a.b_i2s[o] = gemm::f2bf((float)v);
               if (a.f_i2s) a.f_i2s[o] = (float)v;
               if (a.h_i2s) a.h_i2s[o] = (_Float16)(float)v;
-              if (pairs_sol) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+              if (pairs_sol) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + col] = gemm::f2bf((float)v);
             }
           }
         }
@@ -1002,12 +1152,13 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
             int r = idx >> 4, c = idx & 15;
             if (P0 + c < m) {
               const double v = ir ? xsol[dv.out_row[r] * NB + c] : (double)pan[dv.out_row[r] * LDP + c];
-              const int64_t o = ((int64_t)e * m + r) * m + P0 + c;
+              const int col = colof(P0 + c);
+              const int64_t o = ((int64_t)e * m + r) * m + col;
               if (a.in2out) a.in2out[o] = v;
               if (a.b_i2o) a.b_i2o[o] = gemm::f2bf((float)v);
               if (a.f_i2o) a.f_i2o[o] = (float)v;
               if (a.h_i2o) a.h_i2o[o] = (_Float16)(float)v;
-              if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+              if (a.pairs) a.pairs[(int64_t)e * n_out + (int64_t)r * m + col] = gemm::f2bf((float)v);
             }
           }
         }
@@ -1035,12 +1186,13 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
               for (int k = 0; k < dv.n_a; ++k)
                 acc += ir ? xsol[(k * nn + r) * NB + c] : (double)pan[(k * nn + r) * LDP + c];
               const double v = acc * s;
-              const int64_t o = ((int64_t)e * nn + r) * m + P0 + c;
+              const int col = colof(P0 + c);
+              const int64_t o = ((int64_t)e * nn + r) * m + col;
               if (a.in2mean) a.in2mean[o] = v;
               if (a.b_i2m) a.b_i2m[o] = gemm::f2bf((float)v);
               if (a.f_i2m) a.f_i2m[o] = (float)v;
               if (a.h_i2m) a.h_i2m[o] = (_Float16)(float)v;
-              if (pairs_mean) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + P0 + c] = gemm::f2bf((float)v);
+              if (pairs_mean) a.pairs[(int64_t)e * n_out + (int64_t)m * m + (int64_t)r * m + col] = gemm::f2bf((float)v);
             }
           }
         }
@@ -1125,7 +1277,11 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   size_t fac_bytes = sizeof(T) * (size_t)slots * npan * npad * NB;
   size_t inv_bytes = sizeof(T) * (size_t)slots * npan * 2 * NB * NB;
   size_t x_bytes = sizeof(double) * (size_t)slots * xbuf_doubles_per_slot(npad, ir);
-  el_status st = ensure_ws(ctx, ctx->ws_local, fac_bytes + inv_bytes + x_bytes + 256);
+  // refinement: the transport table transposed per ordinate, after xbuf
+  const size_t x_off = (fac_bytes + inv_bytes + 255) / 256 * 256;
+  const size_t tt_off = (x_off + x_bytes + 255) / 256 * 256;
+  const size_t tt_bytes = ir ? sizeof(double) * (size_t)dh.n_a * dh.nn * dh.nn : 0;
+  el_status st = ensure_ws(ctx, ctx->ws_local, tt_off + tt_bytes + 256);
   if (st) return st;
   st = ensure_ws(ctx, ctx->ws_small, 8192);
   if (st) return st;
@@ -1146,7 +1302,15 @@ el_status run_local_t(el_ctx* ctx, el_ctx::DiscEntry* de, bool ir, int64_t E, co
   char* base = reinterpret_cast<char*>(ctx->ws_local.ptr);
   args.fac = reinterpret_cast<T*>(base);
   args.inv = reinterpret_cast<T*>(base + fac_bytes);
-  args.xbuf = reinterpret_cast<double*>(base + ((fac_bytes + inv_bytes + 255) / 256) * 256);
+  args.xbuf = reinterpret_cast<double*>(base + x_off);
+  args.Tt = nullptr;
+  if (ir) {
+    double* tt = reinterpret_cast<double*>(base + tt_off);
+    const int64_t total = (int64_t)dh.n_a * dh.nn * dh.nn;
+    hipLaunchKernelGGL(k_transpose_transport, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 1024)), dim3(256),
+                       0, ctx->stream, de->view.T, tt, dh.n_a, dh.nn);
+    args.Tt = tt;
+  }
   args.refine = ir ? 1 : 0;
   args.rel_resid = rel_resid;
   args.ir_steps = 3;
