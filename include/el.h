@@ -190,6 +190,19 @@ el_status el_local_solve(el_ctx* ctx, el_disc d, int precision, int64_t E,
  * Sec. 2.2.2), 0 elsewhere. */
 el_status el_trace_rhs(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_side_host, double* b);
 
+/* The same right-hand side for boundary radiance that varies along the
+ * boundary (Sec. 2.2.2, b = P_M g, the nodal interpolation of g at the LGL
+ * face nodes): g_bnd (device, FP64, read only) holds g at every boundary
+ * face node for every ordinate, [side][face][n_a][p+1] with the sides in
+ * the order W, E (n_y faces each, from bottom to top), S, N (n_x faces
+ * each, from left to right), 2 (n_x + n_y) n_a (p+1) values in all, face
+ * nodes in increasing coordinate.  b [n_trace] (device) gets g on the
+ * domain-inflow DOFs (s . n < 0) and 0 elsewhere; values at the other
+ * boundary DOFs are not read.  Synchronizes the stream; a non-finite value
+ * on an inflow DOF returns EL_ERR_NONFINITE naming the trace DOF (b is then
+ * written but not meaningful). */
+el_status el_trace_rhs_nodal(el_ctx* ctx, el_disc d, el_mesh mesh, const double* g_bnd, double* b);
+
 /* With a volume source: b[outflow DOFs of e] += src2out[e] (the f_hat_u of
  * el_local_solve, [E][m]; every outflow DOF belongs to one element). */
 el_status el_trace_add_source(el_ctx* ctx, el_disc d, el_mesh mesh, const double* src2out, double* b);

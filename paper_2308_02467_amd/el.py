@@ -91,6 +91,7 @@ _SIGS = {
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "el_trace_rhs": [ctypes.c_void_p, el_disc, el_mesh, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
+    "el_trace_rhs_nodal": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_void_p],
     "el_trace_add_source": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_void_p],
     "el_trace_matvec": [ctypes.c_void_p, el_disc, el_mesh, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_void_p],
@@ -306,6 +307,14 @@ class Context:
         nt = trace_size(d, ms)
         return self._check(lib().el_trace_rhs(self.h, d, ms, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                               _ptr(b, torch.float64, nt, "b")))
+
+    def el_trace_rhs_nodal(self, d, ms, g_bnd, b):
+        """b from boundary radiance g_bnd [2 (n_x + n_y), n_a, p + 1] (faces of
+        the sides W, E, S, N in that order, FP64 on the device)."""
+        nt = trace_size(d, ms)
+        n_bnd = 2 * (ms.n_x + ms.n_y) * d.n_a * (d.p + 1)
+        return self._check(lib().el_trace_rhs_nodal(self.h, d, ms, _ptr(g_bnd, torch.float64, n_bnd, "g_bnd"),
+                                                    _ptr(b, torch.float64, nt, "b")))
 
     def el_trace_matvec(self, d, ms, in2out, x, y):
         nt = trace_size(d, ms)
