@@ -109,13 +109,13 @@ struct LuArgs {
   const double* Tt;     // refinement: transport table transposed per ordinate [n_a][nn][nn]
 };
 
-// Entry (i, j) of the padded local matrix A (identity outside n x n).
+// Entry (i, j) of the padded local matrix A (identity outside n x n), with
+// i = k nn + ndi and j = kp nn + ndj already split into ordinate and node.
 template <typename T>
-__device__ inline T amat(const DiscDev& dv, const double* tau_e, const double* tau_s, int i, int j) {
+__device__ inline T amat(const DiscDev& dv, const double* tau_e, const double* tau_s, int i, int k, int ndi, int j,
+                         int kp, int ndj) {
   if (i >= dv.n || j >= dv.n) return i == j ? T(1) : T(0);
   const int nn = dv.nn;
-  const int k = i / nn, ndi = i - k * nn;
-  const int kp = j / nn, ndj = j - kp * nn;
   double v = 0.0;
   if (k == kp) {
     v = dv.T[((size_t)k * nn + ndi) * nn + ndj];
@@ -124,6 +124,10 @@ __device__ inline T amat(const DiscDev& dv, const double* tau_e, const double* t
   if (ndi == ndj) v -= dv.W[ndi] * tau_s[ndi] * dv.Q[k * dv.n_a + kp];
   return (T)v;
 }
+
+// floor(i / nn) as (i inv) >> 32 with inv = floor(2^32 / nn) + 1, exact for
+// 0 <= i < 2^32 / nn (i < npad)
+__device__ inline int div_nn(int i, uint64_t inv) { return (int)(((uint64_t)(uint32_t)i * inv) >> 32); }
 
 // pan[I..I+16) = Tinv * pan[I..I+16), Tinv a 16x16 block (row-major).
 // Executed by one wave.
@@ -814,6 +818,7 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
   const DiscDev& dv = a.dv;
   const int npad = a.npad, mpad = a.mpad, n = dv.n, m = dv.m, nn = dv.nn;
   const int npan = npad / NB;
+  const uint64_t nn_inv = (1ull << 32) / (uint64_t)nn + 1ull;
   T* pan = reinterpret_cast<T*>(smem);                                   // [npad][LDP]
   int* perm = reinterpret_cast<int*>(smem + sizeof(T) * npad * LDP);     // [npad]
   int* pinv = perm + npad;                                               // [npad]
@@ -884,15 +889,19 @@ __global__ void __launch_bounds__(kThreads) k_local_lu(LuArgs<T> a) {
     for (int J = 0; J < npad; J += NB) {
       if (!pending) {
         // generate the panel of A, rows in current logical order
+        // (a thread's column c = tid % 16 is the same in all its iterations)
+        const int c = tid & 15, j1 = J + c, j2 = J + NB + c;
+        const int kp1 = div_nn(j1, nn_inv), kp2 = div_nn(j2, nn_inv);
+        const int ndj1 = j1 - kp1 * nn, ndj2 = j2 - kp2 * nn;
         for (int idx = tid; idx < npad * NB; idx += kThreads) {
-          int r = idx >> 4, c = idx & 15;
-          pan[r * LDP + c] = amat<T>(dv, tau_e, tau_s, perm[r], J + c);
+          const int r = idx >> 4, i = perm[r], k = div_nn(i, nn_inv), ndi = i - k * nn;
+          pan[r * LDP + c] = amat<T>(dv, tau_e, tau_s, i, k, ndi, j1, kp1, ndj1);
         }
         const bool pair = J + NB < npad;
         if (pair) {
           for (int idx = tid; idx < npad * NB; idx += kThreads) {
-            int r = idx >> 4, c = idx & 15;
-            rs[r * NB + c] = amat<T>(dv, tau_e, tau_s, perm[r], J + NB + c);
+            const int r = idx >> 4, i = perm[r], k = div_nn(i, nn_inv), ndi = i - k * nn;
+            rs[r * NB + c] = amat<T>(dv, tau_e, tau_s, i, k, ndi, j2, kp2, ndj2);
           }
           for (int r = tid; r < npad; r += kThreads) perm_old[r] = perm[r];
           __threadfence_block();
