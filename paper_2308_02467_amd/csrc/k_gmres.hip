@@ -131,18 +131,18 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---- products -----------------------------------------------------------------
-template <typename OpT, bool IMP, int R>
+template <typename OpT, bool IMP, int R, typename XT>
 __global__ void __launch_bounds__(kMVThreads) k_bmatvec(DiscDev dv, const BMesh* __restrict__ ms, int n_mesh,
                                                          const BState* __restrict__ st, int pred,
-                                                         const double* __restrict__ x, double* __restrict__ y) {
+                                                         const XT* __restrict__ x, double* __restrict__ y) {
   extern __shared__ double sm[];
   const int mi = mesh_of_elem(ms, n_mesh, blockIdx.x);
   if (skip(st[mi], pred)) return;
   const BMesh M = ms[mi];
   const int e = (int)((int64_t)blockIdx.x - M.e0);
   const MeshDev md{M.n_x, M.n_y, M.n_vf};
-  matvec_element<OpT, IMP, R>(dv, md, e, reinterpret_cast<const OpT*>(M.op) + (size_t)e * dv.m * dv.m, x + M.d0,
-                              y + M.d0, sm);
+  matvec_element<OpT, IMP, R, XT>(dv, md, e, reinterpret_cast<const OpT*>(M.op) + (size_t)e * dv.m * dv.m,
+                                  x + M.d0, y + M.d0, sm);
 }
 
 // ---- vector kernels (one block = kChunk DOFs of one mesh) ---------------------
@@ -321,8 +321,9 @@ __global__ void __launch_bounds__(kVThreads) k_bscale(double* __restrict__ w, co
 }
 
 // FP32 basis: v = w * inv of the mesh rounded to FP32 once, stored as the
-// basis column vb and, widened, as the FP64 input vd of the next product
-__global__ void __launch_bounds__(kVThreads) k_bscale_to(const double* __restrict__ w, double* __restrict__ vd,
+// basis column vb, which is also the next product's input (widened as it is
+// gathered)
+__global__ void __launch_bounds__(kVThreads) k_bscale_to(const double* __restrict__ w,
                                                           float* __restrict__ vb, const BMesh* __restrict__ ms,
                                                           int n_mesh, const BState* __restrict__ st, int pred) {
   const Span sp = block_span(ms, n_mesh);
@@ -337,9 +338,7 @@ __global__ void __launch_bounds__(kVThreads) k_bscale_to(const double* __restric
   for (int v = 0; v < kVec; ++v) {
     const int64_t ix = base + v * kVThreads;
     if (ix < sp.lim) {
-      const float r = (float)(x[v] * s);
-      vb[ix] = r;
-      vd[ix] = (double)r;
+      vb[ix] = (float)(x[v] * s);
     }
   }
 }
@@ -540,7 +539,6 @@ struct Batch {
   double* V;         // FP64 basis [R + 1][Np] (null with the FP32 basis)
   float* Vf;         // FP32 basis [R + 1][Np] (null with the FP64 basis)
   double* W;         // FP32 basis: working vector w [Np]
-  double* vd;        // FP32 basis: the newest basis vector in FP64 [Np]
   double* tmp;       // [Np]
   double* bcat;      // [Np]
   double* xcat;      // [Np]
@@ -550,23 +548,23 @@ struct Batch {
   BMesh* ms;         // [n_mesh]
 
   // imp: y = (I - P) x (true residuals); otherwise y = P x (Arnoldi)
-  template <bool IMP>
-  void matvec_t(hipStream_t s, int pred, const double* x, double* y) const {
+  template <bool IMP, typename XT>
+  void matvec_t(hipStream_t s, int pred, const XT* x, double* y) const {
     const size_t smem = matvec_smem_bytes(m);
     with_op_type(op_dtype, [&](auto tag) {
       using T = decltype(tag);
       switch (mv_shape) {
         case 1:
-          hipLaunchKernelGGL((k_bmatvec<T, IMP, 2>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
-                             pred, x, y);
+          hipLaunchKernelGGL((k_bmatvec<T, IMP, 2, XT>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh,
+                             st, pred, x, y);
           break;
         case 2:
-          hipLaunchKernelGGL((k_bmatvec<T, IMP, 8>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
-                             pred, x, y);
+          hipLaunchKernelGGL((k_bmatvec<T, IMP, 8, XT>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh,
+                             st, pred, x, y);
           break;
         default:
-          hipLaunchKernelGGL((k_bmatvec<T, IMP, 4>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh, st,
-                             pred, x, y);
+          hipLaunchKernelGGL((k_bmatvec<T, IMP, 4, XT>), dim3((unsigned)E), dim3(kMVThreads), smem, s, dv, ms, n_mesh,
+                             st, pred, x, y);
       }
     });
   }
@@ -600,7 +598,7 @@ struct Batch {
   // v_0 = r / |r| from r in the working vector (FP64 basis: V[0])
   void start_vector(hipStream_t s) const {
     if (f32)
-      hipLaunchKernelGGL(k_bscale_to, dim3(nblk), dim3(kVThreads), 0, s, W, vd, Vf, ms, n_mesh, st, P_ACTIVE);
+      hipLaunchKernelGGL(k_bscale_to, dim3(nblk), dim3(kVThreads), 0, s, W, Vf, ms, n_mesh, st, P_ACTIVE);
     else
       hipLaunchKernelGGL(k_bscale, dim3(nblk), dim3(kVThreads), 0, s, V, ms, n_mesh, st, P_ACTIVE);
   }
@@ -608,14 +606,16 @@ struct Batch {
   void step(hipStream_t s, int j) const {
     const int cnt = j + 1;
     double* w = f32 ? W : V + (size_t)(j + 1) * Np;
-    matvec(s, P_ACTIVE, f32 ? vd : V + (size_t)j * Np, w, false);
+    // with the FP32 basis the product reads the stored (rounded) v_j
+    if (f32) matvec_t<false>(s, P_ACTIVE, Vf + (size_t)j * Np, w);
+    else matvec_t<false>(s, P_ACTIVE, V + (size_t)j * Np, w);
     dot(s, P_ACTIVE, cnt, w, 1, lay.h1);
     update(s, P_ACTIVE, cnt, lay.h1, w, 1.0, lay.sc + 2, cnt);
     dot(s, P_REORTH, cnt, w, 0, lay.h2);
     update(s, P_REORTH, cnt, lay.h2, w, 1.0, lay.sc + 3);
     hipLaunchKernelGGL(k_bgivens, dim3(n_mesh), dim3(64), 0, s, j, n_mesh, hs, lay, st, tol, max_iter);
     if (f32)
-      hipLaunchKernelGGL(k_bscale_to, dim3(nblk), dim3(kVThreads), 0, s, W, vd, Vf + (size_t)(j + 1) * Np, ms,
+      hipLaunchKernelGGL(k_bscale_to, dim3(nblk), dim3(kVThreads), 0, s, W, Vf + (size_t)(j + 1) * Np, ms,
                          n_mesh, st, P_ACTIVE);
     else
       hipLaunchKernelGGL(k_bscale, dim3(nblk), dim3(kVThreads), 0, s, w, ms, n_mesh, st, P_ACTIVE);
@@ -653,7 +653,7 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   const BLay lay = make_layout(R);
   const bool f32 = opts.basis == EL_F32;
   // tmp, b, x (+ w and v_j with the FP32 basis) in FP64, then the basis
-  const size_t v_bytes = sizeof(double) * (size_t)(f32 ? 5 : 3) * Np +
+  const size_t v_bytes = sizeof(double) * (size_t)(f32 ? 4 : 3) * Np +
                          (f32 ? sizeof(float) : sizeof(double)) * (size_t)(R + 1) * Np;
   const size_t p_bytes = sizeof(double) * (size_t)nblk * (R + 2);
   const size_t h_bytes = sizeof(double) * (size_t)n_mesh * lay.S;
@@ -681,13 +681,12 @@ el_status run_trace_solve(el_ctx* ctx, el_ctx::DiscEntry* de, int n_mesh, const 
   if (f32) {
     bt.V = nullptr;
     bt.W = bt.xcat + Np;
-    bt.vd = bt.W + Np;
-    bt.Vf = reinterpret_cast<float*>(bt.vd + Np);
+    bt.Vf = reinterpret_cast<float*>(bt.W + Np);
     bt.partials = reinterpret_cast<double*>(bt.Vf + (size_t)(R + 1) * Np);   // Np is a multiple of kChunk
   } else {
     bt.V = bt.xcat + Np;
     bt.Vf = nullptr;
-    bt.W = bt.vd = nullptr;
+    bt.W = nullptr;
     bt.partials = bt.V + (size_t)(R + 1) * Np;
   }
   bt.hs = bt.partials + (size_t)nblk * (R + 2);

@@ -185,13 +185,14 @@ __host__ __device__ inline size_t matvec_smem_bytes(int m) { return (2 * sizeof(
 
 // IMP: y = x - in2out_e x_in at the outflow DOFs of element e and y = x on
 // the domain-inflow DOFs it sees, i.e. y = (I - P) x; !IMP: y = in2out_e x_in
-// and 0 on the domain-inflow DOFs, i.e. y = P x.  x, y: the mesh's trace
-// vectors; sm: matvec_smem_bytes(m) of LDS.  Every index and x value the
-// element needs is fetched up front, one per thread, so the row loop waits
-// only on the operator stream.
-template <typename OpT, bool IMP, int R>
+// and 0 on the domain-inflow DOFs, i.e. y = P x.  x (FP64, or an FP32 vector
+// widened as it is read), y: the mesh's trace vectors; sm:
+// matvec_smem_bytes(m) of LDS.  Every index and x value the element needs is
+// fetched up front, one per thread, so the row loop waits only on the
+// operator stream.
+template <typename OpT, bool IMP, int R, typename XT = double>
 __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int e, const OpT* __restrict__ op_e,
-                                      const double* __restrict__ x, double* __restrict__ y, double* sm) {
+                                      const XT* __restrict__ x, double* __restrict__ y, double* sm) {
   const int i = e % ms.n_x, j = e / ms.n_x;
   const int m = dv.m;
   double* tin = sm;                                  // [m]
@@ -203,8 +204,8 @@ __device__ inline void matvec_element(const DiscDev& dv, const MeshDev& ms, int 
     const int dof = (F * dv.n_a + dv.in_k[t]) * dv.q + dv.in_j[t];
     const int Fo = face_of(ms, i, j, dv.out_f[t]);
     const int od = (Fo * dv.n_a + dv.out_k[t]) * dv.q + dv.out_j[t];
-    const double v = x[dof];
-    if (IMP) xo[t] = x[od];
+    const double v = (double)x[dof];
+    if (IMP) xo[t] = (double)x[od];
     odof[t] = od;
     tin[t] = v;
     if (on_domain_boundary(ms, i, j, f)) y[dof] = IMP ? v : 0.0;
