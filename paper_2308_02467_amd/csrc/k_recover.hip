@@ -117,17 +117,34 @@ __global__ void k_conserve(DiscDev dv, int64_t E, const double* __restrict__ h, 
   const T* S = i2s + (size_t)e * rows * m;
   const T* O = i2o + (size_t)e * m * m;
   TW* W = out + (size_t)e * m * m;
+  // (four partial sums per thread, so that four loads of a column are in
+  // flight at a time; rows = k nn + nd, a multiple of nn)
   for (int c = threadIdx.x; c < m; c += blockDim.x) {
     double s = 1.0;
     if (!keep) {
-      double absorb = 0.0;
-      for (int r = 0; r < rows; ++r) absorb += wa[r % nn] * op_to_double(S[(int64_t)r * m + c]);
-      absorb *= mult;
-      double sum = 0.0;
-      for (int o = 0; o < m; ++o) sum += dv.out_val[o] * op_to_double(O[(int64_t)o * m + c]);
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int r0 = 0; r0 < rows; r0 += nn) {
+        const T* Sk = S + (int64_t)r0 * m + c;
+        int nd = 0;
+        for (; nd + 4 <= nn; nd += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[u] += wa[nd + u] * op_to_double(Sk[(int64_t)(nd + u) * m]);
+        }
+        for (; nd < nn; ++nd) a[0] += wa[nd] * op_to_double(Sk[(int64_t)nd * m]);
+      }
+      const double absorb = ((a[0] + a[1]) + (a[2] + a[3])) * mult;
+      double b[4] = {0.0, 0.0, 0.0, 0.0};
+      int o = 0;
+      for (; o + 4 <= m; o += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b[u] += dv.out_val[o + u] * op_to_double(O[(int64_t)(o + u) * m + c]);
+      }
+      for (; o < m; ++o) b[0] += dv.out_val[o] * op_to_double(O[(int64_t)o * m + c]);
+      const double sum = (b[0] + b[1]) + (b[2] + b[3]);
       const double target = dv.in_val[c] - absorb;
       if (sum > 0.0 && target > 0.0) s = target / sum;
     }
+#pragma unroll 4
     for (int o = 0; o < m; ++o) W[(int64_t)o * m + c] = op_from_double<TW>(s * op_to_double(O[(int64_t)o * m + c]));
   }
 }
