@@ -541,6 +541,10 @@ __device__ inline void panel_solve2(T* pan, T* rs, T* bbuf, const T* fac, const 
   __syncthreads();
 }
 
+// rows per thread of factor_panel for at most kWaves * MAXT row tiles
+template <int MAXT>
+constexpr int kMaxRows = (kWaves * MAXT * NB + kThreads - 1) / kThreads;
+
 // Partial-pivoting factorization of the 16 columns of the LDS panel, rows
 // [J, npad) in logical order, with the rows held in registers: thread tid
 // owns the rows that sit at logical positions J + tid + kThreads k when the
@@ -558,10 +562,6 @@ __device__ inline void panel_solve2(T* pan, T* rs, T* bbuf, const T* fac, const 
 // without a nonzero candidate still picks a row (and is reported singular).
 // On return the rows are back in pan at their final logical positions and
 // perm is permuted to match.  All threads call it; it ends on a barrier.
-// rows per thread of factor_panel for at most kWaves * MAXT row tiles
-template <int MAXT>
-constexpr int kMaxRows = (kWaves * MAXT * NB + kThreads - 1) / kThreads;
-
 template <typename T, int R>
 __device__ __attribute__((noinline)) void factor_panel(T* pan_g, int* perm_g, T* cand_g, int* sflag_g, int J,
                                                        int npad, int tid) {
