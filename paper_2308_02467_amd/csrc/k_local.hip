@@ -541,6 +541,30 @@ __device__ inline void panel_solve2(T* pan, T* rs, T* bbuf, const T* fac, const 
   __syncthreads();
 }
 
+// Largest 64-bit value over the wave, on every lane: an inclusive max scan
+// within each row of 16 lanes (DPP row shifts by 1, 2, 4, 8), then the row
+// broadcasts of lanes 15 and 31, which leave the wave's maximum in lane 63.
+// A lane whose shift source lies outside its row keeps its own value.
+template <int CTRL, int ROWS>
+__device__ inline unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+  return ((unsigned long long)(uint32_t)h2 << 32) | (uint32_t)l2;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+  unsigned long long o;
+  o = dpp_u64<0x111, 0xf>(v); v = o > v ? o : v;   // row_shr:1
+  o = dpp_u64<0x112, 0xf>(v); v = o > v ? o : v;   // row_shr:2
+  o = dpp_u64<0x114, 0xf>(v); v = o > v ? o : v;   // row_shr:4
+  o = dpp_u64<0x118, 0xf>(v); v = o > v ? o : v;   // row_shr:8
+  o = dpp_u64<0x142, 0xa>(v); v = o > v ? o : v;   // row_bcast:15 into rows 1 and 3
+  o = dpp_u64<0x143, 0xc>(v); v = o > v ? o : v;   // row_bcast:31 into rows 2 and 3
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // rows per thread of factor_panel for at most kWaves * MAXT row tiles
 template <int MAXT>
 constexpr int kMaxRows = (kWaves * MAXT * NB + kThreads - 1) / kThreads;
@@ -597,12 +621,7 @@ __device__ __attribute__((noinline)) void factor_panel(T* pan_g, int* perm_g, T*
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     const int par = (c & 1) * kWaves;
-    unsigned long long wk = best;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(wk, off);
-      wk = o > wk ? o : wk;
-    }
+    const unsigned long long wk = wave_max_u64(best);
     if (wk == 0ull) {
       if ((tid & 63) == 0) ckey[par + wave] = 0ull;
     } else if (best == wk) {
