@@ -243,9 +243,19 @@ struct EpiMAE {
   // (rows ym0.., columns yn0..; pitch ypitch; tile rows below ysplit from ys,
   // the others from ys2)
   static constexpr bool kStageLds = true;
+  int ypitch, ysplit, ym0, yn0;
+  // optionally the same codes transposed, dYT[n][m] (ldT = M, a multiple of
+  // 4): a lane holds four consecutive rows of its column in consecutive
+  // registers (block_begin starts each group of 32 rows), so it packs them
+  // into one 8-byte store
+  uint16_t* dYT;
+  int64_t ldT;
+  uint64_t pack;
+  // LDS pointers are 4 bytes on the device and 8 on the host, so they come
+  // last: every member the host sets has the same offset on both sides (the
+  // host passes them null; the kernel sets them)
   const __attribute__((address_space(3))) uint16_t* ys;
   const __attribute__((address_space(3))) uint16_t* ys2;
-  int ypitch, ysplit, ym0, yn0;
   __device__ Col col(int n) const { return Col{bias[n], ymean[n], 1.f / ystd[n]}; }
   // from the LDS tile, or from HBM with 32-bit byte offsets from the
   // kernel-argument base (the host keeps B * n_out below 2^31): one address
@@ -258,7 +268,7 @@ struct EpiMAE {
     const uint32_t off = ((uint32_t)m * (uint32_t)ld + (uint32_t)n) * 2u;
     return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(y) + off);
   }
-  __device__ void block_begin() { s_abs = 0.f; s_sgn = 0.f; }
+  __device__ void block_begin() { s_abs = 0.f; s_sgn = 0.f; pack = 0; }
   __device__ void operator()(int m, int n, float acc, int, const Col& c, Pre t) {
     const uint32_t i = (uint32_t)m * (uint32_t)ld + (uint32_t)n;   // below 2^31 (host check)
     const float pred = acc + c.b;
@@ -267,7 +277,15 @@ struct EpiMAE {
     s_abs += fabsf(d);
     const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
     s_sgn += sg;
-    dY[i] = d > 0.f ? (uint16_t)0x3f80 : (d < 0.f ? (uint16_t)0xbf80 : (uint16_t)0);
+    const uint16_t code = d > 0.f ? (uint16_t)0x3f80 : (d < 0.f ? (uint16_t)0xbf80 : (uint16_t)0);
+    dY[i] = code;
+    if (dYT) {
+      pack |= (uint64_t)code << (16 * (m & 3));
+      if ((m & 3) == 3) {
+        *reinterpret_cast<uint64_t*>(dYT + (int64_t)n * ldT + (m - 3)) = pack;
+        pack = 0;
+      }
+    }
   }
   // all 64 lanes call it: lanes l and l + 32 hold the two row halves of
   // column n0 + l % 32 of the block at rows m0.  Blocks past the output
@@ -1493,8 +1511,10 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
   const uint16_t* Hlast = s.H + (size_t)(D - 1) * B * W;
   if (B * nout >= ((int64_t)1 << 31))
     return set_error(ctx, EL_ERR_ARG, "el_train_step: batch x n_out must stay below 2^31");
+  // with the transposed output-layer GEMMs (64 | B) the epilogue also
+  // writes dY transposed for dW
   EpiMAE mae{net->theta + net->b_off[D], y, net->y_mean, net->y_std, s.dY, s.colp, s.lossp, nout, 0.f, 0.f,
-             nullptr, nullptr, 0, 0, 0, 0};
+             0, 0, 0, 0, s.dYT, B, 0, nullptr, nullptr};
   st = mm<true, true>(ctx, Hlast, W, net->wbf + net->w_off[D], W, B, nout, W, 1, mae, true);
   if (st) return st;
   // output layer gradients: the bias from the epilogue's per-block column
@@ -1514,7 +1534,6 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
       hipLaunchKernelGGL(k_transpose16, dim3((unsigned)((rows / 64) * (cols / 64))), dim3(256), 0, str, src, rows,
                          cols, dst);
     };
-    tp(s.dY, B, nout, s.dYT);
     tp(Hlast, B, W, s.HT);
     tp(net->wbf + net->w_off[D], nout, W, s.WT);
     st = mm<true, true>(ctx, s.dYT, B, s.HT, B, nout, W, B, 1, EpiF32{net->grad + net->w_off[D], W, 0});
