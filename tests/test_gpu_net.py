@@ -151,7 +151,8 @@ def test_gradients_and_adam(ctx, gemm_tile, tile):
 
 @pytest.mark.parametrize("tile", [-1] + LDS_TILES)
 @pytest.mark.parametrize("n_in,width,depth,n_out,act,B", [(9, 64, 3, 128, 0, 48), (19, 128, 2, 520, 1, 200),
-                                                           (99, 256, 2, 1000, 0, 300), (99, 192, 2, 1000, 0, 300)])
+                                                           (99, 256, 2, 1000, 0, 300), (99, 192, 2, 1000, 0, 300),
+                                                           (99, 128, 2, 640, 0, 128)])
 def test_gradients_fp64_definition(ctx, gemm_tile, tile, n_in, width, depth, n_out, act, B):
     """Gradients of one training step against the plain FP64 definition
     (oracle.mlp without rounding), entry by entry within the running error
@@ -159,7 +160,10 @@ def test_gradients_fp64_definition(ctx, gemm_tile, tile, n_in, width, depth, n_o
     output, so the MAE subgradient sign(pred - target) is the same on both
     sides (the outputs are O(1)).  Tile 3 runs the output layer's MAE
     epilogue with its targets staged in LDS: one k tile (width 64), an odd
-    number of k tiles (width 192) and ragged row and column tiles."""
+    number of k tiles (width 192) and ragged row and column tiles.  With
+    batch, outputs and width multiples of 64 (the last case) the output
+    layer's dW reads the sign matrix that the MAE epilogue writes
+    transposed."""
     from paper_2308_02467_amd import el
     gemm_tile(tile)
     rng = np.random.default_rng(100 + n_out)
