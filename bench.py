@@ -97,6 +97,9 @@ def parse():
                     help="time: --pg-time-limit seconds per network (lr / 10 after 70 %%); paper: 3000 epochs each "
                          "at lr 1e-3, 1e-4 and 1e-5 (Sec. 3.1)")
     ap.add_argument("--pg-layers", default="1,2,3,4", help="network depths (layers) of the generator study")
+    ap.add_argument("--pg-precision", choices=("bf16", "fp32"), default="bf16",
+                    help="network operands of the generator study: bf16 (matrix-core path, bfloat16 targets) or "
+                         "fp32 (el_train_step_f32 / el_net_forward_f32, FP32 targets from the local solve)")
     ap.add_argument("--pg-train", type=int, default=800, help="training fields of the generator study")
     ap.add_argument("--pg-floor", type=float, default=0.0,
                     help="constant added to every generated field (0: the generator as printed)")
@@ -554,11 +557,21 @@ def paper_generator_main(args):
     x, y = learned.training_set(ctx, d, n_tr + n_te, form=el.EL_FORM_IN2MEAN, draws=(h, kap, sig), log=False)
     x_tr, y_tr = x[:n_tr].contiguous(), y[:n_tr].contiguous()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    fp32 = args.pg_precision == "fp32"
+    # operators of every field; FP32 + refinement (residual <= 1e-13): the
+    # FP64 factorization of n = 1372 does not fit one workgroup
+    n_all = n_tr + n_te if fp32 else n_te
+    all_o = torch.empty((n_all, m, m), dtype=torch.float64, device=dev)
+    all_m = torch.empty((n_all, nn, m), dtype=torch.float64, device=dev)
+    ctx.el_local_solve(d, T(h[-n_all:]), T(kap[-n_all:]), T(sig[-n_all:]), precision=el.EL_FP32_IR,
+                       in2out=all_o, in2mean=all_m)
+    ref_o, ref_m = all_o[-n_te:], all_m[-n_te:]
     H, K, S = T(h[n_tr:]), T(kap[n_tr:]), T(sig[n_tr:])
-    ref_o = torch.empty((n_te, m, m), dtype=torch.float64, device=dev)
-    ref_m = torch.empty((n_te, nn, m), dtype=torch.float64, device=dev)
-    # FP32 + refinement (residual <= 1e-13): the FP64 factorization of n = 1372 does not fit one workgroup
-    ctx.el_local_solve(d, H, K, S, precision=el.EL_FP32_IR, in2out=ref_o, in2mean=ref_m)
+    y32_tr = None
+    if fp32:
+        # FP32 targets (in2out, in2mean) of the training fields
+        y32_tr = torch.cat([all_o[:n_tr].flatten(1), all_m[:n_tr].flatten(1)], dim=1).float().contiguous()
+        del all_o, all_m
     n_in = 1 + 2 * nn
     width = (2 * n_in + 7) // 8 * 8
     n_out = m * m + nn * m
@@ -572,18 +585,25 @@ def paper_generator_main(args):
         act = el.EL_ACT_LINEAR if layers == 1 else el.EL_ACT_ELU
         net = el.Net.create(ctx, n_in, width, max(1, layers - 1), n_out, act=act, seed=0)
         net.fit_normalization(x_tr, y_tr)
+        yt = y32_tr if fp32 else y_tr
+        step = net.train_step_f32 if fp32 else None
         t0 = time.perf_counter()
         if args.pg_schedule == "paper":
-            hist = learned.train(net, x_tr, y_tr, 0, batch=50, schedule=[(3000, 1e-3), (3000, 1e-4), (3000, 1e-5)],
-                                 log=True, log_every=500)
+            hist = learned.train(net, x_tr, yt, 0, batch=50, schedule=[(3000, 1e-3), (3000, 1e-4), (3000, 1e-5)],
+                                 log=True, log_every=500, step=step)
         else:
-            hist = learned.train(net, x_tr, y_tr, 100000, batch=50, lr=1e-3, time_limit=args.pg_time_limit,
-                                 decay_at=0.7, log=False)
+            hist = learned.train(net, x_tr, yt, 100000, batch=50, lr=1e-3, time_limit=args.pg_time_limit,
+                                 decay_at=0.7, log=False, step=step)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
-        po = torch.empty((n_te, m, m), dtype=torch.float32, device=dev)
-        pm = torch.empty((n_te, nn, m), dtype=torch.float32, device=dev)
-        net.infer(d, H, K, S, in2out=po, in2mean=pm, fallback=False)
+        if fp32:
+            yo = torch.empty((n_te, n_out), dtype=torch.float32, device=dev)
+            net.forward_f32(x[n_tr:].contiguous(), yo, denormalize=True)
+            po, pm = yo[:, :m * m].reshape(n_te, m, m), yo[:, m * m:].reshape(n_te, nn, m)
+        else:
+            po = torch.empty((n_te, m, m), dtype=torch.float32, device=dev)
+            pm = torch.empty((n_te, nn, m), dtype=torch.float32, device=dev)
+            net.infer(d, H, K, S, in2out=po, in2mean=pm, fallback=False)
         torch.cuda.synchronize()
         eo = ((po.double() - ref_o).flatten(1).norm(dim=1) / ref_o.flatten(1).norm(dim=1)).cpu().numpy()
         em = ((pm.double() - ref_m).flatten(1).norm(dim=1) / ref_m.flatten(1).norm(dim=1)).cpu().numpy()
@@ -600,6 +620,7 @@ def paper_generator_main(args):
     return {"study": "element training with the paper's coefficient generator", "p": p, "n_a": n_a,
             "angular": "p0", "g": 0.8, "albedo": 1.0, "train": n_tr, "test": n_te, "batch": 50,
             "a_sigma": 10.0, "c_sm": 2.0, "floor": args.pg_floor, "schedule": args.pg_schedule,
+            "precision": args.pg_precision,
             "bf16_target_rounding_floor": floor, "networks": rows}
 
 

@@ -393,6 +393,25 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
  * [B][n_in] (float32); for testing the forward pass. */
 el_status el_net_forward(el_ctx* ctx, const el_net* net, int64_t B, const float* x, float* y_norm);
 
+/* FP32 network path (Sec. 3.1 training, measured against the bfloat16
+ * operands above): the same network, MAE loss and Adam step as
+ * el_train_step / el_net_forward, with every product taking FP32 operands
+ * (the FP32 master weights theta directly, FP32 features, hidden
+ * activations, sign matrix and backpropagated gradients) and FP32
+ * accumulation, and FP32 targets y [B][n_out] (same layout as the bfloat16
+ * targets).  It shares the network state (theta, Adam moments, step count,
+ * normalization) with the bfloat16 path and refreshes the bfloat16 weight
+ * copy in its Adam step, so the two can be mixed.  A measuring path, not a
+ * fast one: plain LDS-tiled FP32 products on the vector units.
+ * el_net_forward_f32: y [B][n_out] float32 = the normalized outputs
+ * (denormalize = 0) or the de-normalized operators (output sd + mean;
+ * denormalize = 1).  Scratch: a per-network FP32 workspace grown on demand.
+ * Errors: EL_ERR_ARG for null pointers, B < 0 (forward) or B <= 0 (step),
+ * a negative or NaN lr, or a product beyond the launch limits. */
+el_status el_train_step_f32(el_ctx* ctx, el_net* net, int64_t B, const float* x, const float* y, float lr,
+                            float* loss);
+el_status el_net_forward_f32(el_ctx* ctx, const el_net* net, int64_t B, const float* x, float* y, int denormalize);
+
 /* Learned operators for E elements (inference): in2out [E][m][m] and
  * in2vol = in2sol [E][n][m] (network in the in2sol form) or in2mean
  * [E][nn][m] (in2mean form; the form follows from the network's n_out),

@@ -37,6 +37,7 @@ struct el_net {
   bool fitted = false;
   int device = 0;
   el::Workspace scratch;
+  el::Workspace scratch32;         // FP32 network path (el_train_step_f32, el_net_forward_f32)
 };
 
 namespace el {
@@ -915,7 +916,7 @@ el_status colsum(el_ctx* ctx, const float* X, int64_t B, int64_t N, int64_t rows
   return hip_check(ctx, hipGetLastError(), "launch k_colsum");
 }
 
-// dZ = (sum_s P[s]) * act'(Z); writes FP32 and bfloat16
+// dZ = (sum_s P[s]) * act'(Z); writes FP32 and (dZ16 not null) bfloat16
 __global__ void k_reduce_dact(const float* __restrict__ P, int S, int64_t count, const float* __restrict__ Z, int act,
                               float* __restrict__ dZ, uint16_t* __restrict__ dZ16) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -924,7 +925,7 @@ __global__ void k_reduce_dact(const float* __restrict__ P, int S, int64_t count,
   for (int s = 0; s < S; ++s) acc += P[s * count + i];
   float g = acc * act_df(act, Z[i]);
   dZ[i] = g;
-  dZ16[i] = f2bf(g);
+  if (dZ16) dZ16[i] = f2bf(g);
 }
 
 __global__ void k_reduce_sum(const float* __restrict__ P, int S, int64_t count, float* __restrict__ out) {
@@ -1242,6 +1243,207 @@ el_status forward_hidden(el_ctx* ctx, el_net* net, int64_t B, const Scratch& s, 
   return EL_OK;
 }
 
+// ---- FP32 network path ----------------------------------------------------------
+// The same network, loss and optimizer with FP32 operands everywhere: the
+// FP32 master weights feed the products directly, the features, hidden
+// activations, sign matrix and backpropagated gradients stay FP32, and the
+// targets are FP32.  For measuring what the bfloat16 operands of the
+// matrix-core path cost in accuracy (Sec. 3.1 training); not a hot path.
+
+// C[z] = sum over k in chunk z of A(i, k) B(k, j), with A(i, k) = A[i a_i +
+// k a_k] and B(k, j) = B[k b_k + j b_j] (any transposition through the
+// strides), C[z][i][j] at C + z zstride + i ldc + j.  64 x 64 block tiles of
+// 256 threads with 4 x 4 outputs each, k tiles of 16 through LDS, FMAs in k
+// order within the chunk.
+__global__ void __launch_bounds__(256) k_sgemm(const float* __restrict__ A, int64_t a_i, int64_t a_k,
+                                               const float* __restrict__ Bm, int64_t b_k, int64_t b_j,
+                                               float* __restrict__ C, int64_t ldc, int64_t zstride, int64_t M,
+                                               int64_t N, int64_t K, int64_t kchunk) {
+  __shared__ float As[16][68];
+  __shared__ float Bs[16][68];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int ti = tid >> 4, tj = tid & 15;
+  float acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.f;
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + 256 * u;   // 0 .. 1023: 64 rows x 16 k
+      // consecutive threads along the operand's contiguous dimension
+      int ii, kk;
+      if (a_k == 1) { kk = idx & 15; ii = idx >> 4; } else { ii = idx & 63; kk = idx >> 6; }
+      int64_t gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < M && gk < ke) ? A[gi * a_i + gk * a_k] : 0.f;
+      int jj;
+      if (b_j == 1) { jj = idx & 63; kk = idx >> 6; } else { kk = idx & 15; jj = idx >> 4; }
+      const int64_t gj = j0 + jj;
+      gk = k0 + kk;
+      Bs[kk][jj] = (gj < N && gk < ke) ? Bm[gk * b_k + gj * b_j] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const float4 a = *reinterpret_cast<const float4*>(&As[kk][ti * 4]);
+      const float4 b = *reinterpret_cast<const float4*>(&Bs[kk][tj * 4]);
+      const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(av[r], bv[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+  float* Cz = C + (int64_t)blockIdx.z * zstride;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = i0 + ti * 4 + r;
+    if (i >= M) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t j = j0 + tj * 4 + c;
+      if (j < N) Cz[i * ldc + j] = acc[r][c];
+    }
+  }
+}
+
+// raw inputs x [B][n_in] -> z-scored FP32 features X0 [B][k0] (zero padded)
+__global__ void k_features_f32(const float* __restrict__ x, int64_t B, int n_in, int k0,
+                               const float* __restrict__ mean, const float* __restrict__ stdv,
+                               float* __restrict__ X0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * k0) return;
+  const int64_t b = i / k0;
+  const int f = (int)(i - b * k0);
+  float out = 0.f;
+  if (f < n_in) {
+    const double h = (double)x[b * n_in];
+    const double v = f == 0 ? 0.0 : (double)x[b * n_in + f];
+    out = (feature_value(f, h, v) - mean[f]) / stdv[f];
+  }
+  X0[i] = out;
+}
+
+// hidden layer: Z = P + b (in place), H = act(Z)
+__global__ void k_bias_act_f32(float* __restrict__ Z, const float* __restrict__ bias, int64_t count, int64_t N,
+                               int act, float* __restrict__ H) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float z = Z[i] + bias[i % N];
+  Z[i] = z;
+  H[i] = act_f(act, z);
+}
+
+// output layer: y = P + b (normalized) or (P + b) sd + mean (operators)
+__global__ void k_out_f32(const float* __restrict__ P, const float* __restrict__ bias, const float* __restrict__ ymean,
+                          const float* __restrict__ ystd, int64_t count, int64_t N, int denorm, float* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t n = i % N;
+  const float pred = P[i] + bias[n];
+  Y[i] = denorm ? pred * ystd[n] + ymean[n] : pred;
+}
+
+// MAE against FP32 targets: d = (P + b) - (y - mean) / sd; P <- sign(d),
+// absd = |d|
+__global__ void k_mae_f32(float* __restrict__ P, const float* __restrict__ bias, const float* __restrict__ y,
+                          const float* __restrict__ ymean, const float* __restrict__ ystd, int64_t count, int64_t N,
+                          float* __restrict__ absd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t n = i % N;
+  const float pred = P[i] + bias[n];
+  const float tgt = (y[i] - ymean[n]) * (1.f / ystd[n]);
+  const float d = pred - tgt;
+  absd[i] = fabsf(d);
+  P[i] = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+}
+
+struct Scratch32 {
+  float* X0;     // [B][k0]
+  float* Z;      // [depth][B][width]
+  float* H;      // [depth][B][width]
+  float* P;      // [B][n_out]: output-layer product, then the sign matrix
+  float* absd;   // [B][n_out] (training)
+  float* dZ;     // [B][width] (training)
+  float* part;   // split-K partials (training)
+  float* cst;    // column-sum chunks (training)
+  float* lossp;  // [kLossChunks] (training)
+  float* loss;   // [1]
+};
+
+constexpr int64_t kSgemmChunk = 2048;   // k per split of a long FP32 product
+
+inline int64_t sgemm_splits(int64_t K) { return std::max<int64_t>(1, (K + kSgemmChunk - 1) / kSgemmChunk); }
+
+el_status get_scratch32(el_ctx* ctx, el_net* net, int64_t B, bool train, Scratch32& s) {
+  const int64_t W = net->desc.width, D = net->desc.depth, nout = net->desc.n_out;
+  const int64_t chunks = (B + kColsumRows - 1) / kColsumRows;
+  size_t need = 0;
+  auto add = [&](size_t b) { size_t r = need; need += (b + 255) / 256 * 256; return r; };
+  const size_t oX0 = add((size_t)B * net->k0 * 4), oZ = add((size_t)D * B * W * 4), oH = add((size_t)D * B * W * 4);
+  const size_t oP = add((size_t)B * nout * 4);
+  const size_t oabs = train ? add((size_t)B * nout * 4) : 0, odZ = train ? add((size_t)B * W * 4) : 0;
+  const size_t opart = train ? add((size_t)sgemm_splits(nout) * B * W * 4) : 0;
+  const size_t ocst = train && chunks > 1 ? add((size_t)chunks * std::max<int64_t>(nout, W) * 4) : 0;
+  const size_t olossp = train ? add((size_t)kLossChunks * 4) : 0;
+  const size_t oloss = add(256);
+  if (net->scratch32.bytes < need) {
+    if (net->scratch32.ptr) {
+      hipStreamSynchronize(ctx->stream);
+      hipFree(net->scratch32.ptr);
+      net->scratch32.ptr = nullptr;
+      net->scratch32.bytes = 0;
+    }
+    el_status st = hip_check(ctx, hipMalloc(&net->scratch32.ptr, need), "hipMalloc(FP32 network scratch)");
+    if (st) return st;
+    net->scratch32.bytes = need;
+  }
+  char* b = reinterpret_cast<char*>(net->scratch32.ptr);
+  auto f = [&](size_t o, bool on) { return on ? reinterpret_cast<float*>(b + o) : nullptr; };
+  s.X0 = f(oX0, true); s.Z = f(oZ, true); s.H = f(oH, true); s.P = f(oP, true);
+  s.absd = f(oabs, train); s.dZ = f(odZ, train); s.part = f(opart, train);
+  s.cst = f(ocst, train && chunks > 1); s.lossp = f(olossp, train); s.loss = f(oloss, true);
+  return EL_OK;
+}
+
+// C = A B with the strides of k_sgemm; splits > 1: partials C[z] at zstride
+el_status sgemm(el_ctx* ctx, const float* A, int64_t a_i, int64_t a_k, const float* Bm, int64_t b_k, int64_t b_j,
+                float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t splits, int64_t zstride) {
+  const int64_t mt = (M + 63) / 64, nt = (N + 63) / 64;
+  const int64_t kchunk = (K + splits - 1) / splits;
+  if (mt > 65535 || splits > 65535 || nt > INT32_MAX)
+    return set_error(ctx, EL_ERR_ARG, "FP32 network product: shape too large");
+  hipLaunchKernelGGL(k_sgemm, dim3((unsigned)nt, (unsigned)mt, (unsigned)splits), dim3(256), 0, ctx->stream, A, a_i,
+                     a_k, Bm, b_k, b_j, C, ldc, zstride, M, N, K, kchunk);
+  return hip_check(ctx, hipGetLastError(), "launch k_sgemm");
+}
+
+// features and hidden layers (Z and H kept), then the output-layer product
+// P = H[depth-1] W_out^T (bias not yet added)
+el_status forward32(el_ctx* ctx, el_net* net, int64_t B, const float* x, const Scratch32& s) {
+  hipStream_t str = ctx->stream;
+  const int64_t W = net->desc.width, k0 = net->k0;
+  const int D = net->desc.depth;
+  hipLaunchKernelGGL(k_features_f32, dim3(nblk(B * k0)), dim3(256), 0, str, x, B, net->desc.n_in, (int)k0,
+                     net->feat_mean, net->feat_std, s.X0);
+  for (int l = 0; l < D; ++l) {
+    const int64_t in = net->in_dim[l];
+    const float* X = l == 0 ? s.X0 : s.H + (size_t)(l - 1) * B * W;
+    float* Z = s.Z + (size_t)l * B * W;
+    el_status st = sgemm(ctx, X, in, 1, net->theta + net->w_off[l], 1, in, Z, W, B, W, in, 1, 0);
+    if (st) return st;
+    hipLaunchKernelGGL(k_bias_act_f32, dim3(nblk(B * W)), dim3(256), 0, str, Z, net->theta + net->b_off[l], B * W, W,
+                       net->desc.act, s.H + (size_t)l * B * W);
+  }
+  return sgemm(ctx, s.H + (size_t)(D - 1) * B * W, W, 1, net->theta + net->w_off[D], 1, W, s.P, net->desc.n_out, B,
+               net->desc.n_out, W, 1, 0);
+}
+
 }  // namespace
 
 // ---- allocation-free inference: the static scratch array ----------------------
@@ -1338,6 +1540,7 @@ el_status el_net_destroy(el_net* net) {
   hipDeviceSynchronize();
   hipFree(net->theta);
   hipFree(net->scratch.ptr);
+  hipFree(net->scratch32.ptr);
   delete net;
   return EL_OK;
 }
@@ -1583,6 +1786,83 @@ el_status el_train_step(el_ctx* ctx, el_net* net, int64_t B, const float* x, con
                      net->adam_v, net->wbf, net->n_params, lr, gscale, bc1, bc2);
   if (loss) hipLaunchKernelGGL(k_loss_out, dim3(1), dim3(64), 0, str, s.loss, gscale, loss);
   return hip_check(ctx, hipGetLastError(), "el_train_step");
+}
+
+el_status el_net_forward_f32(el_ctx* ctx, const el_net* cnet, int64_t B, const float* x, float* y, int denormalize) {
+  if (!ctx || !cnet) return EL_ERR_ARG;
+  if (B == 0) return EL_OK;
+  if (B < 0 || !x || !y) return set_error(ctx, EL_ERR_ARG, "el_net_forward_f32: bad argument");
+  el_net* net = const_cast<el_net*>(cnet);
+  hipSetDevice(ctx->device);
+  Scratch32 s;
+  el_status st = get_scratch32(ctx, net, B, false, s);
+  if (st) return st;
+  st = forward32(ctx, net, B, x, s);
+  if (st) return st;
+  const int64_t nout = net->desc.n_out;
+  const int D = net->desc.depth;
+  hipLaunchKernelGGL(k_out_f32, dim3(nblk(B * nout)), dim3(256), 0, ctx->stream, s.P, net->theta + net->b_off[D],
+                     net->y_mean, net->y_std, B * nout, nout, denormalize ? 1 : 0, y);
+  return hip_check(ctx, hipGetLastError(), "el_net_forward_f32");
+}
+
+el_status el_train_step_f32(el_ctx* ctx, el_net* net, int64_t B, const float* x, const float* y, float lr,
+                            float* loss) {
+  if (!ctx || !net || B <= 0 || !x || !y) return set_error(ctx, EL_ERR_ARG, "el_train_step_f32: bad argument");
+  if (!(lr >= 0.f)) return set_error(ctx, EL_ERR_ARG, "el_train_step_f32: lr must be >= 0");
+  hipSetDevice(ctx->device);
+  Scratch32 s;
+  el_status st = get_scratch32(ctx, net, B, true, s);
+  if (st) return st;
+  hipStream_t str = ctx->stream;
+  const int D = net->desc.depth;
+  const int64_t W = net->desc.width, nout = net->desc.n_out;
+  st = forward32(ctx, net, B, x, s);
+  if (st) return st;
+  // output layer: signs of the MAE residuals in P, |residual| in absd
+  hipLaunchKernelGGL(k_mae_f32, dim3(nblk(B * nout)), dim3(256), 0, str, s.P, net->theta + net->b_off[D], y,
+                     net->y_mean, net->y_std, B * nout, nout, s.absd);
+  st = colsum(ctx, s.P, B, nout, kColsumRows, s.cst, net->grad + net->b_off[D]);
+  if (st) return st;
+  {
+    const int64_t n = B * nout, chunk = (n + kLossChunks - 1) / kLossChunks;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(kLossChunks), dim3(256), 0, str, s.absd, n, chunk, s.lossp);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, str, s.lossp, (int64_t)kLossChunks,
+                       (int64_t)kLossChunks, s.loss);
+  }
+  const float* Hlast = s.H + (size_t)(D - 1) * B * W;
+  // dW_out = dY^T H [n_out][W]; dX = dY W_out [B][W] (split over n_out)
+  st = sgemm(ctx, s.P, 1, nout, Hlast, W, 1, net->grad + net->w_off[D], W, nout, W, B, 1, 0);
+  if (st) return st;
+  const int64_t S = sgemm_splits(nout);
+  st = sgemm(ctx, s.P, nout, 1, net->theta + net->w_off[D], W, 1, s.part, W, B, W, nout, S, B * W);
+  if (st) return st;
+  hipLaunchKernelGGL(k_reduce_dact, dim3(nblk(B * W)), dim3(256), 0, str, s.part, (int)S, B * W,
+                     s.Z + (size_t)(D - 1) * B * W, net->desc.act, s.dZ, nullptr);
+  for (int l = D - 1; l >= 0; --l) {
+    const int64_t in = net->in_dim[l];
+    const float* X = l == 0 ? s.X0 : s.H + (size_t)(l - 1) * B * W;
+    st = colsum(ctx, s.dZ, B, W, kColsumRows, s.cst, net->grad + net->b_off[l]);
+    if (st) return st;
+    // dW_l = dZ^T X [W][in]
+    st = sgemm(ctx, s.dZ, 1, W, X, in, 1, net->grad + net->w_off[l], in, W, in, B, 1, 0);
+    if (st) return st;
+    if (l > 0) {
+      // dX = dZ W_l [B][in], then dZ of the layer below
+      st = sgemm(ctx, s.dZ, W, 1, net->theta + net->w_off[l], in, 1, s.part, in, B, in, W, 1, 0);
+      if (st) return st;
+      hipLaunchKernelGGL(k_reduce_dact, dim3(nblk(B * W)), dim3(256), 0, str, s.part, 1, B * W,
+                         s.Z + (size_t)(l - 1) * B * W, net->desc.act, s.dZ, nullptr);
+    }
+  }
+  net->step += 1;
+  const double t = (double)net->step;
+  const float bc1 = (float)(1.0 - std::pow(0.9, t)), bc2 = (float)(1.0 - std::pow(0.999, t));
+  const float gscale = (float)(1.0 / ((double)B * (double)nout));
+  hipLaunchKernelGGL(k_adam, dim3(nblk(net->n_params)), dim3(256), 0, str, net->theta, net->grad, net->adam_m,
+                     net->adam_v, net->wbf, net->n_params, lr, gscale, bc1, bc2);
+  if (loss) hipLaunchKernelGGL(k_loss_out, dim3(1), dim3(64), 0, str, s.loss, gscale, loss);
+  return hip_check(ctx, hipGetLastError(), "el_train_step_f32");
 }
 
 el_status el_infer(el_ctx* ctx, const el_net* cnet, el_disc d, int64_t E, const double* h, const double* kappa,

@@ -126,6 +126,10 @@ _SIGS = {
     "el_train_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_float, ctypes.c_void_p],
     "el_net_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+    "el_train_step_f32": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_float, ctypes.c_void_p],
+    "el_net_forward_f32": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_int],
     "el_infer": [ctypes.c_void_p, ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                  ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
@@ -466,6 +470,18 @@ class Net:
     def forward(self, x, y_norm):
         self.ctx._check(lib().el_net_forward(self.ctx.h, self.h, x.shape[0], _ptr(x, torch.float32, name="x"),
                                              _ptr(y_norm, torch.float32, name="y_norm")))
+
+    def train_step_f32(self, x, y, lr, loss=None):
+        """el_train_step_f32: FP32 operands throughout, float32 targets y."""
+        B = x.shape[0]
+        self.ctx._check(lib().el_train_step_f32(self.ctx.h, self.h, B, _ptr(x, torch.float32, name="x"),
+                                                _ptr(y, torch.float32, name="y"), ctypes.c_float(lr),
+                                                _ptr(loss, torch.float32, 1, "loss")))
+
+    def forward_f32(self, x, y, denormalize=False):
+        """el_net_forward_f32: normalized outputs, or the operators with denormalize."""
+        self.ctx._check(lib().el_net_forward_f32(self.ctx.h, self.h, x.shape[0], _ptr(x, torch.float32, name="x"),
+                                                 _ptr(y, torch.float32, name="y"), int(bool(denormalize))))
 
     def infer(self, d, h, kappa, sigma, in2out=None, in2sol=None, in_range=None, fallback=True,
               precision=EL_FP64, in2mean=None):

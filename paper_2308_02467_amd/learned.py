@@ -43,13 +43,15 @@ def training_set(ctx, d, N, seed=1234, chunk=8192, log=True, form=el.EL_FORM_IN2
 
 
 def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=None, decay_at=0.0,
-          schedule=None, log_every=1):
+          schedule=None, log_every=1, step=None):
     """Adam on the MAE loss; returns the per-epoch mean loss (normalized units).
     decay_at in (0, 1): lr is divided by 10 after that fraction of the epochs
     (or of the time limit), as in the paper's stepwise schedule (Sec. 3.1).
     schedule: a list of (epochs, lr) segments run one after the other (it
     replaces epochs, lr and decay_at), e.g. the paper's 3000 epochs each at
-    1e-3, 1e-4 and 1e-5."""
+    1e-3, 1e-4 and 1e-5.  step: the training step to call (default
+    net.train_step, bfloat16 targets; net.train_step_f32 takes float32
+    targets)."""
     N = x.shape[0]
     nb = N // batch
     rng = np.random.default_rng(seed)
@@ -68,7 +70,7 @@ def train(net, x, y, epochs, batch=4096, lr=1e-3, seed=0, log=True, time_limit=N
         lr_ep = lrs[ep] if lrs is not None else (lr * 0.1 if late else lr)
         for b in rng.permutation(nb):
             b0 = int(b) * batch
-            net.train_step(x[b0:b0 + batch], y[b0:b0 + batch], lr_ep, loss)
+            (step or net.train_step)(x[b0:b0 + batch], y[b0:b0 + batch], lr_ep, loss)
             acc += loss
         hist.append(acc.item() / nb)
         if log and ((ep + 1) % log_every == 0 or ep + 1 == epochs):

@@ -19,6 +19,11 @@ outputs), the same reasoning through dX = dY W, dZ = dX f'(z) and
 dW = dZ^T X.  They are worst-case bounds: a kernel that follows the
 definition stays inside them, a wrong index, a dropped term or a lost split
 does not.
+
+Every function takes the operand unit roundoff u (default U): u = 0 gives the
+bounds of the FP32 network path, whose operands are never rounded below FP32
+(features, weights, activations and gradients in FP32; the FP32 roundings of
+the arithmetic keep their U32 terms).
 """
 import numpy as np
 
@@ -34,7 +39,7 @@ def gam(k):
     return k * U32 / (1.0 - k * U32)
 
 
-def feature_bound(x, fm, fs, k0):
+def feature_bound(x, fm, fs, k0, u=U):
     """|X0_kernel - X0_exact| for raw inputs x [B, n_in]: the feature is
     rounded to FP32, z-scored in FP32 and rounded to bfloat16."""
     x = np.asarray(x, dtype=np.float64)
@@ -46,11 +51,11 @@ def feature_bound(x, fm, fs, k0):
     e_f = U32 * np.abs(f)
     e_z = (e_f + 2 * U32 * np.abs(f - fm[None, :])) / fs[None, :] + 2 * U32 * np.abs(z)
     e = np.zeros((B, k0))
-    e[:, :n_in] = e_z + U * (np.abs(z) + e_z)
+    e[:, :n_in] = e_z + u * (np.abs(z) + e_z)
     return e
 
 
-def forward_bounds(mlp, X0, e0):
+def forward_bounds(mlp, X0, e0, u=U):
     """Exact forward quantities and bounds: returns (out, Xs, Zs, e_out,
     e_xs, e_zs) with e_xs[l] bounding the kernel's layer-l input and
     e_zs[l] its pre-activation."""
@@ -63,14 +68,14 @@ def forward_bounds(mlp, X0, e0):
         A = np.abs(mlp.Ws[l]).T
         X = np.abs(Xs[l])
         K = mlp.Ws[l].shape[1]
-        e_p = (e_x * (1 + U) + U * X) @ A + gam(K) * (((X + e_x) * (1 + U)) @ A)
+        e_p = (e_x * (1 + u) + u * X) @ A + gam(K) * (((X + e_x) * (1 + u)) @ A)
         Z = Zs[l] if l < D else out
         e_z = e_p + U32 * (np.abs(Z) + e_p)
         e_zs.append(e_z)
         if l < D:
             fz = np.abs(act(mlp.act, Zs[l]))
             e_a = L * e_z + 4 * U32 * (fz + np.abs(Zs[l]) + L * e_z)
-            e_x = e_a + U * (np.abs(Xs[l + 1]) + e_a)
+            e_x = e_a + u * (np.abs(Xs[l + 1]) + e_a)
             e_xs.append(e_x)
     return out, Xs, Zs, e_zs[-1], e_xs, e_zs
 
@@ -81,7 +86,7 @@ def denorm_bound(out, e_out, ys, ym):
     return ys[None, :] * e_out + 3 * U32 * (np.abs(out) * ys[None, :] + np.abs(y))
 
 
-def grad_bounds(mlp, Xs, Zs, e_xs, e_zs, dY, dX_last=None):
+def grad_bounds(mlp, Xs, Zs, e_xs, e_zs, dY, dX_last=None, u=U):
     """Exact gradients in loss units (sum over the batch of dY-weighted
     products, dY = sign(d) in {-1, 0, 1}) and their bounds, per layer:
     returns (gW, gb, eW, eb).  dX_last: the exact dY W_D when the caller has
@@ -99,7 +104,7 @@ def grad_bounds(mlp, Xs, Zs, e_xs, e_zs, dY, dX_last=None):
     WD = np.abs(mlp.Ws[D])
     dX = dY @ mlp.Ws[D] if dX_last is None else dX_last
     n_out = mlp.Ws[D].shape[0]
-    e_dX = aY @ (U * WD) + gam(n_out) * (aY @ ((1 + U) * WD))
+    e_dX = aY @ (u * WD) + gam(n_out) * (aY @ ((1 + u) * WD))
     for l in range(D - 1, -1, -1):
         Z = Zs[l]
         df = dact(mlp.act, Z)
@@ -108,7 +113,7 @@ def grad_bounds(mlp, Xs, Zs, e_xs, e_zs, dY, dX_last=None):
         e_dZ = e_dX * np.abs(df) + adX * L2 * e_zs[l] + 4 * U32 * adX * (1 + np.abs(Z)) + U32 * np.abs(dZ)
         gb[l] = dZ.sum(axis=0)
         eb[l] = e_dZ.sum(axis=0) + gam(B) * np.abs(dZ).sum(axis=0)
-        e_dZr = e_dZ + U * (np.abs(dZ) + e_dZ)
+        e_dZr = e_dZ + u * (np.abs(dZ) + e_dZ)
         X = np.abs(Xs[l])
         ex = e_xs[l]
         gW[l] = dZ.T @ Xs[l]
@@ -117,7 +122,7 @@ def grad_bounds(mlp, Xs, Zs, e_xs, e_zs, dY, dX_last=None):
             Wl = np.abs(mlp.Ws[l])
             K = mlp.Ws[l].shape[0]
             dX = dZ @ mlp.Ws[l]
-            e_dX = e_dZr @ ((1 + U) * Wl) + np.abs(dZ) @ (U * Wl) + gam(K) * ((np.abs(dZ) + e_dZr) @ ((1 + U) * Wl))
+            e_dX = e_dZr @ ((1 + u) * Wl) + np.abs(dZ) @ (u * Wl) + gam(K) * ((np.abs(dZ) + e_dZr) @ ((1 + u) * Wl))
     return gW, gb, eW, eb
 
 

@@ -175,3 +175,31 @@ def test_bf16_emulation_inside_fp64_definition_bounds(kind):
     for l in range(depth + 1):
         assert np.all(np.abs(gWb[l] * count - gW[l]) <= eW[l]), l
         assert np.all(np.abs(gbb[l] * count - gb[l]) <= eb[l] + 1e-12 * (np.abs(gb[l]) + B)), l
+
+
+@pytest.mark.parametrize("kind", ["gelu", "elu"])
+def test_fp32_emulation_inside_fp32_path_bounds(kind):
+    """The bounds with operand unit roundoff u = 0 (the FP32 network path)
+    hold for a float32 emulation of the network, and are tight enough that
+    the bfloat16 emulation falls outside them: a path that still rounded its
+    operands to bfloat16 would fail the FP32 GPU tests."""
+    import _netbound as nb
+    rng = np.random.default_rng(11)
+    n_in, width, depth, n_out, B = 11, 48, 3, 40, 30
+    net = _rand_mlp(rng, 16, width, depth, n_out, kind)
+    net.Ws[0][:, n_in:] = 0.0
+    h = rng.uniform(0.005, 0.1, (B, 1))
+    x = np.concatenate([h, rng.uniform(0.01, 3, (B, 5)), rng.uniform(0.05, 30, (B, 5))], axis=1)
+    fm, fs = rng.uniform(-2, 0, n_in), rng.uniform(0.5, 2, n_in)
+    X0 = features(x, fm, fs, 16)
+    e0 = nb.feature_bound(x, fm, fs, 16, u=0.0)
+    out, Xs, Zs, e_out, e_xs, e_zs = nb.forward_bounds(net, X0, e0, u=0.0)
+    X = X0.astype(np.float32)
+    D = len(net.Ws) - 1
+    for l in range(D):
+        Z = X @ net.Ws[l].astype(np.float32).T + net.bs[l].astype(np.float32)
+        X = act(kind, Z.astype(np.float64)).astype(np.float32)
+    o32 = X @ net.Ws[D].astype(np.float32).T + net.bs[D].astype(np.float32)
+    assert np.all(np.abs(o32 - out) <= e_out)
+    ob, _ = net.forward(X0, bf16=True)
+    assert np.any(np.abs(ob - out) > e_out)
