@@ -893,6 +893,17 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, i2m_pl
     mv_bytes = E * m * (m * esz + 3 * 8)        # operator + gathered inflow + outflow read/write
     mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
     mv_kernel = matvec_kernel(el, args.op_dtype, m)
+    # the chip's streaming-read rate over the same operator bytes (a read of
+    # the in2out buffer and nothing else), beside the product's achieved rate
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    ctx.el_stream_read(lo, sink)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.el_stream_read(lo, sink)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sr_ms = e0.elapsed_time(e1) / reps
+    sr_gbs = lo.numel() * lo.element_size() / (sr_ms * 1e-3) / 1e9
 
     study = storage_study(args, ctx, net, d, ms, hh, kap, sig, g_side, b, mean_plain, E, n, m) \
         if args.storage_study else None
@@ -951,7 +962,8 @@ def learned_leg(args, ctx, el, d, ms, hh, kap, sig, g_side, b, i2o_plain, i2m_pl
                             "kernel": f"{mv_kernel} (element body shared with the GMRES product)",
                             "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS,
                             "traffic": recorded_traffic(args.op_dtype, mv_kernel),
-                            "bytes_per_launch": mv_bytes, "avg_launch_ms": mv_ms},
+                            "bytes_per_launch": mv_bytes, "avg_launch_ms": mv_ms,
+                            "stream_read_GBps": sr_gbs, "frac_of_stream_read": mv_gbs / sr_gbs},
     }
     net.close()
     return out

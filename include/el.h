@@ -425,6 +425,16 @@ el_status el_infer(el_ctx* ctx, const el_net* net, el_disc d, int64_t E, const d
                    const double* kappa, const double* sigma, void* in2out, void* in2vol, int out_dtype,
                    uint8_t* in_range, int fallback, int precision, int64_t* n_fallback_host);
 
+/* ---- measurement aid (not a step of the method) ------------------------------
+ * Reads bytes (a multiple of 16; buf 16-byte aligned, device) once with
+ * 16-byte loads and XORs every 32-bit word read into *sink (device; the
+ * caller sets its initial value), so that the reads cannot be removed: the
+ * streaming-read rate of this chip, to set beside the achieved bandwidth of
+ * the HBM-bound kernels (the skeleton product streams its operators).
+ * Stream-ordered, does not synchronize.  EL_ERR_ARG for a null pointer or a
+ * size or address not a multiple of 16; bytes = 0 does nothing. */
+el_status el_stream_read(el_ctx* ctx, const void* buf, size_t bytes, uint32_t* sink);
+
 /* ---- allocation-free inference ---------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  el_infer

@@ -133,6 +133,7 @@ _SIGS = {
     "el_infer": [ctypes.c_void_p, ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                  ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
+    "el_stream_read": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "el_infer_noalloc": [ctypes.c_void_p, ctypes.c_void_p, el_disc, ctypes.c_int64, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                          ctypes.c_void_p],
@@ -319,6 +320,15 @@ class Context:
         n_bnd = 2 * (ms.n_x + ms.n_y) * d.n_a * (d.p + 1)
         return self._check(lib().el_trace_rhs_nodal(self.h, d, ms, _ptr(g_bnd, torch.float64, n_bnd, "g_bnd"),
                                                     _ptr(b, torch.float64, nt, "b")))
+
+    def el_stream_read(self, buf, sink):
+        """Streaming-read reference: read every byte of the device tensor buf
+        once; sink: one-element int32 device tensor receiving the XOR of the
+        32-bit words read."""
+        if not buf.is_contiguous():
+            raise ValueError("buf must be contiguous")
+        return self._check(lib().el_stream_read(self.h, _ptr(buf, name="buf"), buf.numel() * buf.element_size(),
+                                                _ptr(sink, torch.int32, 1, "sink")))
 
     def el_trace_matvec(self, d, ms, in2out, x, y):
         nt = trace_size(d, ms)

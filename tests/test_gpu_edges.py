@@ -104,3 +104,23 @@ def test_smallest_meshes_plain_path(ctx, p, n_a, nx, ny, basis):
     assert np.abs(tg - tref).max() <= 1e-10 * np.abs(tref).max()
     mref = orecover.mean_intensity(od, orecover.recover(rs, ind, tref))
     assert np.abs(mean.cpu().numpy() - mref).max() <= 1e-10 * np.abs(mref).max()
+
+
+@pytest.mark.parametrize("words", [4, 4 * 12345, 4 * 1_000_003])
+def test_stream_read_reads_every_word(ctx, words):
+    """The streaming-read reference (el_stream_read) reads every 32-bit word
+    of its buffer exactly once: its XOR checksum equals the host's, for
+    sizes below one load per thread, ragged against the unrolled loop and
+    beyond one pass of the grid; sizes that are not whole 16-byte loads are
+    refused."""
+    from paper_2308_02467_amd import el
+    rng = np.random.default_rng(words)
+    host = rng.integers(0, 2 ** 31, words, dtype=np.int64).astype(np.int32)
+    buf = torch.from_numpy(host).to(DEV)
+    sink = torch.zeros(1, dtype=torch.int32, device=DEV)
+    print(f"[el_stream_read] {words} words", flush=True)
+    ctx.el_stream_read(buf, sink)
+    torch.cuda.synchronize()
+    assert int(sink.item()) == int(np.bitwise_xor.reduce(host))
+    st = el.lib().el_stream_read(ctx.h, buf.data_ptr(), 8, sink.data_ptr())
+    assert st == el.EL_ERR_ARG
