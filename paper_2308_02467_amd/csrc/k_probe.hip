@@ -20,9 +20,9 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // Each workgroup reads one contiguous 1 MiB chunk, kProbeUnroll
 // non-temporal 16-byte loads per thread in flight (the fastest of the
 // grid-stride and chunked forms with plain or non-temporal loads measured on
-// MI355X); the XOR of every 32-bit word read is folded per thread and
-// combined with one vector atomic per thread into *sink, which keeps the
-// loads from being removed.
+// MI355X); the XOR of every 32-bit word read is folded per thread, then
+// over the wave, and combined with one vector atomic per wave into *sink,
+// which keeps the loads from being removed.
 __global__ void __launch_bounds__(kProbeThreads) k_stream_read(const u32x4* __restrict__ p, int64_t n16,
                                                                  uint32_t* __restrict__ sink) {
   const int64_t b0 = (int64_t)blockIdx.x * kProbeChunk, b1 = min(n16, b0 + kProbeChunk);
@@ -39,7 +39,8 @@ __global__ void __launch_bounds__(kProbeThreads) k_stream_read(const u32x4* __re
     const u32x4 v = p[i];
     acc ^= v.x ^ v.y ^ v.z ^ v.w;
   }
-  atomicXor(sink, acc);
+  for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) atomicXor(sink, acc);
 }
 
 }  // namespace
